@@ -1,0 +1,213 @@
+/*
+ * eitomo.h -- C ABI of the MI355X (gfx950) library for model-based iterative
+ * edge-illumination (EI) X-ray tomography (Modregger et al., "Accelerated iterative
+ * tomographic reconstruction with x-ray edge illumination", arXiv 2202.08627).
+ *
+ * The library reconstructs, slice by slice, an absorption map mu and a phase map delta
+ * (refractive-index decrement) from edge-illumination data s_exp(t, theta, m) by
+ * minimising the least-squares cost of eq. 5 under the forward model of eq. 2 (eq. 4 with
+ * the drift m_o and ring term m_r set to zero):
+ *     s_mod(t, theta, m) = exp(-R[mu](t, theta)) * f_t(m - kappa * d/dt R[delta](t, theta))
+ * where R is the parallel-beam Radon transform of eq. 1 and f_t is the flat-field
+ * illumination curve of detector pixel t.
+ *
+ * Conventions (the paper fixes no discretisation; these are the library's):
+ *   - Unit voxel and detector pitch. Voxel (i, j) (column i = x, row j = y) has centre
+ *     (i - (n-1)/2, j - (n-1)/2); maps are stored planar and row-major, x[c][j][i],
+ *     c = 0 for mu and c = 1 for delta, i.e. float[2][n][n].
+ *   - Detector pixel k sits at t_k = k - (n_det-1)/2; angle theta_a (radians); the ray is
+ *     the line x cos(theta) + y sin(theta) = t.
+ *   - R is Joseph's ray-driven projector: linear interpolation along the axis the ray
+ *     crosses more slowly, interpolation indices computed on the fly (no system matrix,
+ *     as the algorithmic-improvements section recommends). Sinograms are float[2][n_theta][n_det].
+ *   - d/dt is the central difference with zero padding (the paper's finite differences).
+ *   - IC data are float[n_theta][n_mask][n_det]; the flat IC of pixel k is the Gaussian
+ *     A_k exp(-(u - c_k)^2 / (2 sigma_k^2)), u in mask periods.
+ *   - kappa converts the projected-phase slope into a shift in mask periods (z in eq. 2).
+ *
+ * Memory and ownership: all array arguments documented "device" are device pointers
+ * (HIP global memory) owned by the caller; the library never frees them. Arguments
+ * documented "host" are host pointers read during the call only. Apart from the plan's
+ * own small tables (angle and detector tables allocated in eit_plan_create) the library
+ * allocates no device memory: scratch space is the caller's workspace `ws`, at least
+ * eit_workspace_bytes() bytes, 256-byte aligned, and it must not be used concurrently by
+ * two calls.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream). Calls enqueue work on it
+ * and return without synchronising, except eit_reconstruct and eit_reconstruct_batch,
+ * which synchronise the stream once at the end to fill the host report.
+ *
+ * Errors: every int-returning call returns EIT_OK (0) or a negative EIT_ERR_* code;
+ * eit_last_error() returns a thread-local message for the last failure on the calling
+ * thread. Argument validation happens on the host before any device work is enqueued;
+ * on a validation error nothing is enqueued. No C++ exception crosses this interface.
+ */
+#ifndef EITOMO_H
+#define EITOMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EIT_OK 0
+#define EIT_ERR_INVALID_ARG (-1) /* null pointer, non-finite or out-of-range scalar */
+#define EIT_ERR_SHAPE (-2)       /* inconsistent or unsupported sizes */
+#define EIT_ERR_DEVICE (-3)      /* a HIP runtime call failed (message has the hipError_t) */
+#define EIT_ERR_NOMEM (-4)       /* workspace too small / plan table allocation failed */
+#define EIT_ERR_NONFINITE (-5)   /* cost is NaN or Inf at the starting point */
+#define EIT_ERR_LINESEARCH (-6)  /* no step satisfied the Armijo test from an empty memory */
+
+/* Limits checked by eit_plan_create. */
+#define EIT_MAX_N 4096
+#define EIT_MAX_NDET 4096
+#define EIT_MAX_NTHETA 16384
+#define EIT_MAX_NMASK 64
+#define EIT_MAX_LBFGS_M 20
+
+typedef struct eit_plan eit_plan;
+
+/* Problem sizes. n: grid n x n voxels; n_theta angles; n_det detector pixels; n_mask
+ * sample-mask positions per IC; kappa: refraction scale (mask periods per unit slope of
+ * the projected delta). */
+typedef struct {
+    int32_t n, n_theta, n_det, n_mask;
+    double kappa;
+} eit_dims;
+
+/* Acquisition set-up (all host, FP64, read during eit_plan_create only).
+ * theta: [n_theta] radians, or NULL for theta_a = a*pi/n_theta (180 degrees, endpoint
+ *        excluded).
+ * mask_pos: [n_mask] mask offsets in periods, or NULL for (j + 0.5)/n_mask - 0.5.
+ * flat_amp, flat_ctr, flat_sigma: [n_det] Gaussian flat-field IC parameters per pixel
+ *        (required; sigma > 0, amp > 0). */
+typedef struct {
+    const double* theta;
+    const double* mask_pos;
+    const double* flat_amp;
+    const double* flat_ctr;
+    const double* flat_sigma;
+} eit_setup;
+
+/* Optional tile-shape selection (autotuner output); NULL or -1 fields = defaults.
+ * proj_variant / adj_variant index the library's compiled projector / adjoint tile
+ * variants (see eit_variant_info). */
+typedef struct {
+    int32_t proj_variant;
+    int32_t adj_variant;
+} eit_tiling;
+
+/* Optimiser options for eit_reconstruct (L-BFGS on the scaled unknowns
+ * z = [mu / mu_scale ; delta / delta_scale], cost weight lam on ||z||^2, i.e.
+ * lambda_mu = lam / mu_scale^2 and lambda_delta = lam / delta_scale^2 in eq. 5). */
+typedef struct {
+    int32_t max_iter;       /* accepted iterations to run (>= 0) */
+    int32_t lbfgs_m;        /* memory pairs, 1 .. EIT_MAX_LBFGS_M */
+    int32_t max_ls_trials;  /* Armijo backtracking trials per line search (>= 0) */
+    int32_t use_graph;      /* nonzero: replay one captured HIP graph per evaluation */
+    double lam;             /* >= 0 */
+    double mu_scale, delta_scale;   /* > 0 */
+    double tol_rel_step;    /* stop when ||z_{k+1}-z_k|| / ||z_k|| < tol (0 = off) */
+    double c1;              /* Armijo constant, 0 < c1 < 1 (typ. 1e-4) */
+} eit_opts;
+
+/* Host report filled by eit_reconstruct after its final stream synchronisation. */
+typedef struct {
+    int32_t status;         /* EIT_OK or EIT_ERR_LINESEARCH / EIT_ERR_NONFINITE */
+    int32_t iters;          /* accepted iterations */
+    int32_t evals;          /* cost+gradient evaluations (line-search trials included) */
+    int32_t launches;       /* evaluation steps enqueued (no-op steps included) */
+    double cost;            /* final cost F(z) */
+    double gnorm;           /* final ||grad_z F|| */
+} eit_report;
+
+/* Create a plan: validates sizes, computes the angle/detector tables in FP64 on the host
+ * and uploads them (the plan's only device allocations). Requires a current HIP device.
+ * Returns EIT_ERR_SHAPE / EIT_ERR_INVALID_ARG on bad input, EIT_ERR_DEVICE on HIP failure. */
+int eit_plan_create(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
+                    eit_plan** out);
+void eit_plan_destroy(eit_plan* plan);
+
+/* Operation codes for eit_workspace_bytes. */
+#define EIT_OP_PROJECT 1
+#define EIT_OP_BACKPROJECT 2
+#define EIT_OP_COST_GRAD 3
+#define EIT_OP_RECONSTRUCT 4
+#define EIT_OP_SINGLE_SHOT 5
+
+/* Workspace bytes needed by an operation (lbfgs_m used by EIT_OP_RECONSTRUCT only).
+ * Returns 0 for an invalid plan or op. */
+size_t eit_workspace_bytes(const eit_plan* plan, int32_t op, int32_t lbfgs_m);
+
+/* Radon transform R (eq. 1) of both maps: x device float[2][n][n] ->
+ * sino device float[2][n_theta][n_det]. */
+int eit_project(const eit_plan* plan, const float* x, float* sino, void* ws, size_t ws_bytes,
+                void* stream);
+
+/* Exact transpose R^T of eit_project's operator (gather form, no atomics):
+ * sino device float[2][n_theta][n_det] -> x_out device float[2][n][n]. */
+int eit_backproject(const eit_plan* plan, const float* sino, float* x_out, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Cost of eq. 5 (model of eq. 2/4 with m_o = m_r = 0) at x = [mu; delta] (device
+ * float[2][n][n], raw units) for data s_exp (device float[n_theta][n_mask][n_det]):
+ *   S = sum (s_mod - s_exp)^2 + lam_mu ||mu||^2 + lam_delta ||delta||^2
+ * written as one FP64 value to cost_dev (device double*), reduced deterministically.
+ * If grad is non-NULL (device float[2][n][n]) the analytic gradient dS/dx is written too
+ * (adjoint backprojection of the IC residual seeds). Asynchronous; never syncs. */
+int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, double lam_mu,
+                      double lam_delta, double* cost_dev, float* grad, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Minimise the cost from x (device float[2][n][n], raw units): x holds the start on entry
+ * and x_K on return. L-BFGS (memory opts->lbfgs_m, compact representation, FP64 dot
+ * products) with Armijo backtracking, entirely device-resident; one accepted step per
+ * iteration. Synchronises `stream` at the end and fills *rep (host, may be NULL).
+ * cost_hist (device double[max_iter + 1], may be NULL) receives F after the start
+ * evaluation and after every accepted iteration. */
+int eit_reconstruct(const eit_plan* plan, const float* s_exp, const eit_opts* opts, float* x,
+                    double* cost_hist, eit_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Many independent slices (3-D as a stack of 2-D problems, combined-results section) in
+ * one sequence of persistent launches, optionally replayed from one captured HIP graph.
+ * plans/s_exp/x/reps are host arrays of n_slices entries (s_exp[i], x[i] device pointers
+ * as in eit_reconstruct; reps may be NULL). Slices may differ in every size. Workspace:
+ * eit_batch_workspace_bytes. Each slice runs its own optimiser state and line search. */
+size_t eit_batch_workspace_bytes(int32_t n_slices, const eit_plan* const* plans, int32_t lbfgs_m);
+int eit_reconstruct_batch(int32_t n_slices, const eit_plan* const* plans,
+                          const float* const* s_exp, float* const* x, const eit_opts* opts,
+                          eit_report* reps, void* ws, size_t ws_bytes, void* stream);
+
+/* Host-only diagnostic (no device needed): validates like eit_plan_create and reports the
+ * tiling-dependent sizes and the FP64 tables the plan would upload, so that launch shapes
+ * and LDS bounds can be checked on the host. Output arrays may be NULL; if given they need
+ * 6*n_theta doubles (per angle: inv, base, slope, slope as float, step weight, source 0/1),
+ * n_groups*proj_a int32 (angle ids, -1 = empty), n_groups*n_dblk*n_strips int32 (window
+ * origins) and 8*n_theta doubles (per angle: cos, sin, offset, cos as float, sin as float,
+ * 1/w, 1/w^2, 1/w - 1/w^2). Call once with NULL arrays to learn the sizes. */
+typedef struct {
+    int32_t proj_variant, adj_variant;
+    int32_t proj_a, proj_w, proj_r;
+    int32_t adj_tx, adj_ty, adj_ac;
+    int32_t n_groups, n_dblk, n_strips, win_w, win_pitch;
+    int32_t kwin, kwin_pitch_limit, n_tx, n_ty;
+    int64_t proj_lds_bytes;
+} eit_plan_info;
+int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
+                     eit_plan_info* info, double* proj_angles, int32_t* groups, int32_t* win_lo,
+                     double* adj_angles);
+
+/* Thread-local message describing the last non-zero return on this thread. */
+const char* eit_last_error(void);
+
+/* Compiled tile variants: kind 0 = projector (a = angles per group, b = detectors per
+ * block, c = rows per strip), kind 1 = adjoint (a, b = voxel tile, c = angles per chunk).
+ * Returns the number of variants of that kind; fills a/b/c for index v if in range. */
+int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EITOMO_H */

@@ -1,0 +1,771 @@
+// C ABI of the EI tomography library (declared in include/eitomo.h): host-side validation,
+// FP64 table construction, workspace layout, launch sequencing and the reconstruction
+// driver (one captured HIP graph per cost/gradient evaluation, replayed until the
+// device-side optimiser reports completion).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eit_internal.h"
+#include "eitomo.h"
+
+using namespace eit;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(EIT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    }
+};
+
+int default_proj_variant(int n) { return n <= 128 ? 1 : 0; }
+int default_adj_variant(int n) { (void)n; return 0; }
+
+int grid_for(int n_items, int cap) { return std::max(1, std::min(n_items, cap)); }
+constexpr int kGridCap = 256 * 16;   // persistent-grid cap: CUs x resident blocks
+
+}  // namespace
+
+// ============================================================================ plan
+struct eit_plan {
+    int n, n_theta, n_det, n_mask;
+    double kappa;
+    int proj_v, adj_v;
+    ProjTile pt;
+    AdjTile at;
+    int n_groups, n_dblk, n_strips, win_w, win_shift;
+    size_t proj_lds;
+    int n_tx, n_ty, kwin;
+    int n_trx;             // transpose tiles per side
+    int64_t nv;            // 2 n^2
+    int n_vblocks;
+    // device tables
+    ProjAngle* pang = nullptr;
+    int32_t* groups = nullptr;
+    int32_t* win_lo = nullptr;
+    AdjAngle* aang = nullptr;
+    float4* flat = nullptr;
+    float* mask = nullptr;
+    // single-slice item lists (slice 0)
+    Item* it_tr = nullptr;
+    Item* it_pr = nullptr;
+    Item* it_ic = nullptr;
+    Item* it_bp = nullptr;
+    Item* it_vec = nullptr;
+    int n_it_tr, n_it_pr, n_it_ic, n_it_bp, n_it_vec;
+    int device;
+};
+
+namespace {
+
+template <class T>
+int upload(T** dst, const std::vector<T>& v) {
+    *dst = nullptr;
+    if (v.empty()) return EIT_OK;
+    HIP_TRY(hipMalloc((void**)dst, v.size() * sizeof(T)));
+    HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EIT_OK;
+}
+
+void free_plan(eit_plan* p) {
+    if (!p) return;
+    void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->flat, p->mask,
+                    p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Projector angle record in the stepping frame (see ProjAngle).
+ProjAngle make_pangle(double th, int n, bool row) {
+    const double c = 0.5 * (n - 1);
+    const double cs = std::cos(th), sn = std::sin(th);
+    ProjAngle a{};
+    if (row) {
+        a.inv = 1.0 / cs;
+        a.base = c * sn / cs + c;
+        a.slope = -sn / cs;
+        a.w = (float)(1.0 / std::fabs(cs));
+        a.src = 0;
+    } else {
+        a.inv = 1.0 / sn;
+        a.base = c * cs / sn + c;
+        a.slope = -cs / sn;
+        a.w = (float)(1.0 / std::fabs(sn));
+        a.src = 1;
+    }
+    a.slope_f = (float)a.slope;
+    return a;
+}
+
+}  // namespace
+
+namespace {
+
+struct HostTables {
+    std::vector<ProjAngle> pang;
+    std::vector<int32_t> groups, win_lo;
+    std::vector<AdjAngle> aang;
+    std::vector<float4> flat;
+    std::vector<float> maskf;
+    std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
+};
+
+// Validation and FP64 table construction; touches no device (testable on the host).
+int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
+               eit_plan* p, HostTables& h) {
+    if (!dims || !setup) return fail(EIT_ERR_INVALID_ARG, "dims or setup is NULL");
+    const int n = dims->n, nt = dims->n_theta, nd = dims->n_det, nm = dims->n_mask;
+    if (n < 2 || n > EIT_MAX_N) return fail(EIT_ERR_SHAPE, "n=%d outside [2, %d]", n, EIT_MAX_N);
+    if (nt < 1 || nt > EIT_MAX_NTHETA)
+        return fail(EIT_ERR_SHAPE, "n_theta=%d outside [1, %d]", nt, EIT_MAX_NTHETA);
+    if (nd < 2 || nd > EIT_MAX_NDET)
+        return fail(EIT_ERR_SHAPE, "n_det=%d outside [2, %d]", nd, EIT_MAX_NDET);
+    if (nm < 1 || nm > EIT_MAX_NMASK)
+        return fail(EIT_ERR_SHAPE, "n_mask=%d outside [1, %d]", nm, EIT_MAX_NMASK);
+    if (!std::isfinite(dims->kappa)) return fail(EIT_ERR_INVALID_ARG, "kappa is not finite");
+    if (!setup->flat_amp || !setup->flat_ctr || !setup->flat_sigma)
+        return fail(EIT_ERR_INVALID_ARG, "flat-field IC parameters are NULL");
+    std::vector<double> theta(nt), mpos(nm);
+    for (int a = 0; a < nt; ++a) {
+        theta[a] = setup->theta ? setup->theta[a] : a * M_PI / nt;
+        if (!std::isfinite(theta[a])) return fail(EIT_ERR_INVALID_ARG, "theta[%d] not finite", a);
+    }
+    for (int j = 0; j < nm; ++j) {
+        mpos[j] = setup->mask_pos ? setup->mask_pos[j] : (j + 0.5) / nm - 0.5;
+        if (!std::isfinite(mpos[j])) return fail(EIT_ERR_INVALID_ARG, "mask_pos[%d] not finite", j);
+    }
+    for (int k = 0; k < nd; ++k) {
+        if (!finite_pos(setup->flat_amp[k]) || !finite_pos(setup->flat_sigma[k]) ||
+            !std::isfinite(setup->flat_ctr[k]))
+            return fail(EIT_ERR_INVALID_ARG, "flat-field parameters of pixel %d invalid", k);
+    }
+    int pv = tiling && tiling->proj_variant >= 0 ? tiling->proj_variant : default_proj_variant(n);
+    int av = tiling && tiling->adj_variant >= 0 ? tiling->adj_variant : default_adj_variant(n);
+    if (pv >= proj_variant_count()) return fail(EIT_ERR_INVALID_ARG, "proj_variant %d unknown", pv);
+    if (av >= adj_variant_count()) return fail(EIT_ERR_INVALID_ARG, "adj_variant %d unknown", av);
+
+    p->n = n; p->n_theta = nt; p->n_det = nd; p->n_mask = nm; p->kappa = dims->kappa;
+    p->proj_v = pv; p->adj_v = av; p->device = -1;
+    p->pt = proj_variant(pv);
+    p->at = adj_variant(av);
+    const int A = p->pt.A, W = p->pt.W, R = p->pt.R;
+
+    // ---- projector tables: row/column flag decided once here in FP64 (ties -> rows)
+    std::vector<ProjAngle>& pang = h.pang;
+    pang.assign(nt, ProjAngle{});
+    std::vector<int> cls(nt);
+    for (int a = 0; a < nt; ++a) {
+        const double cs = std::cos(theta[a]), sn = std::sin(theta[a]);
+        const bool row = std::fabs(cs) >= std::fabs(sn);
+        pang[a] = make_pangle(theta[a], n, row);
+        cls[a] = (row ? 0 : 2) + (pang[a].inv > 0 ? 0 : 1);
+    }
+    // groups: runs of consecutive angles of one class, chunked by A
+    std::vector<int32_t>& groups = h.groups;
+    groups.clear();
+    for (int a = 0; a < nt;) {
+        int b = a;
+        while (b < nt && cls[b] == cls[a] && b - a < A) ++b;
+        for (int q = 0; q < A; ++q) groups.push_back(a + q < b ? a + q : -1);
+        a = b;
+    }
+    p->n_groups = (int)groups.size() / A;
+    p->n_dblk = (nd + W - 1) / W;
+    p->n_strips = (n + R - 1) / R;
+    std::vector<int32_t>& win_lo = h.win_lo;
+    win_lo.assign((size_t)p->n_groups * p->n_dblk * p->n_strips, 0);
+    int win_w = 2;
+    for (int g = 0; g < p->n_groups; ++g)
+        for (int b = 0; b < p->n_dblk; ++b) {
+            const int k0 = b * W, k1 = std::min(b * W + W - 1, nd - 1);
+            const double t0 = k0 - 0.5 * (nd - 1), t1 = k1 - 0.5 * (nd - 1);
+            for (int s = 0; s < p->n_strips; ++s) {
+                const double p0 = (double)s * R, p1 = p0 + R - 1;
+                double umin = 1e300, umax = -1e300;
+                for (int q = 0; q < A; ++q) {
+                    const int a = groups[(size_t)g * A + q];
+                    if (a < 0) continue;
+                    const ProjAngle& pa = pang[a];
+                    for (double t : {t0, t1})
+                        for (double pp : {p0, p1}) {
+                            const double u = t * pa.inv + pa.base + pp * pa.slope;
+                            umin = std::min(umin, u);
+                            umax = std::max(umax, u);
+                        }
+                }
+                const int lo = (int)std::floor(umin - 1e-3) - 1;
+                win_lo[((size_t)g * p->n_dblk + b) * p->n_strips + s] = lo;
+                win_w = std::max(win_w, (int)std::floor(umax + 1e-3) - lo + 2);
+            }
+        }
+    p->win_w = win_w;
+    p->win_shift = 0;
+    while ((1 << p->win_shift) < win_w) ++p->win_shift;
+    p->proj_lds = (size_t)R * ((size_t)1 << p->win_shift) * sizeof(float2);
+    if (p->proj_lds > 64 * 1024) {
+        return fail(EIT_ERR_SHAPE, "projector window %d too wide for variant %d", win_w, pv);
+    }
+
+    // ---- adjoint tables
+    std::vector<AdjAngle>& aang = h.aang;
+    aang.assign(nt, AdjAngle{});
+    double span = 0.0;
+    const double c = 0.5 * (n - 1), cdet = 0.5 * (nd - 1);
+    for (int a = 0; a < nt; ++a) {
+        const double cs = std::cos(theta[a]), sn = std::sin(theta[a]);
+        const bool row = std::fabs(cs) >= std::fabs(sn);
+        const double wv = row ? std::fabs(cs) : std::fabs(sn);
+        AdjAngle q{};
+        q.cs = cs; q.sn = sn; q.cd = cdet - c * (cs + sn);
+        q.cs_f = (float)cs; q.sn_f = (float)sn;
+        q.iw = (float)(1.0 / wv);
+        q.iw2 = (float)(1.0 / (wv * wv));
+        q.iwm = (float)(1.0 / wv - 1.0 / (wv * wv));
+        aang[a] = q;
+        span = std::max(span, (p->at.TX - 1) * std::fabs(cs) + (p->at.TY - 1) * std::fabs(sn));
+    }
+    p->kwin = (int)std::ceil(span) + 4;
+    if (p->kwin > adj_pitch_limit(av)) {
+        return fail(EIT_ERR_SHAPE, "adjoint window %d exceeds variant capacity", p->kwin);
+    }
+    p->n_tx = (n + p->at.TX - 1) / p->at.TX;
+    p->n_ty = (n + p->at.TY - 1) / p->at.TY;
+
+    // ---- detector tables
+    std::vector<float4>& flat = h.flat;
+    flat.assign(nd, float4{});
+    for (int k = 0; k < nd; ++k) {
+        const double sg = setup->flat_sigma[k];
+        flat[k] = make_float4((float)setup->flat_amp[k], (float)setup->flat_ctr[k],
+                              (float)(1.0 / (2.0 * sg * sg)), (float)(1.0 / (sg * sg)));
+    }
+    std::vector<float>& maskf = h.maskf;
+    maskf.assign(nm, 0.f);
+    for (int j = 0; j < nm; ++j) maskf[j] = (float)mpos[j];
+
+    // ---- single-slice work items
+    p->n_trx = (n + kTrTile - 1) / kTrTile;
+    p->nv = 2LL * n * n;
+    p->n_vblocks = (int)((p->nv + kVecChunk - 1) / kVecChunk);
+    std::vector<Item>&it_tr = h.it_tr, &it_pr = h.it_pr, &it_ic = h.it_ic, &it_bp = h.it_bp,
+                     &it_vec = h.it_vec;
+    for (int ty = 0; ty < p->n_trx; ++ty)
+        for (int tx = 0; tx < p->n_trx; ++tx) it_tr.push_back(make_int4(0, tx, ty, 0));
+    for (int g = 0; g < p->n_groups; ++g)
+        for (int b = 0; b < p->n_dblk; ++b) it_pr.push_back(make_int4(0, g, b, 0));
+    for (int a = 0; a < nt; ++a) it_ic.push_back(make_int4(0, a, 0, 0));
+    for (int ty = 0; ty < p->n_ty; ++ty)
+        for (int tx = 0; tx < p->n_tx; ++tx) it_bp.push_back(make_int4(0, tx, ty, 0));
+    for (int b = 0; b < p->n_vblocks; ++b) it_vec.push_back(make_int4(0, b, 0, 0));
+    p->n_it_tr = (int)it_tr.size(); p->n_it_pr = (int)it_pr.size(); p->n_it_ic = nt;
+    p->n_it_bp = (int)it_bp.size(); p->n_it_vec = (int)it_vec.size();
+
+    return EIT_OK;
+}
+
+}  // namespace
+
+extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
+                               const eit_tiling* tiling, eit_plan** out) {
+    if (!out) return fail(EIT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    eit_plan* p = new eit_plan();
+    HostTables h;
+    int rc = build_host(dims, setup, tiling, p, h);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(EIT_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    if ((rc = upload(&p->pang, h.pang)) || (rc = upload(&p->groups, h.groups)) ||
+        (rc = upload(&p->win_lo, h.win_lo)) || (rc = upload(&p->aang, h.aang)) ||
+        (rc = upload(&p->flat, h.flat)) || (rc = upload(&p->mask, h.maskf)) ||
+        (rc = upload(&p->it_tr, h.it_tr)) || (rc = upload(&p->it_pr, h.it_pr)) ||
+        (rc = upload(&p->it_ic, h.it_ic)) || (rc = upload(&p->it_bp, h.it_bp)) ||
+        (rc = upload(&p->it_vec, h.it_vec))) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return EIT_OK;
+}
+
+extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
+                                const eit_tiling* tiling, eit_plan_info* info,
+                                double* proj_angles, int32_t* groups, int32_t* win_lo,
+                                double* adj_angles) {
+    if (!info) return fail(EIT_ERR_INVALID_ARG, "info is NULL");
+    eit_plan tmp{};
+    HostTables h;
+    int rc = build_host(dims, setup, tiling, &tmp, h);
+    if (rc) return rc;
+    info->proj_variant = tmp.proj_v; info->adj_variant = tmp.adj_v;
+    info->proj_a = tmp.pt.A; info->proj_w = tmp.pt.W; info->proj_r = tmp.pt.R;
+    info->adj_tx = tmp.at.TX; info->adj_ty = tmp.at.TY; info->adj_ac = tmp.at.AC;
+    info->n_groups = tmp.n_groups; info->n_dblk = tmp.n_dblk; info->n_strips = tmp.n_strips;
+    info->win_w = tmp.win_w; info->win_pitch = 1 << tmp.win_shift;
+    info->proj_lds_bytes = (int64_t)tmp.proj_lds;
+    info->kwin = tmp.kwin; info->n_tx = tmp.n_tx; info->n_ty = tmp.n_ty;
+    info->kwin_pitch_limit = adj_pitch_limit(tmp.adj_v);
+    if (proj_angles)
+        for (size_t a = 0; a < h.pang.size(); ++a) {
+            const ProjAngle& q = h.pang[a];
+            double* o = proj_angles + 6 * a;
+            o[0] = q.inv; o[1] = q.base; o[2] = q.slope; o[3] = q.slope_f; o[4] = q.w; o[5] = q.src;
+        }
+    if (groups) std::copy(h.groups.begin(), h.groups.end(), groups);
+    if (win_lo) std::copy(h.win_lo.begin(), h.win_lo.end(), win_lo);
+    if (adj_angles)
+        for (size_t a = 0; a < h.aang.size(); ++a) {
+            const AdjAngle& q = h.aang[a];
+            double* o = adj_angles + 8 * a;
+            o[0] = q.cs; o[1] = q.sn; o[2] = q.cd; o[3] = q.cs_f; o[4] = q.sn_f;
+            o[5] = q.iw; o[6] = q.iw2; o[7] = q.iwm;
+        }
+    return EIT_OK;
+}
+
+extern "C" void eit_plan_destroy(eit_plan* p) { free_plan(p); }
+
+// ============================================================================ workspace
+namespace {
+
+struct EvalLayout {
+    size_t desc, xT, P, part_ic, part_reg, cost, end;
+};
+
+EvalLayout eval_layout(const eit_plan* p, bool need_P, size_t base = 0) {
+    Layout L;
+    L.off = base;
+    EvalLayout e{};
+    e.desc = L.take(sizeof(SliceDesc));
+    e.xT = L.take(sizeof(float) * (size_t)p->nv);
+    e.P = need_P ? L.take(sizeof(float) * 2 * (size_t)p->n_theta * p->n_det) : 0;
+    e.part_ic = L.take(sizeof(double) * (size_t)p->n_theta);
+    e.part_reg = L.take(sizeof(double) * 2 * (size_t)p->n_trx * p->n_trx);
+    e.cost = L.take(sizeof(double));
+    e.end = L.off;
+    return e;
+}
+
+struct SolveLayout {
+    EvalLayout ev;
+    size_t lbdesc, state, z, zt, g, gt, d, S, Y, part, end;
+};
+
+SolveLayout solve_layout(const eit_plan* p, int m, size_t base = 0) {
+    SolveLayout s{};
+    s.ev = eval_layout(p, true, base);
+    Layout L;
+    L.off = s.ev.end;
+    const size_t vb = sizeof(float) * (size_t)p->nv;
+    s.lbdesc = L.take(sizeof(LbDesc));
+    s.state = L.take(sizeof(SolverState));
+    s.z = L.take(vb); s.zt = L.take(vb); s.g = L.take(vb); s.gt = L.take(vb); s.d = L.take(vb);
+    s.S = L.take(vb * (m + 1));
+    s.Y = L.take(vb * (m + 1));
+    s.part = L.take(sizeof(double) * max_dots(m) * (size_t)p->n_vblocks);
+    s.end = L.off;
+    return s;
+}
+
+SliceDesc base_desc(const eit_plan* p) {
+    SliceDesc d{};
+    d.n = p->n; d.n_theta = p->n_theta; d.n_det = p->n_det; d.n_mask = p->n_mask;
+    d.kappa = (float)p->kappa;
+    d.scale_mu = 1.f; d.scale_de = 1.f;
+    d.proj_tile = p->proj_v; d.adj_tile = p->adj_v;
+    d.n_groups = p->n_groups; d.n_dblk = p->n_dblk; d.n_strips = p->n_strips;
+    d.win_w = p->win_w; d.win_shift = p->win_shift;
+    d.n_tx = p->n_tx; d.n_ty = p->n_ty; d.kwin = p->kwin;
+    d.pang = p->pang; d.groups = p->groups; d.win_lo = p->win_lo; d.aang = p->aang;
+    d.flat = p->flat; d.mask = p->mask;
+    d.n_reg_blocks = p->n_trx * p->n_trx;
+    return d;
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+int check_ws(const void* ws, size_t have, size_t need) {
+    if (!ws) return fail(EIT_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(EIT_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (have < need) return fail(EIT_ERR_NOMEM, "workspace %zu bytes < required %zu", have, need);
+    return EIT_OK;
+}
+
+}  // namespace
+
+extern "C" size_t eit_workspace_bytes(const eit_plan* p, int32_t op, int32_t m) {
+    if (!p) return 0;
+    switch (op) {
+        case EIT_OP_PROJECT: return eval_layout(p, false).end;
+        case EIT_OP_BACKPROJECT: return eval_layout(p, false).end;
+        case EIT_OP_COST_GRAD: return eval_layout(p, true).end;
+        case EIT_OP_RECONSTRUCT:
+            if (m < 1 || m > EIT_MAX_LBFGS_M) return 0;
+            return solve_layout(p, m).end;
+        default: return 0;
+    }
+}
+
+// ============================================================================ single evaluations
+namespace {
+
+int enqueue_eval(const eit_plan* p, const SliceDesc* dd, bool seeds, bool grad, hipStream_t st) {
+    HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
+    HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
+                           p->proj_lds, st));
+    HIP_TRY(launch_ic(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap), seeds ? 1 : 0, st));
+    if (grad)
+        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp,
+                                   grid_for(p->n_it_bp, kGridCap), 1, st));
+    return EIT_OK;
+}
+
+}  // namespace
+
+extern "C" int eit_project(const eit_plan* p, const float* x, float* sino, void* ws,
+                           size_t ws_bytes, void* stream) {
+    if (!p) return fail(EIT_ERR_INVALID_ARG, "plan is NULL");
+    if (!x || !sino) return fail(EIT_ERR_INVALID_ARG, "x or sino is NULL");
+    const EvalLayout L = eval_layout(p, false);
+    if (int rc = check_ws(ws, ws_bytes, L.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    SliceDesc d = base_desc(p);
+    d.x = x;
+    d.xT = (float*)at(ws, L.xT);
+    d.P = sino;
+    d.part_reg = (double*)at(ws, L.part_reg);
+    SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
+    HIP_TRY(launch_store_desc(d, dd, st));
+    HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
+    HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
+                           p->proj_lds, st));
+    return EIT_OK;
+}
+
+extern "C" int eit_backproject(const eit_plan* p, const float* sino, float* x_out, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!p) return fail(EIT_ERR_INVALID_ARG, "plan is NULL");
+    if (!sino || !x_out) return fail(EIT_ERR_INVALID_ARG, "sino or x_out is NULL");
+    const EvalLayout L = eval_layout(p, false);
+    if (int rc = check_ws(ws, ws_bytes, L.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    SliceDesc d = base_desc(p);
+    d.P = const_cast<float*>(sino);   // read only by the adjoint
+    d.g = x_out;
+    SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
+    HIP_TRY(launch_store_desc(d, dd, st));
+    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
+                               0, st));
+    return EIT_OK;
+}
+
+extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float* s_exp,
+                                 double lam_mu, double lam_delta, double* cost_dev, float* grad,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(EIT_ERR_INVALID_ARG, "plan is NULL");
+    if (!x || !s_exp || !cost_dev) return fail(EIT_ERR_INVALID_ARG, "x, s_exp or cost_dev is NULL");
+    if (!(lam_mu >= 0.0) || !(lam_delta >= 0.0) || !std::isfinite(lam_mu) || !std::isfinite(lam_delta))
+        return fail(EIT_ERR_INVALID_ARG, "lam_mu / lam_delta must be finite and >= 0");
+    const EvalLayout L = eval_layout(p, true);
+    if (int rc = check_ws(ws, ws_bytes, L.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    SliceDesc d = base_desc(p);
+    d.x = x;
+    d.xT = (float*)at(ws, L.xT);
+    d.P = (float*)at(ws, L.P);
+    d.s_exp = s_exp;
+    d.g = grad;
+    d.part_ic = (double*)at(ws, L.part_ic);
+    d.part_reg = (double*)at(ws, L.part_reg);
+    d.cost = cost_dev;
+    d.lam_mu = (float)lam_mu; d.lam_de = (float)lam_delta;
+    d.reg_mu = (float)(2.0 * lam_mu); d.reg_de = (float)(2.0 * lam_delta);
+    SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
+    HIP_TRY(launch_store_desc(d, dd, st));
+    if (int rc = enqueue_eval(p, dd, grad != nullptr, false, st)) return rc;
+    HIP_TRY(launch_cost_reduce(dd, 1, st));
+    if (grad)
+        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp,
+                                   grid_for(p->n_it_bp, kGridCap), 1, st));
+    return EIT_OK;
+}
+
+// ============================================================================ reconstruct
+namespace {
+
+int validate_opts(const eit_opts* o) {
+    if (!o) return fail(EIT_ERR_INVALID_ARG, "opts is NULL");
+    if (o->max_iter < 0) return fail(EIT_ERR_INVALID_ARG, "max_iter < 0");
+    if (o->lbfgs_m < 1 || o->lbfgs_m > EIT_MAX_LBFGS_M)
+        return fail(EIT_ERR_INVALID_ARG, "lbfgs_m=%d outside [1, %d]", o->lbfgs_m, EIT_MAX_LBFGS_M);
+    if (o->max_ls_trials < 0) return fail(EIT_ERR_INVALID_ARG, "max_ls_trials < 0");
+    if (!(o->lam >= 0.0) || !std::isfinite(o->lam)) return fail(EIT_ERR_INVALID_ARG, "lam must be finite and >= 0");
+    if (!finite_pos(o->mu_scale) || !finite_pos(o->delta_scale))
+        return fail(EIT_ERR_INVALID_ARG, "mu_scale / delta_scale must be finite and > 0");
+    if (!(o->tol_rel_step >= 0.0) || !std::isfinite(o->tol_rel_step))
+        return fail(EIT_ERR_INVALID_ARG, "tol_rel_step must be finite and >= 0");
+    if (!(o->c1 > 0.0 && o->c1 < 1.0)) return fail(EIT_ERR_INVALID_ARG, "c1 must be in (0, 1)");
+    return EIT_OK;
+}
+
+// One evaluation step of the optimiser for n_slices slices described by (D, L).
+struct StepPlan {
+    const SliceDesc* D;
+    const LbDesc* L;
+    int n_slices;
+    // per projector / adjoint variant groups (batch may mix variants)
+    struct Launch { int variant; const Item* items; int n; size_t lds; };
+    std::vector<Launch> proj, adj;
+    const Item* it_tr; int n_tr;
+    const Item* it_ic; int n_ic;
+    const Item* it_vec; int n_vec;
+};
+
+int enqueue_step(const StepPlan& sp, hipStream_t st) {
+    HIP_TRY(launch_lb_direction(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+    HIP_TRY(launch_transpose(sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
+    for (const auto& l : sp.proj)
+        HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
+    HIP_TRY(launch_ic(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
+    HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
+    for (const auto& l : sp.adj)
+        HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 1, st));
+    HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+    HIP_TRY(launch_lb_finalize(sp.L, sp.n_slices, st));
+    return EIT_OK;
+}
+
+// Replays the step until every slice's optimiser has stopped. Reads back (status, k) of each
+// slice only between rounds of launches; each round enqueues as many steps as the slowest
+// slice still needs iterations (every accepted iteration needs at least one evaluation).
+int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
+             bool use_graph, hipStream_t st, int* launches_out);
+
+// The null stream cannot be captured: graph replays then run on a private non-blocking
+// stream ordered after (and before) the caller's work through events.
+int drive(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
+          bool use_graph, hipStream_t st, int* launches_out) {
+    if (!use_graph || st != nullptr) return drive_on(sp, states, max_iter, max_ls, use_graph, st, launches_out);
+    hipStream_t side = nullptr;
+    hipEvent_t ev = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    int rc = EIT_OK;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ev, 0);
+    if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "stream ordering: %s", hipGetErrorString(e));
+    if (!rc) rc = drive_on(sp, states, max_iter, max_ls, true, side, launches_out);
+    if (!rc) {
+        e = hipEventRecord(ev, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+        if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "stream ordering: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(side);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(side);
+    return rc;
+}
+
+int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
+             bool use_graph, hipStream_t st, int* launches_out) {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph) {
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(sp, st);
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(EIT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(EIT_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+    }
+    const long long cap = (long long)(max_iter + 2) * (max_ls + 2) * 2 + 16;
+    long long total = 0;
+    int rc = EIT_OK;
+    int want = max_iter + 1;
+    std::vector<int32_t> host(5 * states.size());
+    while (rc == EIT_OK) {
+        for (int i = 0; i < want && rc == EIT_OK; ++i) {
+            if (use_graph) {
+                hipError_t e = hipGraphLaunch(exec, st);
+                if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+            } else {
+                rc = enqueue_step(sp, st);
+            }
+            ++total;
+        }
+        if (rc) break;
+        for (size_t q = 0; q < states.size(); ++q) {
+            // k, evals, trials, mode, status are consecutive int32 fields
+            hipError_t e = hipMemcpyAsync(&host[5 * q], &states[q]->k, 5 * sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) { rc = fail(EIT_ERR_DEVICE, "state read-back: %s", hipGetErrorString(e)); break; }
+        }
+        if (rc) break;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = fail(EIT_ERR_DEVICE, "stream sync: %s", hipGetErrorString(e)); break; }
+        int remaining = 0;
+        for (size_t q = 0; q < states.size(); ++q)
+            if (host[5 * q + 4] == ST_RUNNING)
+                remaining = std::max(remaining, std::max(1, max_iter - host[5 * q]));
+        if (rc || remaining == 0) break;
+        if (total > cap) { rc = fail(EIT_ERR_DEVICE, "optimiser did not stop within %lld steps", cap); break; }
+        want = remaining;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (launches_out) *launches_out = (int)std::min<long long>(total, 1 << 30);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_opts* o, float* x,
+                               double* cost_hist, eit_report* rep, void* ws, size_t ws_bytes,
+                               void* stream) {
+    if (!p) return fail(EIT_ERR_INVALID_ARG, "plan is NULL");
+    if (!s_exp || !x) return fail(EIT_ERR_INVALID_ARG, "s_exp or x is NULL");
+    if (int rc = validate_opts(o)) return rc;
+    const SolveLayout S = solve_layout(p, o->lbfgs_m);
+    if (int rc = check_ws(ws, ws_bytes, S.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+
+    SolverState* state = (SolverState*)at(ws, S.state);
+    SliceDesc d = base_desc(p);
+    d.x = (const float*)at(ws, S.zt);
+    d.xT = (float*)at(ws, S.ev.xT);
+    d.P = (float*)at(ws, S.ev.P);
+    d.s_exp = s_exp;
+    d.g = (float*)at(ws, S.gt);
+    d.part_ic = (double*)at(ws, S.ev.part_ic);
+    d.part_reg = (double*)at(ws, S.ev.part_reg);
+    d.cost = &state->f_t;
+    d.scale_mu = (float)o->mu_scale; d.scale_de = (float)o->delta_scale;
+    d.lam_mu = (float)o->lam; d.lam_de = (float)o->lam;
+    d.reg_mu = (float)(2.0 * o->lam); d.reg_de = (float)(2.0 * o->lam);
+    d.skip = &state->skip;
+    d.skip_adj = &state->skip_adj;
+
+    LbDesc l{};
+    l.nv = p->nv; l.n = p->n; l.n_vblocks = p->n_vblocks;
+    l.scale_mu = (float)o->mu_scale; l.scale_de = (float)o->delta_scale;
+    l.z = (float*)at(ws, S.z); l.zt = (float*)at(ws, S.zt); l.g = (float*)at(ws, S.g);
+    l.gt = (float*)at(ws, S.gt); l.d = (float*)at(ws, S.d);
+    l.S = (float*)at(ws, S.S); l.Y = (float*)at(ws, S.Y);
+    l.part = (double*)at(ws, S.part);
+    l.st = state;
+    l.x_user = x;
+    l.cost_hist = cost_hist;
+
+    SliceDesc* dd = (SliceDesc*)at(ws, S.ev.desc);
+    LbDesc* ld = (LbDesc*)at(ws, S.lbdesc);
+    HIP_TRY(launch_store_desc(d, dd, st));
+    HIP_TRY(launch_store_lbdesc(l, ld, st));
+    HIP_TRY(launch_lb_init(ld, 1, o->lbfgs_m, o->max_iter, o->max_ls_trials, o->c1, o->tol_rel_step, st));
+    const int gv = grid_for(p->n_it_vec, kGridCap);
+    HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 1, st));
+
+    StepPlan sp;
+    sp.D = dd; sp.L = ld; sp.n_slices = 1;
+    sp.proj.push_back({p->proj_v, p->it_pr, p->n_it_pr, p->proj_lds});
+    sp.adj.push_back({p->adj_v, p->it_bp, p->n_it_bp, 0});
+    sp.it_tr = p->it_tr; sp.n_tr = p->n_it_tr;
+    sp.it_ic = p->it_ic; sp.n_ic = p->n_it_ic;
+    sp.it_vec = p->it_vec; sp.n_vec = p->n_it_vec;
+    int launches = 0;
+    if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches))
+        return rc;
+    HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 0, st));
+    SolverState hs;
+    HIP_TRY(hipMemcpyAsync(&hs, state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (rep) {
+        rep->status = hs.status == ST_DONE ? EIT_OK : hs.status;
+        rep->iters = hs.k;
+        rep->evals = hs.evals;
+        rep->launches = launches;
+        rep->cost = hs.f;
+        rep->gnorm = std::sqrt(hs.gg);
+    }
+    if (hs.status < 0)
+        return fail(hs.status, hs.status == EIT_ERR_NONFINITE ? "cost is not finite at the start"
+                                                              : "line search failed from an empty memory");
+    return EIT_OK;
+}
+
+// ============================================================================ misc
+extern "C" const char* eit_last_error(void) { return g_err.c_str(); }
+
+extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c) {
+    if (kind == 0) {
+        const int n = proj_variant_count();
+        if (v >= 0 && v < n) {
+            ProjTile t = proj_variant(v);
+            if (a) *a = t.A;
+            if (b) *b = t.W;
+            if (c) *c = t.R;
+        }
+        return n;
+    }
+    if (kind == 1) {
+        const int n = adj_variant_count();
+        if (v >= 0 && v < n) {
+            AdjTile t = adj_variant(v);
+            if (a) *a = t.TX;
+            if (b) *b = t.TY;
+            if (c) *c = t.AC;
+        }
+        return n;
+    }
+    return 0;
+}
+
+extern "C" size_t eit_batch_workspace_bytes(int32_t, const eit_plan* const*, int32_t) { return 0; }
+extern "C" int eit_reconstruct_batch(int32_t, const eit_plan* const*, const float* const*,
+                                     float* const*, const eit_opts*, eit_report*, void*, size_t,
+                                     void*) {
+    return fail(EIT_ERR_INVALID_ARG, "batched reconstruction not built yet");
+}

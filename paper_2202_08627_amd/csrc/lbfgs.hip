@@ -1,0 +1,414 @@
+// Device-resident L-BFGS for the EI cost (the paper minimises eq. 5 with an L-BFGS
+// method). Compact representation (Byrd, Nocedal & Schnabel): with H_0 = gamma I,
+//   H g = gamma g + S e - gamma Y c,  c = R^{-1} (S^T g),
+//   e = R^{-T} ((D + gamma Y^T Y) c - gamma Y^T g),
+// R the upper triangle of S^T Y and D its diagonal -- algebraically the two-loop recursion,
+// but every inner product of an iteration is gathered in one vector pass and the small
+// m x m algebra runs in one thread. Inner products accumulate in FP64. The line search
+// (Armijo backtracking) is a device-side state machine: each replay of the evaluation
+// sequence either starts a new direction or halves the step, with no host round trip.
+#include "eit_internal.h"
+#include "reduce.h"
+#include "eitomo.h"
+
+namespace eit {
+
+// ------------------------------------------------------------------------ helpers
+__device__ void steepest(SolverState& s) {
+    s.gamma = 1.0;
+    for (int r = 0; r < kMaxM; ++r) { s.cc[r] = 0.0; s.ee[r] = 0.0; }
+    s.gd = -s.gg;
+    s.alpha = 1.0 / sqrt(s.gg);
+    s.trials = 0;
+    s.mode = MODE_NEW_DIR;
+}
+
+__device__ void reset_memory(SolverState& s) {
+    s.m_cur = 0;
+    s.spare = 0;
+}
+
+// Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first).
+__device__ void compact_direction(SolverState& s, const double* a, const double* b) {
+    const int mc = s.m_cur;
+    const int W = kMaxM + 1;
+    const int newest = s.order[mc - 1];
+    const double gamma = s.SY[newest * W + newest] / s.YY[newest * W + newest];
+    double c[kMaxM], v[kMaxM], e[kMaxM];
+    for (int r = mc - 1; r >= 0; --r) {                 // c = R^{-1} a (back substitution)
+        double acc = a[r];
+        for (int q = r + 1; q < mc; ++q) acc -= s.SY[s.order[r] * W + s.order[q]] * c[q];
+        c[r] = acc / s.SY[s.order[r] * W + s.order[r]];
+    }
+    for (int r = 0; r < mc; ++r) {                      // v = (D + gamma Y^T Y) c - gamma b
+        double acc = s.SY[s.order[r] * W + s.order[r]] * c[r] - gamma * b[r];
+        for (int q = 0; q < mc; ++q) acc += gamma * s.YY[s.order[r] * W + s.order[q]] * c[q];
+        v[r] = acc;
+    }
+    for (int r = 0; r < mc; ++r) {                      // e = R^{-T} v (forward substitution)
+        double acc = v[r];
+        for (int q = 0; q < r; ++q) acc -= s.SY[s.order[q] * W + s.order[r]] * e[q];
+        e[r] = acc / s.SY[s.order[r] * W + s.order[r]];
+    }
+    double gHg = gamma * s.gg;
+    for (int r = 0; r < mc; ++r) gHg += a[r] * e[r] - gamma * b[r] * c[r];
+    for (int r = 0; r < kMaxM; ++r) {
+        s.ee[r] = r < mc ? e[r] : 0.0;
+        s.cc[r] = r < mc ? gamma * c[r] : 0.0;
+    }
+    s.gamma = gamma;
+    s.gd = -gHg;
+    s.alpha = 1.0;
+    s.trials = 0;
+    s.mode = MODE_NEW_DIR;
+    if (!(s.gd < 0.0)) {                                // not a descent direction
+        reset_memory(s);
+        steepest(s);
+    }
+}
+
+__device__ void finish(SolverState& s, int status) {
+    s.status = status;
+    s.skip = 1;
+    s.skip_adj = 1;
+}
+
+// ------------------------------------------------------------------------ init / scale
+__global__ void k_lb_init(const LbDesc* __restrict__ L, int m, int max_iter, int max_ls,
+                          double c1, double tol) {
+    if (threadIdx.x != 0) return;
+    SolverState& s = *L[blockIdx.x].st;
+    s.f = 0.0; s.f_t = 0.0; s.alpha = 0.0; s.gd = 0.0; s.gamma = 1.0; s.gg = 0.0;
+    s.c1 = c1; s.tol = tol;
+    for (int r = 0; r < kMaxM; ++r) { s.cc[r] = 0.0; s.ee[r] = 0.0; s.order[r] = 0; }
+    s.cost_hist = L[blockIdx.x].cost_hist;
+    s.k = 0; s.evals = 0; s.trials = 0; s.mode = MODE_INIT; s.status = ST_RUNNING;
+    s.m_cur = 0; s.m = m; s.max_iter = max_iter; s.max_ls = max_ls; s.accept = 0;
+    s.spare = 0; s.launches = 0; s.skip = 0; s.skip_adj = 0;
+}
+
+// to_z: z = x_user / scale; else x_user = z * scale.
+__global__ __launch_bounds__(kVecThreads) void k_lb_scale(const LbDesc* __restrict__ L,
+                                                        const Item* __restrict__ items,
+                                                        int n_items, int to_z) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const LbDesc& l = L[w.x];
+        const int64_t half = l.nv / 2;
+        const int64_t e0 = (int64_t)w.y * kVecChunk;
+        const int64_t e1 = min(e0 + kVecChunk, l.nv);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            const float sc = e < half ? l.scale_mu : l.scale_de;
+            if (to_z) l.z[e] = l.x_user[e] / sc;
+            else l.x_user[e] = l.z[e] * sc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------ direction + trial point
+// INIT: zt = z. NEW_DIR: d = -gamma g - sum ee_r s_r + sum cc_r y_r, zt = z + alpha d.
+// BACKTRACK: zt = z + alpha d (alpha already halved).
+__global__ __launch_bounds__(kVecThreads) void k_lb_direction(const LbDesc* __restrict__ L,
+                                                            const Item* __restrict__ items,
+                                                            int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const LbDesc& l = L[w.x];
+        const SolverState& s = *l.st;
+        if (s.skip) continue;
+        const int mode = s.mode;
+        const int mc = s.m_cur;
+        const float alpha = (float)s.alpha;
+        const float gamma = (float)s.gamma;
+        const int64_t e0 = (int64_t)w.y * kVecChunk;
+        const int64_t e1 = min(e0 + kVecChunk, l.nv);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            const float z = l.z[e];
+            if (mode == MODE_INIT) {
+                l.zt[e] = z;
+                continue;
+            }
+            float dv;
+            if (mode == MODE_NEW_DIR) {
+                dv = -gamma * l.g[e];
+                for (int r = 0; r < mc; ++r) {
+                    const int64_t o = (int64_t)s.order[r] * l.nv + e;
+                    dv = fmaf(-(float)s.ee[r], l.S[o], dv);
+                    dv = fmaf((float)s.cc[r], l.Y[o], dv);
+                }
+                l.d[e] = dv;
+            } else {
+                dv = l.d[e];
+            }
+            l.zt[e] = fmaf(alpha, dv, z);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------ decision
+// One block per slice: reduce the cost at the trial point (FP64, fixed order) and run the
+// Armijo test F(zt) <= F(z) + c1 alpha g.d.
+__global__ __launch_bounds__(256) void k_lb_decide(const SliceDesc* __restrict__ D,
+                                                  const LbDesc* __restrict__ L) {
+    __shared__ double red[4];
+    const SliceDesc& d = D[blockIdx.x];
+    SolverState& s = *L[blockIdx.x].st;
+    if (s.skip) return;
+    double a = 0.0, r0 = 0.0, r1 = 0.0;
+    for (int i = threadIdx.x; i < d.n_theta; i += 256) a += d.part_ic[i];
+    for (int b = threadIdx.x; b < d.n_reg_blocks; b += 256) {
+        r0 += d.part_reg[2 * b];
+        r1 += d.part_reg[2 * b + 1];
+    }
+    a = block_sum(a, red);
+    r0 = block_sum(r0, red);
+    r1 = block_sum(r1, red);
+    if (threadIdx.x != 0) return;
+    const double ft = a + (double)d.lam_mu * r0 + (double)d.lam_de * r1;
+    s.f_t = ft;
+    s.launches += 1;
+    s.evals += 1;
+    if (s.mode == MODE_INIT) {
+        if (!isfinite(ft)) {
+            s.accept = 0;
+            finish(s, EIT_ERR_NONFINITE);
+        } else {
+            s.accept = 1;
+            s.skip_adj = 0;
+        }
+        return;
+    }
+    s.trials += 1;
+    const bool ok = ft <= s.f + s.c1 * s.alpha * s.gd;      // false for NaN
+    if (ok) {
+        s.accept = 1;
+        s.skip_adj = 0;
+        return;
+    }
+    s.accept = 0;
+    s.skip_adj = 1;
+    if (s.trials >= s.max_ls) {
+        if (s.m_cur > 0) {           // drop the memory, retry along -g
+            reset_memory(s);
+            steepest(s);
+        } else {
+            finish(s, EIT_ERR_LINESEARCH);
+        }
+    } else {
+        s.alpha *= 0.5;
+        s.mode = MODE_BACKTRACK;
+    }
+}
+
+// ------------------------------------------------------------------------ accept: update + dots
+// s_new = zt - z, y_new = gt - g into the spare slot; z <- zt, g <- gt; per-block partial
+// inner products: [0] g.g [1] s.s [2] y.y [3] s.y [4] z_old.z_old [5] s.g [6] y.g and, for
+// every committed slot r: [7+4r] s_r.y [8+4r] y_r.y [9+4r] s_r.g [10+4r] y_r.g (g = new g).
+__global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restrict__ L,
+                                                         const Item* __restrict__ items,
+                                                         int n_items) {
+    __shared__ double red[kVecThreads / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const LbDesc& l = L[w.x];
+        const SolverState& st = *l.st;
+        if (st.skip_adj) continue;
+        const int init = st.mode == MODE_INIT;
+        const int mc = init ? 0 : st.m_cur;
+        const int64_t nv = l.nv;
+        const int64_t e0 = (int64_t)w.y * kVecChunk;
+        const int64_t e1 = min(e0 + kVecChunk, nv);
+        constexpr int PER = kVecChunk / kVecThreads;
+        float sv[PER], yv[PER], gv[PER];
+        double acc[kDotsFixed];
+        for (int q = 0; q < kDotsFixed; ++q) acc[q] = 0.0;
+        const int64_t sp = (int64_t)st.spare * nv;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
+            sv[u] = 0.f; yv[u] = 0.f; gv[u] = 0.f;
+            if (e < e1) {
+                const float gt = l.gt[e];
+                gv[u] = gt;
+                acc[0] = fma((double)gt, (double)gt, acc[0]);
+                if (!init) {
+                    const float zo = l.z[e], zn = l.zt[e], go = l.g[e];
+                    const float s = zn - zo, y = gt - go;
+                    sv[u] = s; yv[u] = y;
+                    l.S[sp + e] = s;
+                    l.Y[sp + e] = y;
+                    l.z[e] = zn;
+                    acc[1] = fma((double)s, (double)s, acc[1]);
+                    acc[2] = fma((double)y, (double)y, acc[2]);
+                    acc[3] = fma((double)s, (double)y, acc[3]);
+                    acc[4] = fma((double)zo, (double)zo, acc[4]);
+                    acc[5] = fma((double)s, (double)gt, acc[5]);
+                    acc[6] = fma((double)y, (double)gt, acc[6]);
+                }
+                l.g[e] = gt;
+            }
+        }
+        double* part = l.part + w.y - (int64_t)0;   // column w.y of [dot][n_vblocks]
+        const int nb = l.n_vblocks;
+        for (int q = 0; q < kDotsFixed; ++q) {
+            const double v = block_sum(acc[q], red);
+            if (threadIdx.x == 0) part[(int64_t)q * nb] = v;
+        }
+        for (int r = 0; r < mc; ++r) {
+            const int64_t o = (int64_t)st.order[r] * nv;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
+                if (e < e1) {
+                    const double sr = l.S[o + e], yr = l.Y[o + e];
+                    a0 = fma(sr, (double)yv[u], a0);
+                    a1 = fma(yr, (double)yv[u], a1);
+                    a2 = fma(sr, (double)gv[u], a2);
+                    a3 = fma(yr, (double)gv[u], a3);
+                }
+            }
+            a0 = block_sum(a0, red);
+            a1 = block_sum(a1, red);
+            a2 = block_sum(a2, red);
+            a3 = block_sum(a3, red);
+            if (threadIdx.x == 0) {
+                part[(int64_t)(kDotsFixed + 4 * r + 0) * nb] = a0;
+                part[(int64_t)(kDotsFixed + 4 * r + 1) * nb] = a1;
+                part[(int64_t)(kDotsFixed + 4 * r + 2) * nb] = a2;
+                part[(int64_t)(kDotsFixed + 4 * r + 3) * nb] = a3;
+            }
+        }
+        (void)sv;
+    }
+}
+
+// ------------------------------------------------------------------------ accept: finalize
+// One block per slice: reduce the partial inner products (one wavefront per product, fixed
+// order), commit the pair if s.y > 1e-10 ||s|| ||y||, advance the iteration counter, test
+// the stopping rules and compute the next direction's coefficients.
+__global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
+    __shared__ double dots[max_dots(kMaxM)];
+    const LbDesc& l = L[blockIdx.x];
+    SolverState& s = *l.st;
+    if (s.skip_adj) return;
+    const int init = s.mode == MODE_INIT;
+    const int mc = init ? 0 : s.m_cur;
+    const int nd = kDotsFixed + 4 * mc;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = wid; q < nd; q += 4) {
+        double v = 0.0;
+        for (int b = lane; b < l.n_vblocks; b += 64) v += l.part[(int64_t)q * l.n_vblocks + b];
+        v = wave_sum(v);
+        if (lane == 0) dots[q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int W = kMaxM + 1;
+    s.f = s.f_t;
+    s.gg = dots[0];
+    if (init) {
+        if (s.cost_hist) s.cost_hist[0] = s.f;
+        reset_memory(s);
+        steepest(s);
+        if (s.max_iter <= 0) { finish(s, ST_DONE); return; }
+        if (s.max_ls <= 0) { finish(s, EIT_ERR_LINESEARCH); return; }
+        s.skip_adj = 1;
+        return;
+    }
+    const double ss = dots[1], yy = dots[2], sy = dots[3], zz = dots[4];
+    double a[kMaxM], b[kMaxM];
+    for (int r = 0; r < mc; ++r) {
+        a[r] = dots[kDotsFixed + 4 * r + 2];
+        b[r] = dots[kDotsFixed + 4 * r + 3];
+    }
+    int m_new = mc;
+    if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
+        const int sp = s.spare;
+        for (int r = 0; r < mc; ++r) {
+            const int o = s.order[r];
+            s.SY[o * W + sp] = dots[kDotsFixed + 4 * r + 0];
+            const double yyr = dots[kDotsFixed + 4 * r + 1];
+            s.YY[o * W + sp] = yyr;
+            s.YY[sp * W + o] = yyr;
+        }
+        s.SY[sp * W + sp] = sy;
+        s.YY[sp * W + sp] = yy;
+        if (mc < s.m) {
+            s.order[mc] = sp;
+            a[mc] = dots[5];
+            b[mc] = dots[6];
+            m_new = mc + 1;
+            int nxt = 0;                          // smallest slot id not in the ring
+            for (;; ++nxt) {
+                bool used = false;
+                for (int r = 0; r < m_new; ++r) used |= (s.order[r] == nxt);
+                if (!used) break;
+            }
+            s.spare = nxt;
+        } else {
+            const int evict = s.order[0];
+            for (int r = 0; r + 1 < mc; ++r) {
+                s.order[r] = s.order[r + 1];
+                a[r] = a[r + 1];
+                b[r] = b[r + 1];
+            }
+            s.order[mc - 1] = sp;
+            a[mc - 1] = dots[5];
+            b[mc - 1] = dots[6];
+            s.spare = evict;
+        }
+    }
+    s.m_cur = m_new;
+    s.k += 1;
+    if (s.cost_hist) s.cost_hist[s.k] = s.f;
+    if (s.k >= s.max_iter) { finish(s, ST_DONE); return; }
+    if (s.tol > 0.0 && zz > 0.0 && sqrt(ss / zz) < s.tol) { finish(s, ST_DONE); return; }
+    if (s.m_cur == 0) steepest(s);
+    else compact_direction(s, a, b);
+    s.skip_adj = 1;
+}
+
+// ------------------------------------------------------------------------ descriptor upload
+__global__ void k_store_desc(SliceDesc v, SliceDesc* dst) { *dst = v; }
+__global__ void k_store_lbdesc(LbDesc v, LbDesc* dst) { *dst = v; }
+
+// ------------------------------------------------------------------------ launchers
+hipError_t launch_lb_init(const LbDesc* L, int n_slices, int m, int max_iter, int max_ls,
+                          double c1, double tol, hipStream_t s) {
+    k_lb_init<<<n_slices, 64, 0, s>>>(L, m, max_iter, max_ls, c1, tol);
+    return hipGetLastError();
+}
+hipError_t launch_lb_scale(const LbDesc* L, const Item* items, int n_items, int grid, int to_z,
+                           hipStream_t s) {
+    k_lb_scale<<<grid, kVecThreads, 0, s>>>(L, items, n_items, to_z);
+    return hipGetLastError();
+}
+hipError_t launch_lb_direction(const LbDesc* L, const Item* items, int n_items, int grid,
+                               hipStream_t s) {
+    k_lb_direction<<<grid, kVecThreads, 0, s>>>(L, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s) {
+    k_lb_decide<<<n_slices, 256, 0, s>>>(D, L);
+    return hipGetLastError();
+}
+hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int grid,
+                            hipStream_t s) {
+    k_lb_update<<<grid, kVecThreads, 0, s>>>(L, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s) {
+    k_lb_finalize<<<n_slices, 256, 0, s>>>(L);
+    return hipGetLastError();
+}
+hipError_t launch_store_desc(const SliceDesc& v, SliceDesc* dst, hipStream_t s) {
+    k_store_desc<<<1, 1, 0, s>>>(v, dst);
+    return hipGetLastError();
+}
+hipError_t launch_store_lbdesc(const LbDesc& v, LbDesc* dst, hipStream_t s) {
+    k_store_lbdesc<<<1, 1, 0, s>>>(v, dst);
+    return hipGetLastError();
+}
+
+}  // namespace eit

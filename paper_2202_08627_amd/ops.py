@@ -1,0 +1,238 @@
+"""Python binding over libeitomo.so: torch tensors provide device memory and the stream,
+every step runs in the library's HIP kernels. No CPU fallback exists: without the built
+library or a GPU these functions raise."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require(t, shape, dtype=torch.float32, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _f64(a, n):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())
+    if a.size < max(n, 0):
+        raise ValueError(f"array of {a.size} values, {n} needed")
+    return a
+
+
+@dataclass
+class Geometry:
+    n: int
+    n_theta: int
+    n_det: int
+    n_mask: int
+    kappa: float
+    theta: np.ndarray
+    mask_pos: np.ndarray
+    flat_amp: np.ndarray
+    flat_ctr: np.ndarray
+    flat_sigma: np.ndarray
+
+    @classmethod
+    def from_case(cls, case):
+        c = case.cfg
+        return cls(c.n, c.n_theta, c.n_det, c.n_mask, c.kappa, case.theta, case.mask_pos,
+                   case.flat_amp, case.flat_ctr, case.flat_sigma)
+
+    def c_args(self):
+        arrs = [_f64(self.theta, self.n_theta), _f64(self.mask_pos, self.n_mask),
+                _f64(self.flat_amp, self.n_det), _f64(self.flat_ctr, self.n_det),
+                _f64(self.flat_sigma, self.n_det)]
+        dims = L.Dims(self.n, self.n_theta, self.n_det, self.n_mask, float(self.kappa))
+        setup = L.Setup(*[L.dptr(a) for a in arrs])
+        return dims, setup, arrs
+
+
+def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, tables: bool = False):
+    """Host-only plan diagnostics (no GPU needed): sizes and, optionally, the FP64 tables."""
+    dims, setup, keep = geo.c_args()
+    til = L.Tiling(proj_variant, adj_variant)
+    info = L.PlanInfo()
+    L.check(L.lib().eit_plan_inspect(C.byref(dims), C.byref(setup), C.byref(til), C.byref(info),
+                                     None, None, None, None))
+    out = {f: getattr(info, f) for f, _ in L.PlanInfo._fields_}
+    if tables:
+        pa = np.zeros(6 * geo.n_theta)
+        gr = np.zeros(info.n_groups * info.proj_a, dtype=np.int32)
+        wl = np.zeros(info.n_groups * info.n_dblk * info.n_strips, dtype=np.int32)
+        aa = np.zeros(8 * geo.n_theta)
+        L.check(L.lib().eit_plan_inspect(C.byref(dims), C.byref(setup), C.byref(til), C.byref(info),
+                                         L.dptr(pa), gr.ctypes.data_as(L.IP), wl.ctypes.data_as(L.IP),
+                                         L.dptr(aa)))
+        out["proj_angles"] = pa.reshape(-1, 6)
+        out["groups"] = gr.reshape(info.n_groups, info.proj_a)
+        out["win_lo"] = wl.reshape(info.n_groups, info.n_dblk, info.n_strips)
+        out["adj_angles"] = aa.reshape(-1, 8)
+    del keep
+    return out
+
+
+def variants(kind: int):
+    """List of (a, b, c) tile shapes of the compiled projector (0) or adjoint (1) variants."""
+    n = L.lib().eit_variant_info(kind, -1, None, None, None)
+    out = []
+    for v in range(n):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        L.lib().eit_variant_info(kind, v, C.byref(a), C.byref(b), C.byref(c))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+class Plan:
+    """Owns one eit_plan (device angle/detector tables) for a slice geometry."""
+
+    def __init__(self, geo: Geometry, proj_variant: int = -1, adj_variant: int = -1):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.geo = geo
+        dims, setup, keep = geo.c_args()
+        til = L.Tiling(proj_variant, adj_variant)
+        h = C.c_void_p()
+        torch.cuda.current_device()
+        L.check(L.lib().eit_plan_create(C.byref(dims), C.byref(setup), C.byref(til), C.byref(h)))
+        del keep
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        return cls(Geometry.from_case(case), **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.lib().eit_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    @property
+    def x_shape(self):
+        return (2, self.geo.n, self.geo.n)
+
+    @property
+    def sino_shape(self):
+        return (2, self.geo.n_theta, self.geo.n_det)
+
+    @property
+    def data_shape(self):
+        return (self.geo.n_theta, self.geo.n_mask, self.geo.n_det)
+
+    def workspace_bytes(self, op: int, m: int = 10) -> int:
+        return int(L.lib().eit_workspace_bytes(self.handle, op, m))
+
+    def workspace(self, op: int, m: int = 10):
+        nb = self.workspace_bytes(op, m)
+        if nb == 0:
+            raise ValueError("invalid workspace request")
+        return torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    # -------------------------------------------------------------- operators
+    def project(self, x, out=None, ws=None):
+        _require(x, self.x_shape, name="x")
+        out = torch.empty(self.sino_shape, dtype=torch.float32, device=x.device) if out is None else out
+        ws = self.workspace(L.EIT_OP_PROJECT) if ws is None else ws
+        L.check(L.lib().eit_project(self.handle, _ptr(x), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def backproject(self, sino, out=None, ws=None):
+        _require(sino, self.sino_shape, name="sino")
+        out = torch.empty(self.x_shape, dtype=torch.float32, device=sino.device) if out is None else out
+        ws = self.workspace(L.EIT_OP_BACKPROJECT) if ws is None else ws
+        L.check(L.lib().eit_backproject(self.handle, _ptr(sino), _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream()))
+        return out
+
+    def cost_and_grad(self, x, s_exp, lam_mu: float, lam_delta: float, want_grad: bool = True,
+                      ws=None):
+        """(cost as a 0-d float64 device tensor, gradient [2][n][n] or None)."""
+        _require(x, self.x_shape, name="x")
+        _require(s_exp, self.data_shape, name="s_exp")
+        cost = torch.empty((), dtype=torch.float64, device=x.device)
+        grad = torch.empty(self.x_shape, dtype=torch.float32, device=x.device) if want_grad else None
+        ws = self.workspace(L.EIT_OP_COST_GRAD) if ws is None else ws
+        L.check(L.lib().eit_cost_and_grad(self.handle, _ptr(x), _ptr(s_exp), float(lam_mu),
+                                          float(lam_delta), _ptr(cost), _ptr(grad), _ptr(ws),
+                                          ws.numel(), _stream()))
+        return cost, grad
+
+    def reconstruct(self, s_exp, x0=None, iters: int = 50, lam: float = 1e-2, mu_scale: float = 0.05,
+                    delta_scale: float = 1e-3, m: int = 10, max_ls: int = 20, tol_rel_step: float = 0.0,
+                    c1: float = 1e-4, use_graph: bool = True, cost_hist: bool = False, ws=None):
+        """L-BFGS reconstruction; returns (x_K, report dict, cost history or None)."""
+        _require(s_exp, self.data_shape, name="s_exp")
+        if x0 is None:
+            x = torch.zeros(self.x_shape, dtype=torch.float32, device=s_exp.device)
+        else:
+            _require(x0, self.x_shape, name="x0")
+            x = x0.clone()
+        hist = torch.zeros(iters + 1, dtype=torch.float64, device=s_exp.device) if cost_hist else None
+        opts = L.Opts(iters, m, max_ls, 1 if use_graph else 0, lam, mu_scale, delta_scale,
+                      tol_rel_step, c1)
+        rep = L.Report()
+        ws = self.workspace(L.EIT_OP_RECONSTRUCT, m) if ws is None else ws
+        rc = L.lib().eit_reconstruct(self.handle, _ptr(s_exp), C.byref(opts), _ptr(x), _ptr(hist),
+                                     C.byref(rep), _ptr(ws), ws.numel(), _stream())
+        report = {f: getattr(rep, f) for f, _ in L.Report._fields_}
+        if rc not in (L.EIT_OK, L.EIT_ERR_LINESEARCH, L.EIT_ERR_NONFINITE):
+            L.check(rc)
+        report["rc"] = rc
+        return x, report, hist
+
+
+class EITCost(torch.autograd.Function):
+    """S(x) of eq. 5 as an autograd node. Forward computes the cost only and saves x;
+    backward recomputes the projections (checkpointed) and runs the adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, x, s_exp, plan: Plan, lam_mu: float, lam_delta: float):
+        cost, _ = plan.cost_and_grad(x.detach(), s_exp, lam_mu, lam_delta, want_grad=False)
+        ctx.save_for_backward(x, s_exp)
+        ctx.plan = plan
+        ctx.lam = (lam_mu, lam_delta)
+        return cost
+
+    @staticmethod
+    def backward(ctx, g_out):
+        x, s_exp = ctx.saved_tensors
+        _, grad = ctx.plan.cost_and_grad(x.detach(), s_exp, *ctx.lam, want_grad=True)
+        return (g_out.to(grad.dtype) * grad), None, None, None, None
+
+
+def eit_cost(x, s_exp, plan: Plan, lam_mu: float, lam_delta: float):
+    return EITCost.apply(x, s_exp, plan, lam_mu, lam_delta)

@@ -1,0 +1,197 @@
+"""C-ABI checks that need no GPU: every declared symbol is exported, host-side validation
+returns the documented error codes before any device call, and the launch geometry the
+host tables produce keeps every LDS access of the projector and adjoint kernels in
+bounds (emulating the kernels' FP32/FP64 index arithmetic on the host)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_08627_amd import _lib as L
+from paper_2202_08627_amd import configs, ops, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eitomo.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(eit_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = C.CDLL(L.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def geo_for(cfg, **over):
+    c = synth.make_case(cfg) if cfg.n <= 128 else None
+    if c is not None:
+        g = ops.Geometry.from_case(c)
+    else:
+        g = ops.Geometry(cfg.n, cfg.n_theta, cfg.n_det, cfg.n_mask, cfg.kappa,
+                         synth.angles(cfg.n_theta), synth.mask_positions(cfg.n_mask),
+                         np.ones(cfg.n_det), np.zeros(cfg.n_det), np.full(cfg.n_det, 0.6))
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+def inspect_rc(g):
+    try:
+        ops.inspect(g)
+        return 0
+    except L.EitError as e:
+        return e.code
+
+
+def test_validation_errors():
+    g = geo_for(configs.SMALL_64)
+    assert inspect_rc(g) == 0
+    import copy
+    for field, val, code in [("n", 1, L.EIT_ERR_SHAPE), ("n", 5000, L.EIT_ERR_SHAPE),
+                             ("n_det", 1, L.EIT_ERR_SHAPE), ("n_mask", 0, L.EIT_ERR_SHAPE),
+                             ("n_theta", 0, L.EIT_ERR_SHAPE), ("kappa", float("nan"), L.EIT_ERR_INVALID_ARG)]:
+        gg = copy.copy(g)
+        setattr(gg, field, val)
+        m = max(gg.n_mask, 1)
+        gg.mask_pos = np.zeros(m)
+        gg.theta = np.zeros(max(gg.n_theta, 1))
+        gg.flat_amp = np.ones(max(gg.n_det, 1))
+        gg.flat_ctr = np.zeros(max(gg.n_det, 1))
+        gg.flat_sigma = np.ones(max(gg.n_det, 1))
+        assert inspect_rc(gg) == code, field
+    gg = copy.copy(g)
+    gg.flat_sigma = np.full(g.n_det, -1.0)
+    assert inspect_rc(gg) == L.EIT_ERR_INVALID_ARG
+    gg = copy.copy(g)
+    gg.theta = np.full(g.n_theta, np.inf)
+    assert inspect_rc(gg) == L.EIT_ERR_INVALID_ARG
+
+
+def test_null_arguments_rejected_without_device():
+    lib = L.lib()
+    assert lib.eit_project(None, None, None, None, 0, None) == L.EIT_ERR_INVALID_ARG
+    assert lib.eit_backproject(None, None, None, None, 0, None) == L.EIT_ERR_INVALID_ARG
+    assert lib.eit_cost_and_grad(None, None, None, 0.0, 0.0, None, None, None, 0, None) == L.EIT_ERR_INVALID_ARG
+    assert lib.eit_reconstruct(None, None, None, None, None, None, None, 0, None) == L.EIT_ERR_INVALID_ARG
+    assert lib.eit_workspace_bytes(None, L.EIT_OP_RECONSTRUCT, 10) == 0
+    assert b"NULL" in lib.eit_last_error()
+    assert lib.eit_plan_create(None, None, None, None) == L.EIT_ERR_INVALID_ARG
+
+
+def test_variant_registry():
+    pv = ops.variants(0)
+    av = ops.variants(1)
+    assert len(pv) >= 3 and len(av) >= 3
+    for a, w, r in pv:
+        assert a * w <= 1024 and w % 64 == 0
+    for tx, ty, ac in av:
+        assert tx * ty <= 1024 and (tx * ty) % 64 == 0
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def fmaf(a, b, c):
+    # float32 fused multiply-add: exact product in FP64 (24x24 bits), one rounding to FP32
+    return f32(np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64))
+
+
+def check_projector_bounds(g, pv):
+    info = ops.inspect(g, proj_variant=pv, tables=True)
+    A, W, R = info["proj_a"], info["proj_w"], info["proj_r"]
+    assert info["proj_lds_bytes"] <= 64 * 1024
+    assert info["win_pitch"] >= info["win_w"]
+    pa, groups, wl = info["proj_angles"], info["groups"], info["win_lo"]
+    ng, nb, ns = wl.shape
+    nd = g.n_det
+    a_eff = np.where(groups >= 0, groups, groups[:, :1])                     # [ng, A]
+    # rows of each group share a source (all angles of a group come from one class)
+    src = pa[a_eff, 5]
+    assert np.all(src == src[:, :1])
+    kl = np.array([0, W - 1])
+    k = np.arange(nb)[:, None] * W + kl[None, :]                              # [nb, 2]
+    k_eff = np.minimum(k, nd - 1)
+    t = k_eff - 0.5 * (nd - 1)
+    inv = pa[a_eff, 0][:, None, :, None]                                      # [ng,1,A,1]
+    base = pa[a_eff, 1][:, None, :, None]
+    slope = pa[a_eff, 2][:, None, :, None, None]
+    slope_f = pa[a_eff, 3][:, None, :, None, None]
+    ut0 = t[None, :, None, :] * inv + base                                   # [ng,nb,A,2]
+    p0 = (np.arange(ns) * R).astype(np.float64)
+    lo = wl.astype(np.float64)                                               # [ng,nb,ns]
+    ur = f32(ut0[..., None] + p0[None, None, None, None, :] * slope
+             - lo[:, :, None, None, :])                                       # [ng,nb,A,2,ns]
+    for r in (0, R - 1):
+        u = fmaf(float(r), slope_f, ur)
+        i = np.trunc(u)
+        assert i.min() >= 0, (pv, i.min())
+        assert i.max() <= info["win_w"] - 2, (pv, i.max(), info["win_w"])
+
+
+def check_adjoint_bounds(g, av):
+    info = ops.inspect(g, adj_variant=av, tables=True)
+    TX, TY, kwin = info["adj_tx"], info["adj_ty"], info["kwin"]
+    assert kwin <= info["kwin_pitch_limit"]
+    aa = info["adj_angles"]
+    cs, sn, cd, csf, snf = (aa[:, q] for q in range(5))
+    i0 = (np.arange(info["n_tx"]) * TX).astype(np.float64)
+    j0 = (np.arange(info["n_ty"]) * TY).astype(np.float64)
+    I0, J0 = np.meshgrid(i0, j0, indexing="xy")
+    I0 = I0.ravel()[:, None]
+    J0 = J0.ravel()[:, None]
+    uc = J0 * sn + (I0 * cs + cd)
+    umin = uc + np.minimum(0.0, (TX - 1) * cs) + np.minimum(0.0, (TY - 1) * sn)
+    lo = np.floor(umin) - 1
+    offs = f32(uc - lo)
+    for il in (0, TX - 1):
+        for jl in (0, TY - 1):
+            u = fmaf(float(il), csf, fmaf(float(jl), snf, offs))
+            b = np.trunc(u)
+            assert b.min() >= 0, (av, b.min())
+            assert b.max() <= kwin - 2, (av, b.max(), kwin)
+
+
+SHAPES = [configs.SMALL_64, configs.SLICE_512, configs.SLICE_1024,
+          configs.SliceConfig(n=256, n_theta=360, n_det=256, n_mask=8),
+          configs.SliceConfig(n=768, n_theta=1080, n_det=768, n_mask=8),
+          configs.SliceConfig(n=37, n_theta=13, n_det=45, n_mask=3),
+          configs.SliceConfig(n=100, n_theta=7, n_det=70, n_mask=1)]
+
+
+@pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: f"{c.n}x{c.n_theta}x{c.n_det}")
+def test_lds_indices_in_bounds(cfg):
+    g = geo_for(cfg)
+    for pv in range(len(ops.variants(0))):
+        check_projector_bounds(g, pv)
+    for av in range(len(ops.variants(1))):
+        check_adjoint_bounds(g, av)
+
+
+def test_irregular_angles_in_bounds():
+    rng = np.random.default_rng(0)
+    g = geo_for(configs.SliceConfig(n=96, n_theta=50, n_det=110, n_mask=4))
+    g.theta = np.sort(rng.uniform(-np.pi, 2 * np.pi, g.n_theta))
+    for pv in range(len(ops.variants(0))):
+        check_projector_bounds(g, pv)
+    for av in range(len(ops.variants(1))):
+        check_adjoint_bounds(g, av)
+
+
+def test_row_flags_match_oracle_rule():
+    """The plan's FP64 row/column decision is the one the oracle's projector uses."""
+    from oracle import radon
+    g = geo_for(configs.SliceConfig(n=64, n_theta=720, n_det=64, n_mask=5))
+    info = ops.inspect(g, tables=True)
+    src = info["proj_angles"][:, 5]
+    assert np.array_equal(src == 0, radon.row_flags(g.theta))

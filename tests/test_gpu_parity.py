@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs. Tolerances: projections 1e-5 relative L2 (FP32), gradients 1e-4 relative L2,
+cost 1e-6 relative (FP64 reduction of FP32 residuals), reconstructions after a fixed number
+of iterations 1e-3 relative L2 per map."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbfgs as olbfgs
+from oracle import model as omodel
+from oracle import radon as oradon
+from paper_2202_08627_amd import configs, synth
+from helpers import geometry, rel_l2, tiny_cfg
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_08627_amd import ops as _ops
+    return _ops
+
+
+CASES = [
+    tiny_cfg(n=16, n_theta=24),
+    configs.SMALL_64,
+    tiny_cfg(n=37, n_theta=13, n_det=45, n_mask=3),
+    tiny_cfg(n=100, n_theta=7, n_det=70, n_mask=1),
+    tiny_cfg(n=130, n_theta=181, n_det=131, n_mask=8),
+]
+IDS = [f"{c.n}x{c.n_theta}x{c.n_det}x{c.n_mask}" for c in CASES]
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=IDS)
+def test_project_parity(ops, cfg):
+    say("project", cfg.n, cfg.n_theta, cfg.n_det)
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    rng = np.random.default_rng(1)
+    for x in (c.x_true, rng.standard_normal((2, cfg.n, cfg.n))):
+        P = host(plan.project(dev(x)))
+        x32 = x.astype(np.float32).astype(np.float64)
+        ref = np.stack([oradon.project(x32[q], c.theta, cfg.n_det) for q in range(2)])
+        assert rel_l2(P, ref) < 1e-5
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=IDS)
+def test_backproject_parity(ops, cfg):
+    say("backproject", cfg.n, cfg.n_theta, cfg.n_det)
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal((2, cfg.n_theta, cfg.n_det)).astype(np.float32).astype(np.float64)
+    B = host(plan.backproject(dev(y)))
+    ref = np.stack([oradon.backproject(y[q], c.theta, cfg.n) for q in range(2)])
+    assert rel_l2(B, ref) < 1e-5
+
+
+def test_adjoint_identity_on_gpu(ops):
+    """<R x, y> = <x, R^T y> for the gather kernel against the ray kernel (FP32 operands,
+    FP64 dot products on the host)."""
+    cfg = configs.SLICE_512
+    g = ops.Geometry(cfg.n, cfg.n_theta, cfg.n_det, cfg.n_mask, cfg.kappa, synth.angles(cfg.n_theta),
+                     synth.mask_positions(cfg.n_mask), np.ones(cfg.n_det), np.zeros(cfg.n_det),
+                     np.full(cfg.n_det, 0.6))
+    plan = ops.Plan(g)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((2, cfg.n, cfg.n), device="cuda", generator=gen)
+    y = torch.randn((2, cfg.n_theta, cfg.n_det), device="cuda", generator=gen)
+    Rx = plan.project(x)
+    RTy = plan.backproject(y)
+    lhs = float((Rx.double() * y.double()).sum())
+    rhs = float((x.double() * RTy.double()).sum())
+    scale = float(Rx.double().norm() * y.double().norm())
+    assert abs(lhs - rhs) < 1e-5 * scale
+
+
+def test_no_sample_gives_flat_field(ops):
+    """mu = delta = 0 => s_mod = f: the cost equals sum (f - s_exp)^2 (P6 on the device)."""
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    z = np.zeros((2, cfg.n, cfg.n))
+    cost, grad = plan.cost_and_grad(dev(z), dev(c.s_exp), 0.0, 0.0)
+    f = c.flat_amp * np.exp(-(c.mask_pos[:, None] - c.flat_ctr) ** 2 / (2 * c.flat_sigma ** 2))
+    ref = float(np.sum((f[None] - c.s_exp.astype(np.float64)) ** 2))
+    assert float(cost) == pytest.approx(ref, rel=1e-6)
+
+
+@pytest.mark.parametrize("cfg", CASES[:4], ids=IDS[:4])
+def test_cost_and_grad_parity(ops, cfg):
+    say("cost_and_grad", cfg.n, cfg.n_theta)
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    geo = geometry(c, omodel)
+    rng = np.random.default_rng(3)
+    x = c.x_true + 0.3 * np.stack([cfg.mu_scale * rng.standard_normal((cfg.n, cfg.n)),
+                                   cfg.delta_scale * rng.standard_normal((cfg.n, cfg.n))])
+    x = x.astype(np.float32).astype(np.float64)
+    cost, grad = plan.cost_and_grad(dev(x), dev(c.s_exp), cfg.lam_mu, cfg.lam_delta)
+    S, gm, gd = omodel.cost_and_grad(x[0], x[1], c.s_exp, geo, cfg.lam_mu, cfg.lam_delta)
+    assert float(cost) == pytest.approx(S, rel=1e-5)
+    G = host(grad)
+    assert rel_l2(G[0], gm) < 1e-4
+    assert rel_l2(G[1], gd) < 1e-4
+
+
+def test_autograd_function_matches_oracle(ops):
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    geo = geometry(c, omodel)
+    x = (c.x_true * 0.8).astype(np.float32).astype(np.float64)
+    xt = dev(x).requires_grad_(True)
+    S = ops.eit_cost(xt, dev(c.s_exp), plan, cfg.lam_mu, cfg.lam_delta)
+    (2.0 * S).backward()
+    S_o, gm, gd = omodel.cost_and_grad(x[0], x[1], c.s_exp, geo, cfg.lam_mu, cfg.lam_delta)
+    assert float(S) == pytest.approx(S_o, rel=1e-5)
+    G = host(xt.grad) / 2.0
+    assert rel_l2(G[0], gm) < 1e-4 and rel_l2(G[1], gd) < 1e-4
+
+
+def _oracle_recon(c, cfg, iters, m=10):
+    geo = geometry(c, omodel)
+    prob = omodel.ScaledProblem(c.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
+    return olbfgs.reconstruct(prob, np.zeros((2, cfg.n, cfg.n)), iters, m=m)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_reconstruct_parity_small(ops, use_graph):
+    """Plain method at 64^2 / 90 angles / M = 5: x_50 within 1e-3 relative L2 per map."""
+    cfg = configs.SMALL_64
+    say("reconstruct small graph=", use_graph)
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    x, rep, hist = plan.reconstruct(dev(c.s_exp), iters=cfg.iters, lam=cfg.lam, mu_scale=cfg.mu_scale,
+                                    delta_scale=cfg.delta_scale, use_graph=use_graph, cost_hist=True)
+    xo, st, tr = _oracle_recon(c, cfg, cfg.iters)
+    say("report", rep, "oracle evals", st.evals)
+    assert rep["rc"] == 0 and rep["iters"] == cfg.iters
+    X = host(x)
+    assert rel_l2(X[0], xo[0]) < 1e-3
+    assert rel_l2(X[1], xo[1]) < 1e-3
+    h = host(hist)
+    assert np.allclose(h[1:], tr.cost, rtol=1e-4)
+    assert np.all(np.diff(h) <= 0)
+
+
+def test_reconstruct_forced_line_search_failure(ops):
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    x, rep, _ = plan.reconstruct(dev(c.s_exp), iters=5, max_ls=0)
+    assert rep["rc"] == -6 and rep["iters"] == 0
+
+
+def test_reconstruct_nonfinite_data(ops):
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    s = c.s_exp.copy()
+    s[3, 1, 7] = np.nan
+    plan = ops.Plan.from_case(c)
+    x, rep, _ = plan.reconstruct(dev(s), iters=5)
+    assert rep["rc"] == -5 and rep["iters"] == 0
+
+
+def test_reconstruct_zero_iterations_returns_start(ops):
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    x0 = dev(c.x_true)
+    x, rep, _ = plan.reconstruct(dev(c.s_exp), x0=x0, iters=0)
+    assert rep["rc"] == 0 and rep["iters"] == 0
+    assert torch.allclose(x, x0, rtol=1e-6, atol=0)
+
+
+def test_opts_validation(ops):
+    from paper_2202_08627_amd import _lib as L
+    cfg = configs.SMALL_64
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    for kw in (dict(m=0), dict(m=21), dict(lam=-1.0), dict(mu_scale=0.0), dict(c1=1.5),
+               dict(iters=-1), dict(max_ls=-2)):
+        with pytest.raises(L.EitError) as e:
+            plan.reconstruct(dev(c.s_exp), **kw)
+        assert e.value.code == L.EIT_ERR_INVALID_ARG
+
+
+def test_large_slice_sampled_projection(ops):
+    """Full-size 512^2 / 720-angle workload: the projector in the benchmark's launch shape,
+    checked against the oracle on 24 sampled angles (the oracle's rows are independent)."""
+    cfg = configs.SLICE_512
+    say("large projection")
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    P = host(plan.project(dev(c.x_true)))
+    sel = np.linspace(0, cfg.n_theta - 1, 24).astype(int)
+    sel = np.unique(np.concatenate([sel, [0, 180, 360, 540]]))
+    x32 = c.x_true.astype(np.float32).astype(np.float64)
+    for q in range(2):
+        ref = oradon.project(x32[q], c.theta[sel], cfg.n_det)
+        assert rel_l2(P[q, sel], ref) < 1e-5
+
+
+def test_large_slice_sampled_backprojection(ops):
+    cfg = configs.SLICE_512
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    rng = np.random.default_rng(4)
+    sel = np.unique(np.linspace(0, cfg.n_theta - 1, 20).astype(int))
+    y = np.zeros((2, cfg.n_theta, cfg.n_det))
+    y[:, sel] = rng.standard_normal((2, sel.size, cfg.n_det)).astype(np.float32)
+    B = host(plan.backproject(dev(y)))
+    for q in range(2):
+        ref = oradon.backproject(y[q, sel], c.theta[sel], cfg.n)
+        assert rel_l2(B[q], ref) < 1e-5
