@@ -111,7 +111,21 @@ typedef struct {
     double mu_scale, delta_scale;   /* > 0 */
     double tol_rel_step;    /* stop when ||z_{k+1}-z_k|| / ||z_k|| < tol (0 = off) */
     double c1;              /* Armijo constant, 0 < c1 < 1 (typ. 1e-4) */
+    int32_t profile;        /* nonzero: direct launches bracketed by hipEvents per phase
+                               (fills eit_report.phase_ms; use_graph is ignored) */
+    int32_t pad;
 } eit_opts;
+
+/* Phases of one evaluation step, in launch order (indices of eit_report.phase_ms). */
+#define EIT_PHASE_DIRECTION 0   /* L-BFGS direction and trial point */
+#define EIT_PHASE_TRANSPOSE 1   /* transposed copy of the trial point, ||z||^2 partials */
+#define EIT_PHASE_PROJECT 2     /* Radon transform of both maps */
+#define EIT_PHASE_IC 3          /* IC model, residual, cost partials, adjoint seeds */
+#define EIT_PHASE_DECIDE 4      /* cost reduction and Armijo decision */
+#define EIT_PHASE_BACKPROJECT 5 /* adjoint backprojection (gradient) */
+#define EIT_PHASE_UPDATE 6      /* accepted step: s, y, inner products */
+#define EIT_PHASE_FINALIZE 7    /* memory update and next direction coefficients */
+#define EIT_N_PHASES 8
 
 /* Host report filled by eit_reconstruct after its final stream synchronisation. */
 typedef struct {
@@ -121,6 +135,9 @@ typedef struct {
     int32_t launches;       /* evaluation steps enqueued (no-op steps included) */
     double cost;            /* final cost F(z) */
     double gnorm;           /* final ||grad_z F|| */
+    double phase_ms[EIT_N_PHASES];   /* profile mode: summed device time per phase */
+    int32_t phase_steps;    /* profile mode: steps timed */
+    int32_t pad;
 } eit_report;
 
 /* Create a plan: validates sizes, computes the angle/detector tables in FP64 on the host

@@ -49,12 +49,16 @@ class Tiling(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lbfgs_m", C.c_int32), ("max_ls_trials", C.c_int32),
                 ("use_graph", C.c_int32), ("lam", C.c_double), ("mu_scale", C.c_double),
-                ("delta_scale", C.c_double), ("tol_rel_step", C.c_double), ("c1", C.c_double)]
+                ("delta_scale", C.c_double), ("tol_rel_step", C.c_double), ("c1", C.c_double),
+                ("profile", C.c_int32), ("pad", C.c_int32)]
 
 
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("evals", C.c_int32),
-                ("launches", C.c_int32), ("cost", C.c_double), ("gnorm", C.c_double)]
+                ("launches", C.c_int32), ("cost", C.c_double), ("gnorm", C.c_double),
+                ("phase_ms", C.c_double * 8), ("phase_steps", C.c_int32), ("pad", C.c_int32)]
+
+PHASES = ["direction", "transpose", "project", "ic", "decide", "backproject", "update", "finalize"]
 
 
 class PlanInfo(C.Structure):

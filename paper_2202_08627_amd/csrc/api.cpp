@@ -411,7 +411,7 @@ SliceDesc base_desc(const eit_plan* p) {
     SliceDesc d{};
     d.n = p->n; d.n_theta = p->n_theta; d.n_det = p->n_det; d.n_mask = p->n_mask;
     d.kappa = (float)p->kappa;
-    d.scale_mu = 1.f; d.scale_de = 1.f;
+    d.scale_mu = 1.0; d.scale_de = 1.0;
     d.proj_tile = p->proj_v; d.adj_tile = p->adj_v;
     d.n_groups = p->n_groups; d.n_dblk = p->n_dblk; d.n_strips = p->n_strips;
     d.win_w = p->win_w; d.win_shift = p->win_shift;
@@ -518,8 +518,8 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
     d.part_ic = (double*)at(ws, L.part_ic);
     d.part_reg = (double*)at(ws, L.part_reg);
     d.cost = cost_dev;
-    d.lam_mu = (float)lam_mu; d.lam_de = (float)lam_delta;
-    d.reg_mu = (float)(2.0 * lam_mu); d.reg_de = (float)(2.0 * lam_delta);
+    d.lam_mu = lam_mu; d.lam_de = lam_delta;
+    d.reg_mu = 2.0 * lam_mu; d.reg_de = 2.0 * lam_delta;
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     HIP_TRY(launch_store_desc(d, dd, st));
     if (int rc = enqueue_eval(p, dd, grad != nullptr, false, st)) return rc;
@@ -561,31 +561,76 @@ struct StepPlan {
     const Item* it_vec; int n_vec;
 };
 
-int enqueue_step(const StepPlan& sp, hipStream_t st) {
+// ev: optional array of EIT_N_PHASES + 1 events recorded around the phases.
+int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev = nullptr) {
+    auto mark = [&](int i) -> int {
+        if (ev) HIP_TRY(hipEventRecord(ev[i], st));
+        return EIT_OK;
+    };
+    if (int rc = mark(0)) return rc;
     HIP_TRY(launch_lb_direction(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+    if (int rc = mark(1)) return rc;
     HIP_TRY(launch_transpose(sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
+    if (int rc = mark(2)) return rc;
     for (const auto& l : sp.proj)
         HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
+    if (int rc = mark(3)) return rc;
     HIP_TRY(launch_ic(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
+    if (int rc = mark(4)) return rc;
     HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
+    if (int rc = mark(5)) return rc;
     for (const auto& l : sp.adj)
         HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 1, st));
+    if (int rc = mark(6)) return rc;
     HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+    if (int rc = mark(7)) return rc;
     HIP_TRY(launch_lb_finalize(sp.L, sp.n_slices, st));
-    return EIT_OK;
+    return mark(8);
 }
+
+struct PhaseTimer {
+    std::vector<hipEvent_t> ev;     // (steps) x (EIT_N_PHASES + 1)
+    double ms[EIT_N_PHASES] = {0};
+    int steps = 0;
+    ~PhaseTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    int next(hipEvent_t** out) {
+        const size_t base = ev.size();
+        for (int i = 0; i <= EIT_N_PHASES; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        *out = &ev[base];
+        ++steps;
+        return EIT_OK;
+    }
+    int collect() {
+        for (int s = 0; s < steps; ++s)
+            for (int i = 0; i < EIT_N_PHASES; ++i) {
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, ev[(size_t)s * (EIT_N_PHASES + 1) + i],
+                                            ev[(size_t)s * (EIT_N_PHASES + 1) + i + 1]));
+                ms[i] += t;
+            }
+        return EIT_OK;
+    }
+};
 
 // Replays the step until every slice's optimiser has stopped. Reads back (status, k) of each
 // slice only between rounds of launches; each round enqueues as many steps as the slowest
 // slice still needs iterations (every accepted iteration needs at least one evaluation).
 int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-             bool use_graph, hipStream_t st, int* launches_out);
+             bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt);
 
 // The null stream cannot be captured: graph replays then run on a private non-blocking
 // stream ordered after (and before) the caller's work through events.
 int drive(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-          bool use_graph, hipStream_t st, int* launches_out) {
-    if (!use_graph || st != nullptr) return drive_on(sp, states, max_iter, max_ls, use_graph, st, launches_out);
+          bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt) {
+    if (pt) use_graph = false;
+    if (!use_graph || st != nullptr)
+        return drive_on(sp, states, max_iter, max_ls, use_graph, st, launches_out, pt);
     hipStream_t side = nullptr;
     hipEvent_t ev = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -594,7 +639,7 @@ int drive(const StepPlan& sp, const std::vector<SolverState*>& states, int max_i
     if (e == hipSuccess) e = hipEventRecord(ev, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, ev, 0);
     if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "stream ordering: %s", hipGetErrorString(e));
-    if (!rc) rc = drive_on(sp, states, max_iter, max_ls, true, side, launches_out);
+    if (!rc) rc = drive_on(sp, states, max_iter, max_ls, true, side, launches_out, nullptr);
     if (!rc) {
         e = hipEventRecord(ev, side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
@@ -607,7 +652,7 @@ int drive(const StepPlan& sp, const std::vector<SolverState*>& states, int max_i
 }
 
 int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-             bool use_graph, hipStream_t st, int* launches_out) {
+             bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt) {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     if (use_graph) {
@@ -633,7 +678,9 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
                 hipError_t e = hipGraphLaunch(exec, st);
                 if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
             } else {
-                rc = enqueue_step(sp, st);
+                hipEvent_t* ev = nullptr;
+                if (pt) rc = pt->next(&ev);
+                if (!rc) rc = enqueue_step(sp, st, ev);
             }
             ++total;
         }
@@ -683,9 +730,9 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     d.part_ic = (double*)at(ws, S.ev.part_ic);
     d.part_reg = (double*)at(ws, S.ev.part_reg);
     d.cost = &state->f_t;
-    d.scale_mu = (float)o->mu_scale; d.scale_de = (float)o->delta_scale;
-    d.lam_mu = (float)o->lam; d.lam_de = (float)o->lam;
-    d.reg_mu = (float)(2.0 * o->lam); d.reg_de = (float)(2.0 * o->lam);
+    d.scale_mu = o->mu_scale; d.scale_de = o->delta_scale;
+    d.lam_mu = o->lam; d.lam_de = o->lam;
+    d.reg_mu = 2.0 * o->lam; d.reg_de = 2.0 * o->lam;
     d.skip = &state->skip;
     d.skip_adj = &state->skip_adj;
 
@@ -716,7 +763,9 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     sp.it_ic = p->it_ic; sp.n_ic = p->n_it_ic;
     sp.it_vec = p->it_vec; sp.n_vec = p->n_it_vec;
     int launches = 0;
-    if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches))
+    PhaseTimer timer;
+    PhaseTimer* pt = o->profile ? &timer : nullptr;
+    if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches, pt))
         return rc;
     HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 0, st));
     SolverState hs;
@@ -729,6 +778,13 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
         rep->launches = launches;
         rep->cost = hs.f;
         rep->gnorm = std::sqrt(hs.gg);
+        for (int i = 0; i < EIT_N_PHASES; ++i) rep->phase_ms[i] = 0.0;
+        rep->phase_steps = 0;
+        if (pt) {
+            if (int rc = pt->collect()) return rc;
+            for (int i = 0; i < EIT_N_PHASES; ++i) rep->phase_ms[i] = pt->ms[i];
+            rep->phase_steps = pt->steps;
+        }
     }
     if (hs.status < 0)
         return fail(hs.status, hs.status == EIT_ERR_NONFINITE ? "cost is not finite at the start"

@@ -41,9 +41,9 @@ struct AdjTile  { int TX, TY, AC; };      // voxel tile, angles per staged chunk
 struct SliceDesc {
     int32_t n, n_theta, n_det, n_mask;
     float kappa;
-    float scale_mu, scale_de;      // P_raw = scale * R x   (1 for raw units)
-    float reg_mu, reg_de;          // gradient adds reg * x  (2 lambda)
-    float lam_mu, lam_de;          // cost adds lam * ||x||^2
+    double scale_mu, scale_de;     // P_raw = scale * R x   (1 for raw units)
+    double reg_mu, reg_de;         // gradient adds reg * x  (2 lambda)
+    double lam_mu, lam_de;         // cost adds lam * ||x||^2
     int32_t proj_tile, adj_tile;   // variant ids
     // projector work decomposition
     int32_t n_groups, n_dblk, n_strips, win_w;

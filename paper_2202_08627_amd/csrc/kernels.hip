@@ -96,7 +96,7 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
         const float* sd = sm + (size_t)n * n;
         const int32_t* lo_tab = d.win_lo + ((size_t)grp * d.n_dblk + dblk) * d.n_strips;
         const int pshift = d.win_shift, pitch = 1 << pshift, win_w = d.win_w;
-        float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+        double acc_m = 0.0, acc_d = 0.0;
         for (int s = 0; s < d.n_strips; ++s) {
             const int p0 = s * R;
             const int lo = lo_tab[s];
@@ -115,14 +115,24 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
                 }
             }
             __syncthreads();
-            const float ur = (float)(fma((double)p0, pa.slope, ut0) - (double)lo);
+            // Ray origin for this strip split into an integer window column and a fraction
+            // in [0, 1) (FP64), so the FP32 interpolation coordinate stays below ~R in
+            // magnitude and keeps ~1e-6 absolute precision.
+            const double up0 = fma((double)p0, pa.slope, ut0);
+            const double fl0 = floor(up0);
+            const float uf = (float)(up0 - fl0);
+            const int ioff = (int)fl0 - lo;                 // >= 1 by construction of lo
+            const int imin = -ioff, imax = win_w - 2 - ioff;
+            const float2* rowp = win + ioff;
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float u = fmaf((float)r, pa.slope_f, ur);
-                int i = (int)u;                 // u >= 1 by construction of lo
-                const float ph = u - (float)i;
-                i = min(max(i, 0), win_w - 2);
-                const float2* q = win + (r << pshift) + i;
+                const float u = fmaf((float)r, pa.slope_f, uf);
+                const float fl = floorf(u);
+                const float ph = u - fl;
+                const int i = min(max((int)fl, imin), imax);
+                const float2* q = rowp + i;
+                rowp += pitch;
                 const float2 v0 = q[0], v1 = q[1];
                 const float om = 1.f - ph;
                 c0 = fmaf(om, v0.x, c0);
@@ -130,10 +140,12 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
                 c2 = fmaf(ph, v1.x, c2);
                 c3 = fmaf(ph, v1.y, c3);
             }
+            acc_m += (double)c0 + (double)c2;     // strip sums combined in FP64
+            acc_d += (double)c1 + (double)c3;
         }
         if (a >= 0 && k < d.n_det) {
-            d.P[(size_t)a * d.n_det + k] = pa.w * (c0 + c2);
-            d.P[((size_t)d.n_theta + a) * d.n_det + k] = pa.w * (c1 + c3);
+            d.P[(size_t)a * d.n_det + k] = (float)(pa.w * acc_m);
+            d.P[((size_t)d.n_theta + a) * d.n_det + k] = (float)(pa.w * acc_d);
         }
     }
 }
@@ -160,27 +172,30 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
         float* Pm = d.P + (size_t)a * nd;
         float* Pd = d.P + ((size_t)d.n_theta + a) * nd;
         const float* se = d.s_exp + (size_t)a * M * nd;
-        const float sm = d.scale_mu, sdl = d.scale_de, kap = d.kappa;
+        const double sm = d.scale_mu, sdl = d.scale_de;
+        const float kap = d.kappa;
         double r2 = 0.0;
         for (int k = threadIdx.x; k < nd; k += kIcThreads) {
-            const float pm = sm * Pm[k];
-            const float pp = k + 1 < nd ? sdl * Pd[k + 1] : 0.f;
-            const float pn = k > 0 ? sdl * Pd[k - 1] : 0.f;
-            const float T = expf(-pm);
-            const float dl = kap * 0.5f * (pp - pn);
+            // The residual is a small difference of O(1) numbers, so the model is evaluated
+            // in FP64 from the FP32 projections.
+            const double pm = sm * (double)Pm[k];
+            const double pp = k + 1 < nd ? sdl * (double)Pd[k + 1] : 0.0;
+            const double pn = k > 0 ? sdl * (double)Pd[k - 1] : 0.0;
+            const double T = exp(-pm);
+            const double dl = (double)kap * 0.5 * (pp - pn);
             const float4 fl = d.flat[k];       // A, c, 1/(2 s^2), 1/s^2
-            float sf = 0.f, sfp = 0.f;
+            double sf = 0.0, sfp = 0.0;
             for (int j = 0; j < M; ++j) {
-                const float uu = d.mask[j] - dl - fl.y;
-                const float f = fl.x * expf(-uu * uu * fl.z);
-                const float r = fmaf(T, f, -se[(size_t)j * nd + k]);
-                r2 = fma((double)r, (double)r, r2);
-                sf = fmaf(r, f, sf);
-                sfp = fmaf(r, -uu * fl.w * f, sfp);
+                const double uu = (double)d.mask[j] - dl - (double)fl.y;
+                const double f = (double)fl.x * exp(-uu * uu * (double)fl.z);
+                const double r = fma(T, f, -(double)se[(size_t)j * nd + k]);
+                r2 = fma(r, r, r2);
+                sf = fma(r, f, sf);
+                sfp = fma(r, -uu * (double)fl.w * f, sfp);
             }
             if (want_seeds) {
-                Pm[k] = sm * (-2.f * T * sf);          // G_Pmu, scaled
-                gdl[k] = -2.f * T * sfp;               // G_Delta
+                Pm[k] = (float)(sm * (-2.0 * T * sf));   // G_Pmu, scaled
+                gdl[k] = (float)(-2.0 * T * sfp);               // G_Delta
             }
         }
         __syncthreads();   // all reads of Pd done, gdl complete
@@ -188,7 +203,7 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
             for (int k = threadIdx.x; k < nd; k += kIcThreads) {
                 const float gp = k + 1 < nd ? gdl[k + 1] : 0.f;
                 const float gn = k > 0 ? gdl[k - 1] : 0.f;
-                Pd[k] = sdl * (-kap * 0.5f * (gp - gn));
+                Pd[k] = (float)(sdl * (-(double)kap * 0.5 * ((double)gp - (double)gn)));
             }
         }
         r2 = block_sum(r2, red);
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(256) void k_cost_reduce(const SliceDesc* __restrict
     s = block_sum(s, red);
     r0 = block_sum(r0, red);
     r1 = block_sum(r1, red);
-    if (threadIdx.x == 0) d.cost[0] = s + (double)d.lam_mu * r0 + (double)d.lam_de * r1;
+    if (threadIdx.x == 0) d.cost[0] = s + d.lam_mu * r0 + d.lam_de * r1;
 }
 
 // ------------------------------------------------------------------------ adjoint
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(TX* TY) void k_backproject(const SliceDesc* __restr
         const int i0 = w.y * TX, j0 = w.z * TY;
         const float* Gm = d.P;
         const float* Gd = d.P + (size_t)nth * nd;
-        float am = 0.f, ad = 0.f;
+        double acc_m = 0.0, acc_d = 0.0;
         const float fil = (float)il, fjl = (float)jl;
         for (int ab = 0; ab < nth; ab += AC) {
             const int na = min(AC, nth - ab);
@@ -278,6 +293,7 @@ __global__ __launch_bounds__(TX* TY) void k_backproject(const SliceDesc* __restr
                 }
             }
             __syncthreads();
+            float am = 0.f, ad = 0.f;
             for (int aa = 0; aa < na; ++aa) {
                 const AdjAngle q = d.aang[ab + aa];
                 const float u = fmaf(fil, q.cs_f, fmaf(fjl, q.sn_f, offs[aa]));
@@ -291,17 +307,19 @@ __global__ __launch_bounds__(TX* TY) void k_backproject(const SliceDesc* __restr
                 am = fmaf(w0, g0.x, fmaf(w1, g1.x, am));
                 ad = fmaf(w0, g0.y, fmaf(w1, g1.y, ad));
             }
+            acc_m += (double)am;          // chunk sums combined in FP64
+            acc_d += (double)ad;
         }
         const int i = i0 + il, j = j0 + jl;
         if (i < n && j < n) {
             const size_t o = (size_t)j * n + i;
             const size_t o2 = o + (size_t)n * n;
             if (add_reg) {
-                am = fmaf(d.reg_mu, d.x[o], am);
-                ad = fmaf(d.reg_de, d.x[o2], ad);
+                acc_m = fma(d.reg_mu, (double)d.x[o], acc_m);
+                acc_d = fma(d.reg_de, (double)d.x[o2], acc_d);
             }
-            d.g[o] = am;
-            d.g[o2] = ad;
+            d.g[o] = (float)acc_m;
+            d.g[o2] = (float)acc_d;
         }
     }
 }

@@ -118,8 +118,8 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_direction(const LbDesc* __re
         if (s.skip) continue;
         const int mode = s.mode;
         const int mc = s.m_cur;
-        const float alpha = (float)s.alpha;
-        const float gamma = (float)s.gamma;
+        const double alpha = s.alpha;
+        const double gamma = s.gamma;
         const int64_t e0 = (int64_t)w.y * kVecChunk;
         const int64_t e1 = min(e0 + kVecChunk, l.nv);
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
@@ -128,19 +128,20 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_direction(const LbDesc* __re
                 l.zt[e] = z;
                 continue;
             }
-            float dv;
+            double dv;
             if (mode == MODE_NEW_DIR) {
-                dv = -gamma * l.g[e];
+                // the direction is a combination with cancellation: accumulate in FP64
+                dv = -gamma * (double)l.g[e];
                 for (int r = 0; r < mc; ++r) {
                     const int64_t o = (int64_t)s.order[r] * l.nv + e;
-                    dv = fmaf(-(float)s.ee[r], l.S[o], dv);
-                    dv = fmaf((float)s.cc[r], l.Y[o], dv);
+                    dv = fma(-s.ee[r], (double)l.S[o], dv);
+                    dv = fma(s.cc[r], (double)l.Y[o], dv);
                 }
-                l.d[e] = dv;
+                l.d[e] = (float)dv;
             } else {
-                dv = l.d[e];
+                dv = (double)l.d[e];
             }
-            l.zt[e] = fmaf(alpha, dv, z);
+            l.zt[e] = (float)fma(alpha, dv, (double)z);
         }
     }
 }
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void k_lb_decide(const SliceDesc* __restrict__
     r0 = block_sum(r0, red);
     r1 = block_sum(r1, red);
     if (threadIdx.x != 0) return;
-    const double ft = a + (double)d.lam_mu * r0 + (double)d.lam_de * r1;
+    const double ft = a + d.lam_mu * r0 + d.lam_de * r1;
     s.f_t = ft;
     s.launches += 1;
     s.evals += 1;

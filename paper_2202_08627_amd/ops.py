@@ -193,7 +193,8 @@ class Plan:
 
     def reconstruct(self, s_exp, x0=None, iters: int = 50, lam: float = 1e-2, mu_scale: float = 0.05,
                     delta_scale: float = 1e-3, m: int = 10, max_ls: int = 20, tol_rel_step: float = 0.0,
-                    c1: float = 1e-4, use_graph: bool = True, cost_hist: bool = False, ws=None):
+                    c1: float = 1e-4, use_graph: bool = True, cost_hist: bool = False, ws=None,
+                    profile: bool = False):
         """L-BFGS reconstruction; returns (x_K, report dict, cost history or None)."""
         _require(s_exp, self.data_shape, name="s_exp")
         if x0 is None:
@@ -203,12 +204,13 @@ class Plan:
             x = x0.clone()
         hist = torch.zeros(iters + 1, dtype=torch.float64, device=s_exp.device) if cost_hist else None
         opts = L.Opts(iters, m, max_ls, 1 if use_graph else 0, lam, mu_scale, delta_scale,
-                      tol_rel_step, c1)
+                      tol_rel_step, c1, 1 if profile else 0, 0)
         rep = L.Report()
         ws = self.workspace(L.EIT_OP_RECONSTRUCT, m) if ws is None else ws
         rc = L.lib().eit_reconstruct(self.handle, _ptr(s_exp), C.byref(opts), _ptr(x), _ptr(hist),
                                      C.byref(rep), _ptr(ws), ws.numel(), _stream())
-        report = {f: getattr(rep, f) for f, _ in L.Report._fields_}
+        report = {f: getattr(rep, f) for f, _ in L.Report._fields_ if f not in ("phase_ms", "pad")}
+        report["phase_ms"] = dict(zip(L.PHASES, list(rep.phase_ms)))
         if rc not in (L.EIT_OK, L.EIT_ERR_LINESEARCH, L.EIT_ERR_NONFINITE):
             L.check(rc)
         report["rc"] = rc
