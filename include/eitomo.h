@@ -220,9 +220,10 @@ int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_til
 const char* eit_last_error(void);
 
 /* Compiled tile variants: kind 0 = projector (a = angles per group, b = detectors per
- * block, c = rows per strip), kind 1 = adjoint (a, b = voxel tile, c = angles per chunk).
- * Returns the number of variants of that kind; fills a/b/c for index v if in range. */
-int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c);
+ * block, c = rows per strip, d = staged pairs per row), kind 1 = adjoint (a, b = voxel tile,
+ * c = angles per chunk, d = voxels per thread). Returns the number of variants of that kind;
+ * fills a/b/c/d (each may be NULL) for index v if in range. */
+int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c, int32_t* d);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,10 @@ struct Layout {
     }
 };
 
-int default_proj_variant(int n) { return n <= 128 ? 1 : 0; }
+// Projector variants tried in order when the caller does not choose one; the last (one
+// angle per group, window <= 64/cos(45 deg) + 16 + 4 columns) fits every geometry.
+const int kProjPrefSmall[] = {1, 7, 8};
+const int kProjPrefLarge[] = {0, 1, 7, 8};
 int default_adj_variant(int n) { (void)n; return 0; }
 
 int grid_for(int n_items, int cap) { return std::max(1, std::min(n_items, cap)); }
@@ -173,11 +176,24 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
             !std::isfinite(setup->flat_ctr[k]))
             return fail(EIT_ERR_INVALID_ARG, "flat-field parameters of pixel %d invalid", k);
     }
-    int pv = tiling && tiling->proj_variant >= 0 ? tiling->proj_variant : default_proj_variant(n);
+    const bool pv_given = tiling && tiling->proj_variant >= 0;
+    int pv = pv_given ? tiling->proj_variant : (n <= 128 ? kProjPrefSmall[0] : kProjPrefLarge[0]);
     int av = tiling && tiling->adj_variant >= 0 ? tiling->adj_variant : default_adj_variant(n);
     if (pv >= proj_variant_count()) return fail(EIT_ERR_INVALID_ARG, "proj_variant %d unknown", pv);
     if (av >= adj_variant_count()) return fail(EIT_ERR_INVALID_ARG, "adj_variant %d unknown", av);
-
+    if (!pv_given) {
+        // first preferred variant whose staging window fits
+        const int* pref = n <= 128 ? kProjPrefSmall : kProjPrefLarge;
+        const int np = n <= 128 ? 3 : 4;
+        for (int q = 0; q < np; ++q) {
+            eit_tiling t{pref[q], av};
+            eit_plan probe{};
+            HostTables hh;
+            const std::string keep = g_err;
+            if (build_host(dims, setup, &t, &probe, hh) == EIT_OK) { pv = pref[q]; break; }
+            g_err = keep;
+        }
+    }
     p->n = n; p->n_theta = nt; p->n_det = nd; p->n_mask = nm; p->kappa = dims->kappa;
     p->proj_v = pv; p->adj_v = av; p->device = -1;
     p->pt = proj_variant(pv);
@@ -234,10 +250,11 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         }
     p->win_w = win_w;
     p->win_shift = 0;
-    while ((1 << p->win_shift) < win_w) ++p->win_shift;
-    p->proj_lds = (size_t)R * ((size_t)1 << p->win_shift) * sizeof(float2);
-    if (p->proj_lds > 64 * 1024) {
-        return fail(EIT_ERR_SHAPE, "projector window %d too wide for variant %d", win_w, pv);
+    while ((1 << p->win_shift) < p->pt.PW) ++p->win_shift;
+    p->proj_lds = (size_t)R * (size_t)p->pt.PW * sizeof(float2);
+    if (win_w > p->pt.PW) {
+        return fail(EIT_ERR_SHAPE, "projector window %d wider than variant %d's pitch %d", win_w,
+                    pv, p->pt.PW);
     }
 
     // ---- adjoint tables
@@ -795,7 +812,8 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
 // ============================================================================ misc
 extern "C" const char* eit_last_error(void) { return g_err.c_str(); }
 
-extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c) {
+extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c,
+                                int32_t* dd) {
     if (kind == 0) {
         const int n = proj_variant_count();
         if (v >= 0 && v < n) {
@@ -803,6 +821,7 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
             if (a) *a = t.A;
             if (b) *b = t.W;
             if (c) *c = t.R;
+            if (dd) *dd = t.PW;
         }
         return n;
     }
@@ -813,6 +832,7 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
             if (a) *a = t.TX;
             if (b) *b = t.TY;
             if (c) *c = t.AC;
+            if (dd) *dd = t.VPT;
         }
         return n;
     }

@@ -32,8 +32,8 @@ struct AdjAngle {
 };
 
 // Tile shapes (compile-time variants, chosen per grid-size class).
-struct ProjTile { int A, W, R; };         // angles per group, detectors per block, rows per strip
-struct AdjTile  { int TX, TY, AC; };      // voxel tile, angles per staged chunk
+struct ProjTile { int A, W, R, PW; };     // angles per group, detectors per block, rows per strip, pitch
+struct AdjTile  { int TX, TY, AC, VPT; }; // voxel tile, angles per staged chunk, voxels per thread
 
 // ---------------------------------------------------------------- per-slice descriptor
 // Everything a kernel needs for one slice. Lives in device memory; kernels index it by the

@@ -18,6 +18,15 @@ __device__ __forceinline__ bool skipped_adj(const SliceDesc& d) {
     return (d.skip != nullptr && *d.skip != 0) || (d.skip_adj != nullptr && *d.skip_adj != 0);
 }
 
+// Pointers read out of a descriptor are generic; these casts let the compiler use global
+// (vector) loads and, for wavefront-uniform addresses of read-only tables, scalar loads.
+typedef const __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ gfloat* as_global(const float* p) { return (gfloat*)p; }
+template <class T>
+__device__ __forceinline__ T cld(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
 // ------------------------------------------------------------------------ transpose
 // Item (slice, tile_x, tile_y, -): 32x32 tile of both maps through LDS. Also writes the
 // tile's sums of mu^2 and delta^2 (FP64) to part_reg[tile] for the regulariser.
@@ -70,69 +79,84 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // Item (slice, group, detector block, -). Thread (angle slot al, detector kl) follows one
 // ray. The block walks the stepped axis in strips of R rows; for each strip it stages the
 // window [lo, lo + win_w) of the interpolation axis (host-computed lo, conservative in FP64)
-// as interleaved (mu, delta) pairs in LDS; each sample is then one 16-byte LDS read of the
-// two neighbouring pairs and four FMAs.
-template <int A, int W, int R>
+// as interleaved (mu, delta) pairs in LDS, PW pairs per row; each sample is then one 16-byte
+// LDS read of the two neighbouring pairs and four FMAs. The next strip's window is loaded into
+// registers while the current one is consumed.
+template <int A, int W, int R, int PW>
 __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
-    extern __shared__ float2 win[];   // [R][pitch]
     constexpr int NT = A * W;
+    constexpr int SLOTS = R * PW / NT;
+    static_assert(SLOTS * NT == R * PW, "strip must tile the block");
+    static_assert(W % 64 == 0, "one angle per whole wavefront");
+    __shared__ float2 win[R * PW];
     const int tid = threadIdx.x;
-    const int al = tid / W, kl = tid % W;
+    const int al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
+    const int kl = tid % W;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
         if (skipped(d)) continue;
         const int n = d.n, grp = w.y, dblk = w.z;
-        const int a = d.groups[grp * A + al];
-        const int a0 = d.groups[grp * A];
-        const ProjAngle pa = d.pang[a >= 0 ? a : a0];
-        const int src = d.pang[a0].src;
+        const int a = cld(d.groups + grp * A + al);
+        const int a0 = cld(d.groups + grp * A);
+        const ProjAngle* pp = d.pang + (a >= 0 ? a : a0);
+        const double inv = cld(&pp->inv), base = cld(&pp->base), slope = cld(&pp->slope);
+        const float slope_f = cld(&pp->slope_f), wstep = cld(&pp->w);
+        const int src = cld(&d.pang[a0].src);
         const int k = dblk * W + kl;
         const int k_eff = k < d.n_det ? k : d.n_det - 1;
         const double t = (double)k_eff - 0.5 * (double)(d.n_det - 1);
-        const double ut0 = fma(t, pa.inv, pa.base);
-        const float* sm = src ? d.xT : d.x;
-        const float* sd = sm + (size_t)n * n;
+        const double ut0 = fma(t, inv, base);
+        const gfloat* sm = as_global(src ? d.xT : d.x);
+        const gfloat* sd = sm + (size_t)n * n;
         const int32_t* lo_tab = d.win_lo + ((size_t)grp * d.n_dblk + dblk) * d.n_strips;
-        const int pshift = d.win_shift, pitch = 1 << pshift, win_w = d.win_w;
-        double acc_m = 0.0, acc_d = 0.0;
-        for (int s = 0; s < d.n_strips; ++s) {
+        const int win_w = d.win_w, ns = d.n_strips;
+
+        float2 buf[SLOTS];
+        auto load_strip = [&](int s) {
+            const int lo = cld(lo_tab + s);
             const int p0 = s * R;
-            const int lo = lo_tab[s];
-            __syncthreads();
-            for (int e = tid; e < R * pitch; e += NT) {
-                const int r = e >> pshift, c = e & (pitch - 1);
-                if (c < win_w) {
-                    const int row = p0 + r, col = lo + c;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (row < n && col >= 0 && col < n) {
-                        const size_t o = (size_t)row * n + col;
-                        v.x = sm[o];
-                        v.y = sd[o];
-                    }
-                    win[e] = v;
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) {
+                const int e = tid + q * NT;
+                const int r = e / PW, c = e % PW;
+                const int row = p0 + r, col = lo + c;
+                float2 v = make_float2(0.f, 0.f);
+                if (c < win_w && row < n && (unsigned)col < (unsigned)n) {
+                    const unsigned o = (unsigned)row * (unsigned)n + (unsigned)col;
+                    v.x = sm[o];
+                    v.y = sd[o];
                 }
+                buf[q] = v;
             }
+        };
+        load_strip(0);
+        double acc_m = 0.0, acc_d = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            const int lo = cld(lo_tab + s);
+            __syncthreads();                           // previous strip fully consumed
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) win[tid + q * NT] = buf[q];
             __syncthreads();
+            if (s + 1 < ns) load_strip(s + 1);         // in flight during this strip
             // Ray origin for this strip split into an integer window column and a fraction
             // in [0, 1) (FP64), so the FP32 interpolation coordinate stays below ~R in
             // magnitude and keeps ~1e-6 absolute precision.
-            const double up0 = fma((double)p0, pa.slope, ut0);
+            const double up0 = fma((double)(s * R), slope, ut0);
             const double fl0 = floor(up0);
             const float uf = (float)(up0 - fl0);
             const int ioff = (int)fl0 - lo;                 // >= 1 by construction of lo
-            const int imin = -ioff, imax = win_w - 2 - ioff;
+            const float umin = (float)(-ioff);
+            const float umax = (float)(win_w - 2 - ioff) + 0.99f;
             const float2* rowp = win + ioff;
             float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float u = fmaf((float)r, pa.slope_f, uf);
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)r, slope_f, uf), umin, umax);
                 const float fl = floorf(u);
                 const float ph = u - fl;
-                const int i = min(max((int)fl, imin), imax);
-                const float2* q = rowp + i;
-                rowp += pitch;
+                const float2* q = rowp + r * PW + (int)fl;
                 const float2 v0 = q[0], v1 = q[1];
                 const float om = 1.f - ph;
                 c0 = fmaf(om, v0.x, c0);
@@ -144,8 +168,8 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             acc_d += (double)c1 + (double)c3;
         }
         if (a >= 0 && k < d.n_det) {
-            d.P[(size_t)a * d.n_det + k] = (float)(pa.w * acc_m);
-            d.P[((size_t)d.n_theta + a) * d.n_det + k] = (float)(pa.w * acc_d);
+            d.P[(size_t)a * d.n_det + k] = (float)(wstep * acc_m);
+            d.P[((size_t)d.n_theta + a) * d.n_det + k] = (float)(wstep * acc_d);
         }
     }
 }
@@ -231,26 +255,47 @@ __global__ __launch_bounds__(256) void k_cost_reduce(const SliceDesc* __restrict
 }
 
 // ------------------------------------------------------------------------ adjoint
-// Item (slice, tile_x, tile_y, -). Thread = voxel (il, jl) of a TX x TY tile. For each
-// chunk of AC angles the block stages, per angle, the kwin detector bins the tile can
-// reach (starting at lo = floor(min over the tile of u) - 1, computed in FP64) as
-// interleaved (G_mu, G_delta) pairs in LDS; a voxel then reads its two bins with one
-// 16-byte LDS read and applies the Joseph triangle weights. No atomics: each voxel's sum
-// is accumulated in a fixed angle order by one thread.
+// Item (slice, tile_x, tile_y, -). A TX x TY voxel tile; thread (il, jl) owns VPT voxels of
+// column il (rows jl + q TY/VPT). For each chunk of AC angles the block stages, per angle, the
+// kwin detector bins the tile can reach (starting at lo = floor(min over the tile of u) - 1,
+// FP64) as interleaved (G_mu, G_delta) pairs in LDS, plus the angle's FP32 constants; a voxel
+// then reads its two bins with one 16-byte LDS read and applies the Joseph triangle weights.
+// No atomics: each voxel's sum is accumulated in a fixed angle order by one thread, chunk
+// sums in FP64. The next chunk's bins are loaded into registers during the current chunk.
+constexpr int isqrt_ceil(int v) {
+    int s = 0;
+    while (s * s < v) ++s;
+    return s;
+}
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
-// Upper bound of the window width for a TX x TY tile: the span (TX-1)|cos| + (TY-1)|sin|
-// is at most TX + TY - 2, plus 4 bins of margin.
+// Window bound for a TX x TY tile: (TX-1)|cos| + (TY-1)|sin| <= sqrt((TX-1)^2 + (TY-1)^2),
+// plus 4 bins of margin.
 template <int TX, int TY>
-constexpr int adj_pitch_max() { return pow2_at_least(TX + TY + 2); }
+constexpr int adj_pitch_max() {
+    return pow2_at_least(isqrt_ceil((TX - 1) * (TX - 1) + (TY - 1) * (TY - 1)) + 4);
+}
 
-template <int TX, int TY, int AC>
-__global__ __launch_bounds__(TX* TY) void k_backproject(const SliceDesc* __restrict__ D,
-                                                        const Item* __restrict__ items,
-                                                        int n_items, int add_reg) {
-    __shared__ float2 gw[AC * adj_pitch_max<TX, TY>()];      // [AC][pitch]
-    __shared__ float offs[AC];
-    __shared__ int los[AC];
-    constexpr int NT = TX * TY;
+struct TileWin { int lo; float off; };
+__device__ __forceinline__ TileWin tile_window(const AdjAngle* q, int i0, int j0, int TX, int TY) {
+    const double cs = cld(&q->cs), sn = cld(&q->sn), cd = cld(&q->cd);
+    const double uc = fma((double)j0, sn, fma((double)i0, cs, cd));
+    const double umin = uc + fmin(0.0, (TX - 1) * cs) + fmin(0.0, (TY - 1) * sn);
+    const int lo = (int)floor(umin) - 1;
+    return TileWin{lo, (float)(uc - (double)lo)};
+}
+
+template <int TX, int TY, int AC, int VPT>
+__global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* __restrict__ D,
+                                                              const Item* __restrict__ items,
+                                                              int n_items, int add_reg) {
+    constexpr int NT = TX * TY / VPT;
+    constexpr int PK = adj_pitch_max<TX, TY>();
+    constexpr int SLOTS = AC * PK / NT;
+    constexpr int JS = TY / VPT;
+    static_assert(SLOTS * NT == AC * PK, "chunk must tile the block");
+    __shared__ float2 gw[AC * PK];
+    __shared__ float4 rec[AC];     // cs, sn, offset, 1/w
+    __shared__ float2 rec2[AC];    // 1/w^2, 1/w - 1/w^2
     const int tid = threadIdx.x;
     const int il = tid % TX, jl = tid / TX;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -259,104 +304,144 @@ __global__ __launch_bounds__(TX* TY) void k_backproject(const SliceDesc* __restr
         if (skipped_adj(d)) continue;
         const int n = d.n, nd = d.n_det, nth = d.n_theta;
         const int kwin = d.kwin;
-        int pshift = 0;
-        while ((1 << pshift) < kwin) ++pshift;
-        const int pitch = 1 << pshift;
         const int i0 = w.y * TX, j0 = w.z * TY;
-        const float* Gm = d.P;
-        const float* Gd = d.P + (size_t)nth * nd;
-        double acc_m = 0.0, acc_d = 0.0;
-        const float fil = (float)il, fjl = (float)jl;
-        for (int ab = 0; ab < nth; ab += AC) {
-            const int na = min(AC, nth - ab);
-            __syncthreads();
-            if (tid < na) {
-                const AdjAngle q = d.aang[ab + tid];
-                const double uc = fma((double)j0, q.sn, fma((double)i0, q.cs, q.cd));
-                const double umin = uc + fmin(0.0, (TX - 1) * q.cs) + fmin(0.0, (TY - 1) * q.sn);
-                const int lo = (int)floor(umin) - 1;
-                los[tid] = lo;
-                offs[tid] = (float)(uc - (double)lo);
-            }
-            __syncthreads();
-            for (int e = tid; e < AC * pitch; e += NT) {
-                const int aa = e >> pshift, b = e & (pitch - 1);
-                if (aa < na && b < kwin) {
-                    const int k = los[aa] + b;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (k >= 0 && k < nd) {
-                        const size_t o = (size_t)(ab + aa) * nd + k;
+        const gfloat* Gm = as_global(d.P);
+        const gfloat* Gd = Gm + (size_t)nth * nd;
+        const AdjAngle* aang = d.aang;
+        const int nchunks = (nth + AC - 1) / AC;
+
+        float2 buf[SLOTS];
+        auto load_chunk = [&](int ch) {
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) {
+                const int e = tid + q * NT;
+                const int aa = e / PK, b = e % PK;
+                const int a = ch * AC + aa;
+                float2 v = make_float2(0.f, 0.f);
+                if (a < nth && b < kwin) {
+                    const int k = tile_window(aang + a, i0, j0, TX, TY).lo + b;
+                    if ((unsigned)k < (unsigned)nd) {
+                        const unsigned o = (unsigned)a * (unsigned)nd + (unsigned)k;
                         v.x = Gm[o];
                         v.y = Gd[o];
                     }
-                    gw[e] = v;
                 }
+                buf[q] = v;
+            }
+        };
+        load_chunk(0);
+        double acc_m[VPT], acc_d[VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { acc_m[q] = 0.0; acc_d[q] = 0.0; }
+        const float fil = (float)il, fjl = (float)jl;
+        const float bmax = (float)(kwin - 2) + 0.99f;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            __syncthreads();                           // previous chunk fully consumed
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) gw[tid + q * NT] = buf[q];
+            if (tid < AC) {
+                const int a = ch * AC + tid;
+                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);
+                float2 r2 = make_float2(0.f, 0.f);
+                if (a < nth) {
+                    const AdjAngle* q = aang + a;
+                    const TileWin tw = tile_window(q, i0, j0, TX, TY);
+                    r1 = make_float4(cld(&q->cs_f), cld(&q->sn_f), tw.off, cld(&q->iw));
+                    r2 = make_float2(cld(&q->iw2), cld(&q->iwm));
+                }
+                rec[tid] = r1;
+                rec2[tid] = r2;
             }
             __syncthreads();
-            float am = 0.f, ad = 0.f;
-            for (int aa = 0; aa < na; ++aa) {
-                const AdjAngle q = d.aang[ab + aa];
-                const float u = fmaf(fil, q.cs_f, fmaf(fjl, q.sn_f, offs[aa]));
-                int b = (int)u;
-                const float f = u - (float)b;
-                b = min(max(b, 0), kwin - 2);
-                const float w0 = fmaxf(0.f, fmaf(-f, q.iw2, q.iw));
-                const float w1 = fmaxf(0.f, fmaf(f, q.iw2, q.iwm));
-                const float2* p = gw + (aa << pshift) + b;
-                const float2 g0 = p[0], g1 = p[1];
-                am = fmaf(w0, g0.x, fmaf(w1, g1.x, am));
-                ad = fmaf(w0, g0.y, fmaf(w1, g1.y, ad));
+            if (ch + 1 < nchunks) load_chunk(ch + 1);  // in flight during this chunk
+            float am[VPT], ad[VPT];
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { am[q] = 0.f; ad[q] = 0.f; }
+#pragma unroll 4
+            for (int aa = 0; aa < AC; ++aa) {
+                const float4 r1 = rec[aa];
+                const float2 r2 = rec2[aa];
+                const float u0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
+                const float2* row = gw + aa * PK;
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const float uq = q == 0 ? u0 : fmaf((float)(q * JS), r1.y, u0);
+                    const float u = __builtin_amdgcn_fmed3f(uq, 0.f, bmax);
+                    const float fl = floorf(u);
+                    const float f = u - fl;
+                    const float w0 = fmaxf(0.f, fmaf(-f, r2.x, r1.w));
+                    const float w1 = fmaxf(0.f, fmaf(f, r2.x, r2.y));
+                    const float2* p = row + (int)fl;
+                    const float2 g0 = p[0], g1 = p[1];
+                    am[q] = fmaf(w0, g0.x, fmaf(w1, g1.x, am[q]));
+                    ad[q] = fmaf(w0, g0.y, fmaf(w1, g1.y, ad[q]));
+                }
             }
-            acc_m += (double)am;          // chunk sums combined in FP64
-            acc_d += (double)ad;
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {        // chunk sums combined in FP64
+                acc_m[q] += (double)am[q];
+                acc_d[q] += (double)ad[q];
+            }
         }
-        const int i = i0 + il, j = j0 + jl;
-        if (i < n && j < n) {
-            const size_t o = (size_t)j * n + i;
-            const size_t o2 = o + (size_t)n * n;
-            if (add_reg) {
-                acc_m = fma(d.reg_mu, (double)d.x[o], acc_m);
-                acc_d = fma(d.reg_de, (double)d.x[o2], acc_d);
+        const int i = i0 + il;
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int j = j0 + jl + q * JS;
+            if (i < n && j < n) {
+                const size_t o = (size_t)j * n + i;
+                const size_t o2 = o + (size_t)n * n;
+                double vm = acc_m[q], vd = acc_d[q];
+                if (add_reg) {
+                    vm = fma(d.reg_mu, (double)d.x[o], vm);
+                    vd = fma(d.reg_de, (double)d.x[o2], vd);
+                }
+                d.g[o] = (float)vm;
+                d.g[o2] = (float)vd;
             }
-            d.g[o] = (float)acc_m;
-            d.g[o2] = (float)acc_d;
         }
     }
 }
 
 // ------------------------------------------------------------------------ registry
-// Projector variants (A angles x W detectors threads, R rows per strip).
+// Projector variants (A angles x W detectors threads, R rows per strip, PW staged pairs per row).
 #define EIT_PROJ_VARIANTS(X) \
-    X(0, 8, 64, 16)          \
-    X(1, 4, 64, 16)          \
-    X(2, 16, 64, 8)          \
-    X(3, 8, 64, 8)           \
-    X(4, 4, 128, 16)         \
-    X(5, 2, 128, 32)
+    X(0, 8, 64, 16, 256)     \
+    X(1, 4, 64, 16, 128)     \
+    X(2, 16, 64, 8, 256)     \
+    X(3, 8, 64, 8, 256)      \
+    X(4, 4, 128, 16, 256)    \
+    X(5, 8, 64, 32, 256)     \
+    X(6, 16, 64, 16, 256)    \
+    X(7, 2, 64, 16, 128)     \
+    X(8, 1, 64, 16, 128)
 
+// Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
-    X(0, 16, 16, 32)        \
-    X(1, 32, 8, 32)         \
-    X(2, 16, 16, 64)        \
-    X(3, 32, 16, 32)        \
-    X(4, 16, 32, 32)
+    X(0, 16, 16, 32, 1)     \
+    X(1, 16, 16, 32, 2)     \
+    X(2, 32, 16, 32, 2)     \
+    X(3, 32, 32, 32, 4)     \
+    X(4, 16, 32, 32, 2)     \
+    X(5, 16, 16, 64, 1)     \
+    X(6, 32, 32, 16, 4)     \
+    X(7, 32, 16, 32, 4)
 
 int proj_variant_count() {
     int c = 0;
-#define X(id, A, W, R) ++c;
+#define X(id, A, W, R, PW) ++c;
     EIT_PROJ_VARIANTS(X)
 #undef X
     return c;
 }
 ProjTile proj_variant(int v) {
-#define X(id, A, W, R) \
-    if (v == id) return ProjTile{A, W, R};
+#define X(id, A, W, R, PW) \
+    if (v == id) return ProjTile{A, W, R, PW};
     EIT_PROJ_VARIANTS(X)
 #undef X
     return ProjTile{0, 0, 0};
 }
 int adj_pitch_limit(int v) {
-#define X(id, TX, TY, AC) \
+#define X(id, TX, TY, AC, VPT) \
     if (v == id) return adj_pitch_max<TX, TY>();
     EIT_ADJ_VARIANTS(X)
 #undef X
@@ -364,14 +449,14 @@ int adj_pitch_limit(int v) {
 }
 int adj_variant_count() {
     int c = 0;
-#define X(id, TX, TY, AC) ++c;
+#define X(id, TX, TY, AC, VPT) ++c;
     EIT_ADJ_VARIANTS(X)
 #undef X
     return c;
 }
 AdjTile adj_variant(int v) {
-#define X(id, TX, TY, AC) \
-    if (v == id) return AdjTile{TX, TY, AC};
+#define X(id, TX, TY, AC, VPT) \
+    if (v == id) return AdjTile{TX, TY, AC, VPT};
     EIT_ADJ_VARIANTS(X)
 #undef X
     return AdjTile{0, 0, 0};
@@ -387,9 +472,10 @@ hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, 
 hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, int n_items,
                           int grid, size_t lds, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, A, W, R)                                                           \
+#define X(id, A, W, R, PW)                                                       \
     if (variant == id) {                                                         \
-        k_project<A, W, R><<<grid, A * W, lds, s>>>(D, items, n_items);          \
+        (void)lds;                                                               \
+        k_project<A, W, R, PW><<<grid, A * W, 0, s>>>(D, items, n_items);        \
         return hipGetLastError();                                                \
     }
     EIT_PROJ_VARIANTS(X)
@@ -412,10 +498,11 @@ hipError_t launch_cost_reduce(const SliceDesc* D, int n_slices, hipStream_t s) {
 hipError_t launch_backproject(int variant, const SliceDesc* D, const Item* items, int n_items,
                               int grid, int add_reg, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, TX, TY, AC)                                                              \
-    if (variant == id) {                                                               \
-        k_backproject<TX, TY, AC><<<grid, TX * TY, 0, s>>>(D, items, n_items, add_reg); \
-        return hipGetLastError();                                                      \
+#define X(id, TX, TY, AC, VPT)                                                            \
+    if (variant == id) {                                                                  \
+        k_backproject<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(D, items, n_items,  \
+                                                                     add_reg);            \
+        return hipGetLastError();                                                         \
     }
     EIT_ADJ_VARIANTS(X)
 #undef X

@@ -93,13 +93,15 @@ def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, tables
 
 
 def variants(kind: int):
-    """List of (a, b, c) tile shapes of the compiled projector (0) or adjoint (1) variants."""
-    n = L.lib().eit_variant_info(kind, -1, None, None, None)
+    """Tile shapes of the compiled variants: projector (kind 0) as (angles per group,
+    detectors per block, rows per strip); adjoint (kind 1) as (tile x, tile y, angles per
+    chunk, voxels per thread)."""
+    n = L.lib().eit_variant_info(kind, -1, None, None, None, None)
     out = []
     for v in range(n):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        L.lib().eit_variant_info(kind, v, C.byref(a), C.byref(b), C.byref(c))
-        out.append((a.value, b.value, c.value))
+        a, b, c, e = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.lib().eit_variant_info(kind, v, C.byref(a), C.byref(b), C.byref(c), C.byref(e))
+        out.append((a.value, b.value, c.value) if kind == 0 else (a.value, b.value, c.value, e.value))
     return out
 
 
@@ -206,7 +208,8 @@ class Plan:
         opts = L.Opts(iters, m, max_ls, 1 if use_graph else 0, lam, mu_scale, delta_scale,
                       tol_rel_step, c1, 1 if profile else 0, 0)
         rep = L.Report()
-        ws = self.workspace(L.EIT_OP_RECONSTRUCT, m) if ws is None else ws
+        # sized with a valid memory so that the library itself validates `m`
+        ws = self.workspace(L.EIT_OP_RECONSTRUCT, min(max(m, 1), 20)) if ws is None else ws
         rc = L.lib().eit_reconstruct(self.handle, _ptr(s_exp), C.byref(opts), _ptr(x), _ptr(hist),
                                      C.byref(rep), _ptr(ws), ws.numel(), _stream())
         report = {f: getattr(rep, f) for f, _ in L.Report._fields_ if f not in ("phase_ms", "pad")}

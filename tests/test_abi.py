@@ -94,8 +94,8 @@ def test_variant_registry():
     assert len(pv) >= 3 and len(av) >= 3
     for a, w, r in pv:
         assert a * w <= 1024 and w % 64 == 0
-    for tx, ty, ac in av:
-        assert tx * ty <= 1024 and (tx * ty) % 64 == 0
+    for tx, ty, ac, vpt in av:
+        assert tx * ty // vpt <= 1024 and (tx * ty // vpt) % 64 == 0
 
 
 def f32(v):
@@ -108,7 +108,13 @@ def fmaf(a, b, c):
 
 
 def check_projector_bounds(g, pv):
-    info = ops.inspect(g, proj_variant=pv, tables=True)
+    """Emulates the projector's per-strip origin (FP64 floor split) and per-row FP32 FMA, and
+    checks that the LDS column floor(u) + ioff stays in [0, win_w - 2] with no clamping."""
+    try:
+        info = ops.inspect(g, proj_variant=pv, tables=True)
+    except L.EitError as e:
+        assert e.code == L.EIT_ERR_SHAPE      # window wider than this variant's pitch
+        return False
     A, W, R = info["proj_a"], info["proj_w"], info["proj_r"]
     assert info["proj_lds_bytes"] <= 64 * 1024
     assert info["win_pitch"] >= info["win_w"]
@@ -116,7 +122,6 @@ def check_projector_bounds(g, pv):
     ng, nb, ns = wl.shape
     nd = g.n_det
     a_eff = np.where(groups >= 0, groups, groups[:, :1])                     # [ng, A]
-    # rows of each group share a source (all angles of a group come from one class)
     src = pa[a_eff, 5]
     assert np.all(src == src[:, :1])
     kl = np.array([0, W - 1])
@@ -129,20 +134,26 @@ def check_projector_bounds(g, pv):
     slope_f = pa[a_eff, 3][:, None, :, None, None]
     ut0 = t[None, :, None, :] * inv + base                                   # [ng,nb,A,2]
     p0 = (np.arange(ns) * R).astype(np.float64)
-    lo = wl.astype(np.float64)                                               # [ng,nb,ns]
-    ur = f32(ut0[..., None] + p0[None, None, None, None, :] * slope
-             - lo[:, :, None, None, :])                                       # [ng,nb,A,2,ns]
+    lo = wl.astype(np.float64)[:, :, None, None, :]                          # [ng,nb,1,1,ns]
+    up0 = ut0[..., None] + p0 * slope                                         # [ng,nb,A,2,ns]
+    fl0 = np.floor(up0)
+    uf = f32(up0 - fl0)
+    ioff = fl0 - lo
+    assert ioff.min() >= 1
     for r in (0, R - 1):
-        u = fmaf(float(r), slope_f, ur)
-        i = np.trunc(u)
-        assert i.min() >= 0, (pv, i.min())
-        assert i.max() <= info["win_w"] - 2, (pv, i.max(), info["win_w"])
+        col = np.floor(fmaf(float(r), slope_f, uf)) + ioff
+        assert col.min() >= 0, (pv, col.min())
+        assert col.max() <= info["win_w"] - 2, (pv, col.max(), info["win_w"])
+    return True
 
 
-def check_adjoint_bounds(g, av):
+def check_adjoint_bounds(g, av, vpt):
+    """Emulates the adjoint's tile origin (FP64) and per-voxel FP32 FMAs (including the
+    row offsets of a thread's extra voxels) and checks bins stay in [0, kwin - 2]."""
     info = ops.inspect(g, adj_variant=av, tables=True)
     TX, TY, kwin = info["adj_tx"], info["adj_ty"], info["kwin"]
     assert kwin <= info["kwin_pitch_limit"]
+    JS = TY // vpt
     aa = info["adj_angles"]
     cs, sn, cd, csf, snf = (aa[:, q] for q in range(5))
     i0 = (np.arange(info["n_tx"]) * TX).astype(np.float64)
@@ -155,11 +166,13 @@ def check_adjoint_bounds(g, av):
     lo = np.floor(umin) - 1
     offs = f32(uc - lo)
     for il in (0, TX - 1):
-        for jl in (0, TY - 1):
-            u = fmaf(float(il), csf, fmaf(float(jl), snf, offs))
-            b = np.trunc(u)
-            assert b.min() >= 0, (av, b.min())
-            assert b.max() <= kwin - 2, (av, b.max(), kwin)
+        for jl in (0, JS - 1):
+            u0 = fmaf(float(il), csf, fmaf(float(jl), snf, offs))
+            for q in (0, vpt - 1):
+                u = u0 if q == 0 else fmaf(float(q * JS), snf, u0)
+                b = np.floor(u)
+                assert b.min() >= 0, (av, b.min())
+                assert b.max() <= kwin - 2, (av, b.max(), kwin)
 
 
 SHAPES = [configs.SMALL_64, configs.SLICE_512, configs.SLICE_1024,
@@ -169,23 +182,23 @@ SHAPES = [configs.SMALL_64, configs.SLICE_512, configs.SLICE_1024,
           configs.SliceConfig(n=100, n_theta=7, n_det=70, n_mask=1)]
 
 
+def _all_variants(g):
+    ok = [check_projector_bounds(g, pv) for pv in range(len(ops.variants(0)))]
+    assert ok[ops.inspect(g)["proj_variant"]]        # the default variant must apply
+    for av, (tx, ty, ac, vpt) in enumerate(ops.variants(1)):
+        check_adjoint_bounds(g, av, vpt)
+
+
 @pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: f"{c.n}x{c.n_theta}x{c.n_det}")
 def test_lds_indices_in_bounds(cfg):
-    g = geo_for(cfg)
-    for pv in range(len(ops.variants(0))):
-        check_projector_bounds(g, pv)
-    for av in range(len(ops.variants(1))):
-        check_adjoint_bounds(g, av)
+    _all_variants(geo_for(cfg))
 
 
 def test_irregular_angles_in_bounds():
     rng = np.random.default_rng(0)
     g = geo_for(configs.SliceConfig(n=96, n_theta=50, n_det=110, n_mask=4))
     g.theta = np.sort(rng.uniform(-np.pi, 2 * np.pi, g.n_theta))
-    for pv in range(len(ops.variants(0))):
-        check_projector_bounds(g, pv)
-    for av in range(len(ops.variants(1))):
-        check_adjoint_bounds(g, av)
+    _all_variants(g)
 
 
 def test_row_flags_match_oracle_rule():
