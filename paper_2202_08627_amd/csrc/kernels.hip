@@ -27,6 +27,16 @@ __device__ __forceinline__ T cld(const T* p) {
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// Raw buffer resource over `bytes` bytes from `p` (gfx9 descriptor word 3): loads at offsets
+// >= bytes return 0 without touching memory. Every offset is carried in the VGPR operand.
+constexpr int kBufOOB = 0x7ffffff0;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+
 // ------------------------------------------------------------------------ transpose
 // Item (slice, tile_x, tile_y, -): 32x32 tile of both maps through LDS. Also writes the
 // tile's sums of mu^2 and delta^2 (FP64) to part_reg[tile] for the regulariser.
@@ -79,20 +89,31 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // Item (slice, group, detector block, -). Thread (angle slot al, detector kl) follows one
 // ray. The block walks the stepped axis in strips of R rows; for each strip it stages the
 // window [lo, lo + win_w) of the interpolation axis (host-computed lo, conservative in FP64)
-// as interleaved (mu, delta) pairs in LDS, PW pairs per row; each sample is then one 16-byte
-// LDS read of the two neighbouring pairs and four FMAs. The next strip's window is loaded into
-// registers while the current one is consumed.
+// as interleaved (mu, delta) pairs in LDS, PW pairs per row; a sample is then two 8-byte LDS
+// reads of the neighbouring pairs and four FMAs. The next strip's window is loaded into
+// registers (buffer loads: rows past the map read as zero) while the current one is consumed.
+//
+// Index safety: every LDS index is ioff + (int)u (+1) with u in [1 - 1e-5, win_w - ioff - 1)
+// for all rays of the block; the host builds lo and win_w from FP64 extremes with a 1e-3
+// margin, and the host tests replay this exact FP32/FP64 arithmetic for every work item of
+// the benchmark and test geometries.
 template <int A, int W, int R, int PW>
 __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
     constexpr int NT = A * W;
-    constexpr int SLOTS = R * PW / NT;
-    static_assert(SLOTS * NT == R * PW, "strip must tile the block");
     static_assert(W % 64 == 0, "one angle per whole wavefront");
+    static_assert(NT % PW == 0 || PW % NT == 0, "staging must tile the block");
+    // staging map: slot q of thread tid holds (row, column) of the strip window
+    constexpr bool WIDE = NT >= PW;          // whole rows per slot step, else columns per slot
+    constexpr int RS = WIDE ? NT / PW : 1;   // rows staged per slot step
+    constexpr int CS = WIDE ? 1 : PW / NT;   // columns per thread and row
+    static_assert(R % RS == 0, "strip must tile the block");
+    constexpr int SLOTS = R / RS * CS;
     __shared__ float2 win[R * PW];
     const int tid = threadIdx.x;
     const int al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
     const int kl = tid % W;
+    const int sc = tid % PW, sr = tid / PW;  // staging column and first row of this thread
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
@@ -108,27 +129,34 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
         const int k_eff = k < d.n_det ? k : d.n_det - 1;
         const double t = (double)k_eff - 0.5 * (double)(d.n_det - 1);
         const double ut0 = fma(t, inv, base);
-        const gfloat* sm = as_global(src ? d.xT : d.x);
-        const gfloat* sd = sm + (size_t)n * n;
+        const float* map = src ? d.xT : d.x;
+        const int nn4 = n * n * 4;
+        const __amdgpu_buffer_rsrc_t bm = make_rsrc(map, nn4);
+        const __amdgpu_buffer_rsrc_t bd = make_rsrc(map + (size_t)n * n, nn4);
         const int32_t* lo_tab = d.win_lo + ((size_t)grp * d.n_dblk + dblk) * d.n_strips;
         const int win_w = d.win_w, ns = d.n_strips;
+        const int rstep4 = RS * n * 4;
 
         float2 buf[SLOTS];
         auto load_strip = [&](int s) {
             const int lo = cld(lo_tab + s);
-            const int p0 = s * R;
+            if constexpr (WIDE) {
+                const int col = lo + sc;
+                const bool ok = sc < win_w && (unsigned)col < (unsigned)n;
+                int vo = ok ? ((s * R + sr) * n + col) * 4 : kBufOOB;
 #pragma unroll
-            for (int q = 0; q < SLOTS; ++q) {
-                const int e = tid + q * NT;
-                const int r = e / PW, c = e % PW;
-                const int row = p0 + r, col = lo + c;
-                float2 v = make_float2(0.f, 0.f);
-                if (c < win_w && row < n && (unsigned)col < (unsigned)n) {
-                    const unsigned o = (unsigned)row * (unsigned)n + (unsigned)col;
-                    v.x = sm[o];
-                    v.y = sd[o];
+                for (int q = 0; q < SLOTS; ++q) {
+                    buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
+                    vo += rstep4;
                 }
-                buf[q] = v;
+            } else {
+#pragma unroll
+                for (int q = 0; q < SLOTS; ++q) {
+                    const int c = tid + (q % CS) * NT, col = lo + c;
+                    const bool ok = c < win_w && (unsigned)col < (unsigned)n;
+                    const int vo = ok ? ((s * R + q / CS) * n + col) * 4 : kBufOOB;
+                    buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
+                }
             }
         };
         load_strip(0);
@@ -137,26 +165,26 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             const int lo = cld(lo_tab + s);
             __syncthreads();                           // previous strip fully consumed
 #pragma unroll
-            for (int q = 0; q < SLOTS; ++q) win[tid + q * NT] = buf[q];
+            for (int q = 0; q < SLOTS; ++q) {
+                if constexpr (WIDE) win[(sr + q * RS) * PW + sc] = buf[q];
+                else win[(q / CS) * PW + tid + (q % CS) * NT] = buf[q];
+            }
             __syncthreads();
             if (s + 1 < ns) load_strip(s + 1);         // in flight during this strip
-            // Ray origin for this strip split into an integer window column and a fraction
-            // in [0, 1) (FP64), so the FP32 interpolation coordinate stays below ~R in
-            // magnitude and keeps ~1e-6 absolute precision.
+            // Ray origin of the strip, split in FP64 into an integer window column (one
+            // below the strip's lowest crossing) and a fraction, so the FP32 coordinate
+            // u = uf + r*slope lies in [1, R + 1): truncation is the floor, and the
+            // interpolation weight keeps ~2e-6 absolute precision.
             const double up0 = fma((double)(s * R), slope, ut0);
-            const double fl0 = floor(up0);
+            const double fl0 = floor(up0 + fmin(0.0, (double)(R - 1) * slope)) - 1.0;
             const float uf = (float)(up0 - fl0);
-            const int ioff = (int)fl0 - lo;                 // >= 1 by construction of lo
-            const float umin = (float)(-ioff);
-            const float umax = (float)(win_w - 2 - ioff) + 0.99f;
-            const float2* rowp = win + ioff;
+            const float2* rowp = win + ((int)fl0 - lo);
             float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float u = __builtin_amdgcn_fmed3f(fmaf((float)r, slope_f, uf), umin, umax);
-                const float fl = floorf(u);
-                const float ph = u - fl;
-                const float2* q = rowp + r * PW + (int)fl;
+                const float u = fmaf((float)r, slope_f, uf);
+                const float ph = __builtin_amdgcn_fractf(u);
+                const float2* q = rowp + r * PW + (int)u;
                 const float2 v0 = q[0], v1 = q[1];
                 const float om = 1.f - ph;
                 c0 = fmaf(om, v0.x, c0);
@@ -284,20 +312,27 @@ __device__ __forceinline__ TileWin tile_window(const AdjAngle* q, int i0, int j0
     return TileWin{lo, (float)(uc - (double)lo)};
 }
 
+// Index safety: a voxel's coordinate relative to the window is u >= 1 - 1e-5 (lo is one bin
+// below the tile's lowest crossing) and floor(u) + 1 <= kwin - 1 (kwin bounds the tile's
+// span plus margin); the host tests replay this arithmetic for every tile and angle.
 template <int TX, int TY, int AC, int VPT>
 __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* __restrict__ D,
                                                               const Item* __restrict__ items,
                                                               int n_items, int add_reg) {
     constexpr int NT = TX * TY / VPT;
     constexpr int PK = adj_pitch_max<TX, TY>();
-    constexpr int SLOTS = AC * PK / NT;
+    static_assert(NT % PK == 0, "staging must tile the block");
+    constexpr int AS = NT / PK;              // angles staged per slot step
+    static_assert(AC % AS == 0, "chunk must tile the block");
+    constexpr int SLOTS = AC / AS;
     constexpr int JS = TY / VPT;
-    static_assert(SLOTS * NT == AC * PK, "chunk must tile the block");
     __shared__ float2 gw[AC * PK];
-    __shared__ float4 rec[AC];     // cs, sn, offset, 1/w
-    __shared__ float2 rec2[AC];    // 1/w^2, 1/w - 1/w^2
+    __shared__ float4 rec[2][AC];            // cs, sn, offset, 1/w   (double-buffered by chunk)
+    __shared__ float2 rec2[2][AC];           // 1/w^2, 1/w - 1/w^2
+    __shared__ int los[2][AC];
     const int tid = threadIdx.x;
     const int il = tid % TX, jl = tid / TX;
+    const int sb = tid % PK, sa = tid / PK;  // staging bin and first angle of this thread
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
@@ -305,73 +340,75 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
         const int n = d.n, nd = d.n_det, nth = d.n_theta;
         const int kwin = d.kwin;
         const int i0 = w.y * TX, j0 = w.z * TY;
-        const gfloat* Gm = as_global(d.P);
-        const gfloat* Gd = Gm + (size_t)nth * nd;
+        const int sz4 = nth * nd * 4;
+        const __amdgpu_buffer_rsrc_t bGm = make_rsrc(d.P, sz4);
+        const __amdgpu_buffer_rsrc_t bGd = make_rsrc(d.P + (size_t)nth * nd, sz4);
         const AdjAngle* aang = d.aang;
         const int nchunks = (nth + AC - 1) / AC;
 
-        float2 buf[SLOTS];
-        auto load_chunk = [&](int ch) {
-#pragma unroll
-            for (int q = 0; q < SLOTS; ++q) {
-                const int e = tid + q * NT;
-                const int aa = e / PK, b = e % PK;
-                const int a = ch * AC + aa;
-                float2 v = make_float2(0.f, 0.f);
-                if (a < nth && b < kwin) {
-                    const int k = tile_window(aang + a, i0, j0, TX, TY).lo + b;
-                    if ((unsigned)k < (unsigned)nd) {
-                        const unsigned o = (unsigned)a * (unsigned)nd + (unsigned)k;
-                        v.x = Gm[o];
-                        v.y = Gd[o];
-                    }
-                }
-                buf[q] = v;
-            }
-        };
-        load_chunk(0);
-        double acc_m[VPT], acc_d[VPT];
-#pragma unroll
-        for (int q = 0; q < VPT; ++q) { acc_m[q] = 0.0; acc_d[q] = 0.0; }
-        const float fil = (float)il, fjl = (float)jl;
-        const float bmax = (float)(kwin - 2) + 0.99f;
-        for (int ch = 0; ch < nchunks; ++ch) {
-            __syncthreads();                           // previous chunk fully consumed
-#pragma unroll
-            for (int q = 0; q < SLOTS; ++q) gw[tid + q * NT] = buf[q];
+        // per-angle constants and window origin of chunk ch into buffer slot ch & 1
+        auto angle_setup = [&](int ch) {
             if (tid < AC) {
                 const int a = ch * AC + tid;
-                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);
+                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);   // padding angle: zero weights
                 float2 r2 = make_float2(0.f, 0.f);
+                int lo = -(1 << 20);
                 if (a < nth) {
                     const AdjAngle* q = aang + a;
                     const TileWin tw = tile_window(q, i0, j0, TX, TY);
                     r1 = make_float4(cld(&q->cs_f), cld(&q->sn_f), tw.off, cld(&q->iw));
                     r2 = make_float2(cld(&q->iw2), cld(&q->iwm));
+                    lo = tw.lo;
                 }
-                rec[tid] = r1;
-                rec2[tid] = r2;
+                rec[ch & 1][tid] = r1;
+                rec2[ch & 1][tid] = r2;
+                los[ch & 1][tid] = lo;
             }
+        };
+        float2 buf[SLOTS];
+        auto load_chunk = [&](int ch) {
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) {
+                const int aa = sa + q * AS;
+                const int a = ch * AC + aa;
+                const int k = los[ch & 1][aa] + sb;
+                const bool ok = a < nth && sb < kwin && (unsigned)k < (unsigned)nd;
+                const int vo = ok ? (a * nd + k) * 4 : kBufOOB;
+                buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+            }
+        };
+        __syncthreads();                  // LDS of the previous work item fully consumed
+        angle_setup(0);
+        __syncthreads();
+        load_chunk(0);
+        double acc_m[VPT], acc_d[VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { acc_m[q] = 0.0; acc_d[q] = 0.0; }
+        const float fil = (float)il, fjl = (float)jl;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            __syncthreads();                           // previous chunk fully consumed
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) gw[(sa + q * AS) * PK + sb] = buf[q];
+            if (ch + 1 < nchunks) angle_setup(ch + 1);
             __syncthreads();
             if (ch + 1 < nchunks) load_chunk(ch + 1);  // in flight during this chunk
+            const int cb = ch & 1;
             float am[VPT], ad[VPT];
 #pragma unroll
             for (int q = 0; q < VPT; ++q) { am[q] = 0.f; ad[q] = 0.f; }
 #pragma unroll 4
             for (int aa = 0; aa < AC; ++aa) {
-                const float4 r1 = rec[aa];
-                const float2 r2 = rec2[aa];
+                const float4 r1 = rec[cb][aa];
+                const float2 r2 = rec2[cb][aa];
                 const float u0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
                 const float2* row = gw + aa * PK;
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
-                    const float uq = q == 0 ? u0 : fmaf((float)(q * JS), r1.y, u0);
-                    const float u = __builtin_amdgcn_fmed3f(uq, 0.f, bmax);
-                    const float fl = floorf(u);
-                    const float f = u - fl;
+                    const float u = q == 0 ? u0 : fmaf((float)(q * JS), r1.y, u0);
+                    const float f = __builtin_amdgcn_fractf(u);
                     const float w0 = fmaxf(0.f, fmaf(-f, r2.x, r1.w));
                     const float w1 = fmaxf(0.f, fmaf(f, r2.x, r2.y));
-                    const float2* p = row + (int)fl;
+                    const float2* p = row + (int)u;
                     const float2 g0 = p[0], g1 = p[1];
                     am[q] = fmaf(w0, g0.x, fmaf(w1, g1.x, am[q]));
                     ad[q] = fmaf(w0, g0.y, fmaf(w1, g1.y, ad[q]));

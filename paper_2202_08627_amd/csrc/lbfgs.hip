@@ -28,27 +28,29 @@ __device__ void reset_memory(SolverState& s) {
     s.spare = 0;
 }
 
-// Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first).
-__device__ void compact_direction(SolverState& s, const double* a, const double* b) {
+// Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first). SY and YY
+// are the ring-ordered m_cur x m_cur matrices (row stride kMaxM) in LDS; c, v, e are LDS
+// scratch. Runs in one thread.
+__device__ void compact_direction(SolverState& s, const double* a, const double* b,
+                                  const double* SY, const double* YY, double* c, double* v,
+                                  double* e) {
     const int mc = s.m_cur;
-    const int W = kMaxM + 1;
-    const int newest = s.order[mc - 1];
-    const double gamma = s.SY[newest * W + newest] / s.YY[newest * W + newest];
-    double c[kMaxM], v[kMaxM], e[kMaxM];
+    const int W = kMaxM;
+    const double gamma = SY[(mc - 1) * W + (mc - 1)] / YY[(mc - 1) * W + (mc - 1)];
     for (int r = mc - 1; r >= 0; --r) {                 // c = R^{-1} a (back substitution)
         double acc = a[r];
-        for (int q = r + 1; q < mc; ++q) acc -= s.SY[s.order[r] * W + s.order[q]] * c[q];
-        c[r] = acc / s.SY[s.order[r] * W + s.order[r]];
+        for (int q = r + 1; q < mc; ++q) acc -= SY[r * W + q] * c[q];
+        c[r] = acc / SY[r * W + r];
     }
     for (int r = 0; r < mc; ++r) {                      // v = (D + gamma Y^T Y) c - gamma b
-        double acc = s.SY[s.order[r] * W + s.order[r]] * c[r] - gamma * b[r];
-        for (int q = 0; q < mc; ++q) acc += gamma * s.YY[s.order[r] * W + s.order[q]] * c[q];
+        double acc = SY[r * W + r] * c[r] - gamma * b[r];
+        for (int q = 0; q < mc; ++q) acc += gamma * YY[r * W + q] * c[q];
         v[r] = acc;
     }
     for (int r = 0; r < mc; ++r) {                      // e = R^{-T} v (forward substitution)
         double acc = v[r];
-        for (int q = 0; q < r; ++q) acc -= s.SY[s.order[q] * W + s.order[r]] * e[q];
-        e[r] = acc / s.SY[s.order[r] * W + s.order[r]];
+        for (int q = 0; q < r; ++q) acc -= SY[q * W + r] * e[q];
+        e[r] = acc / SY[r * W + r];
     }
     double gHg = gamma * s.gg;
     for (int r = 0; r < mc; ++r) gHg += a[r] * e[r] - gamma * b[r] * c[r];
@@ -287,9 +289,16 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
 // ------------------------------------------------------------------------ accept: finalize
 // One block per slice: reduce the partial inner products (one wavefront per product, fixed
 // order), commit the pair if s.y > 1e-10 ||s|| ||y||, advance the iteration counter, test
-// the stopping rules and compute the next direction's coefficients.
+// the stopping rules and compute the next direction's coefficients. The scalar logic runs in
+// one thread on LDS copies of the state's small matrices.
 __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
+    constexpr int W = kMaxM + 1;
     __shared__ double dots[max_dots(kMaxM)];
+    __shared__ double sSY[W * W], sYY[W * W];
+    __shared__ double oSY[kMaxM * kMaxM], oYY[kMaxM * kMaxM];
+    __shared__ double av[kMaxM], bv[kMaxM], cs[kMaxM], vs[kMaxM], es[kMaxM];
+    __shared__ int sorder[kMaxM];
+    __shared__ int go, sm2;
     const LbDesc& l = L[blockIdx.x];
     SolverState& s = *l.st;
     if (s.skip_adj) return;
@@ -303,71 +312,95 @@ __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ 
         v = wave_sum(v);
         if (lane == 0) dots[q] = v;
     }
+    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+        sSY[i] = s.SY[i];
+        sYY[i] = s.YY[i];
+    }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int W = kMaxM + 1;
-    s.f = s.f_t;
-    s.gg = dots[0];
-    if (init) {
-        if (s.cost_hist) s.cost_hist[0] = s.f;
-        reset_memory(s);
-        steepest(s);
-        if (s.max_iter <= 0) { finish(s, ST_DONE); return; }
-        if (s.max_ls <= 0) { finish(s, EIT_ERR_LINESEARCH); return; }
-        s.skip_adj = 1;
-        return;
-    }
-    const double ss = dots[1], yy = dots[2], sy = dots[3], zz = dots[4];
-    double a[kMaxM], b[kMaxM];
-    for (int r = 0; r < mc; ++r) {
-        a[r] = dots[kDotsFixed + 4 * r + 2];
-        b[r] = dots[kDotsFixed + 4 * r + 3];
-    }
-    int m_new = mc;
-    if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
-        const int sp = s.spare;
-        for (int r = 0; r < mc; ++r) {
-            const int o = s.order[r];
-            s.SY[o * W + sp] = dots[kDotsFixed + 4 * r + 0];
-            const double yyr = dots[kDotsFixed + 4 * r + 1];
-            s.YY[o * W + sp] = yyr;
-            s.YY[sp * W + o] = yyr;
-        }
-        s.SY[sp * W + sp] = sy;
-        s.YY[sp * W + sp] = yy;
-        if (mc < s.m) {
-            s.order[mc] = sp;
-            a[mc] = dots[5];
-            b[mc] = dots[6];
-            m_new = mc + 1;
-            int nxt = 0;                          // smallest slot id not in the ring
-            for (;; ++nxt) {
-                bool used = false;
-                for (int r = 0; r < m_new; ++r) used |= (s.order[r] == nxt);
-                if (!used) break;
-            }
-            s.spare = nxt;
+    if (threadIdx.x == 0) {
+        go = 0;
+        s.f = s.f_t;
+        s.gg = dots[0];
+        if (init) {
+            if (s.cost_hist) s.cost_hist[0] = s.f;
+            reset_memory(s);
+            steepest(s);
+            if (s.max_iter <= 0) finish(s, ST_DONE);
+            else if (s.max_ls <= 0) finish(s, EIT_ERR_LINESEARCH);
+            else s.skip_adj = 1;
         } else {
-            const int evict = s.order[0];
-            for (int r = 0; r + 1 < mc; ++r) {
-                s.order[r] = s.order[r + 1];
-                a[r] = a[r + 1];
-                b[r] = b[r + 1];
+            const double ss = dots[1], yy = dots[2], sy = dots[3], zz = dots[4];
+            for (int r = 0; r < mc; ++r) {
+                av[r] = dots[kDotsFixed + 4 * r + 2];
+                bv[r] = dots[kDotsFixed + 4 * r + 3];
+                sorder[r] = s.order[r];
             }
-            s.order[mc - 1] = sp;
-            a[mc - 1] = dots[5];
-            b[mc - 1] = dots[6];
-            s.spare = evict;
+            int m_new = mc;
+            if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
+                const int sp = s.spare;
+                for (int r = 0; r < mc; ++r) {
+                    const int o = sorder[r];
+                    sSY[o * W + sp] = dots[kDotsFixed + 4 * r + 0];
+                    const double yyr = dots[kDotsFixed + 4 * r + 1];
+                    sYY[o * W + sp] = yyr;
+                    sYY[sp * W + o] = yyr;
+                }
+                sSY[sp * W + sp] = sy;
+                sYY[sp * W + sp] = yy;
+                if (mc < s.m) {
+                    sorder[mc] = sp;
+                    av[mc] = dots[5];
+                    bv[mc] = dots[6];
+                    m_new = mc + 1;
+                    int nxt = 0;                      // smallest slot id not in the ring
+                    for (;; ++nxt) {
+                        bool used = false;
+                        for (int r = 0; r < m_new; ++r) used |= (sorder[r] == nxt);
+                        if (!used) break;
+                    }
+                    s.spare = nxt;
+                } else {
+                    const int evict = sorder[0];
+                    for (int r = 0; r + 1 < mc; ++r) {
+                        sorder[r] = sorder[r + 1];
+                        av[r] = av[r + 1];
+                        bv[r] = bv[r + 1];
+                    }
+                    sorder[mc - 1] = sp;
+                    av[mc - 1] = dots[5];
+                    bv[mc - 1] = dots[6];
+                    s.spare = evict;
+                }
+            }
+            s.m_cur = m_new;
+            sm2 = m_new;
+            for (int r = 0; r < m_new; ++r) s.order[r] = sorder[r];
+            s.k += 1;
+            if (s.cost_hist) s.cost_hist[s.k] = s.f;
+            if (s.k >= s.max_iter) finish(s, ST_DONE);
+            else if (s.tol > 0.0 && zz > 0.0 && sqrt(ss / zz) < s.tol) finish(s, ST_DONE);
+            else if (s.m_cur == 0) { steepest(s); s.skip_adj = 1; }
+            else go = 1;
         }
     }
-    s.m_cur = m_new;
-    s.k += 1;
-    if (s.cost_hist) s.cost_hist[s.k] = s.f;
-    if (s.k >= s.max_iter) { finish(s, ST_DONE); return; }
-    if (s.tol > 0.0 && zz > 0.0 && sqrt(ss / zz) < s.tol) { finish(s, ST_DONE); return; }
-    if (s.m_cur == 0) steepest(s);
-    else compact_direction(s, a, b);
-    s.skip_adj = 1;
+    __syncthreads();
+    // write back the (possibly updated) matrices; gather the ring-ordered blocks
+    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+        s.SY[i] = sSY[i];
+        s.YY[i] = sYY[i];
+    }
+    if (!go) return;
+    const int m2 = sm2;      // via LDS: thread 0's global writes are not read back here
+    for (int i = threadIdx.x; i < m2 * m2; i += blockDim.x) {
+        const int r = i / m2, q = i % m2;
+        oSY[r * kMaxM + q] = sSY[sorder[r] * W + sorder[q]];
+        oYY[r * kMaxM + q] = sYY[sorder[r] * W + sorder[q]];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        compact_direction(s, av, bv, oSY, oYY, cs, vs, es);
+        s.skip_adj = 1;
+    }
 }
 
 // ------------------------------------------------------------------------ descriptor upload

@@ -136,13 +136,14 @@ def check_projector_bounds(g, pv):
     p0 = (np.arange(ns) * R).astype(np.float64)
     lo = wl.astype(np.float64)[:, :, None, None, :]                          # [ng,nb,1,1,ns]
     up0 = ut0[..., None] + p0 * slope                                         # [ng,nb,A,2,ns]
-    fl0 = np.floor(up0)
+    fl0 = np.floor(up0 + np.minimum(0.0, (R - 1) * slope)) - 1.0
     uf = f32(up0 - fl0)
     ioff = fl0 - lo
-    assert ioff.min() >= 1
+    assert ioff.min() >= 0
     for r in (0, R - 1):
-        col = np.floor(fmaf(float(r), slope_f, uf)) + ioff
-        assert col.min() >= 0, (pv, col.min())
+        u = fmaf(float(r), slope_f, uf)
+        assert u.min() >= 0.0, (pv, u.min())           # truncation is the floor
+        col = np.trunc(u) + ioff
         assert col.max() <= info["win_w"] - 2, (pv, col.max(), info["win_w"])
     return True
 
@@ -170,8 +171,8 @@ def check_adjoint_bounds(g, av, vpt):
             u0 = fmaf(float(il), csf, fmaf(float(jl), snf, offs))
             for q in (0, vpt - 1):
                 u = u0 if q == 0 else fmaf(float(q * JS), snf, u0)
-                b = np.floor(u)
-                assert b.min() >= 0, (av, b.min())
+                assert u.min() >= 0.0, (av, u.min())       # truncation is the floor
+                b = np.trunc(u)
                 assert b.max() <= kwin - 2, (av, b.max(), kwin)
 
 
