@@ -117,8 +117,8 @@ typedef struct {
 } eit_opts;
 
 /* Phases of one evaluation step, in launch order (indices of eit_report.phase_ms). */
-#define EIT_PHASE_DIRECTION 0   /* L-BFGS direction and trial point */
-#define EIT_PHASE_TRANSPOSE 1   /* transposed copy of the trial point, ||z||^2 partials */
+#define EIT_PHASE_DIRECTION 0   /* L-BFGS direction, trial point, its transpose and norms */
+#define EIT_PHASE_TRANSPOSE 1   /* folded into EIT_PHASE_DIRECTION (reported as 0) */
 #define EIT_PHASE_PROJECT 2     /* Radon transform of both maps */
 #define EIT_PHASE_IC 3          /* IC model, residual, cost partials, adjoint seeds */
 #define EIT_PHASE_DECIDE 4      /* cost reduction and Armijo decision */

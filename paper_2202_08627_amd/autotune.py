@@ -1,0 +1,125 @@
+"""Tile-shape autotuner for the projector and adjoint kernels.
+
+For a slice geometry (grid size, angles, detector pixels) every compiled variant that fits
+the geometry is timed through the C ABI (eit_project / eit_backproject, HIP events around
+repeated launches on the current stream) and the fastest pair is stored in a JSON cache keyed
+by the size class. `tiling_for(geo)` returns the cached choice (or -1/-1 = library defaults).
+
+    python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+import numpy as np
+
+from . import _lib as L
+from . import ops, synth
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
+
+
+def size_key(geo) -> str:
+    return f"{geo.n}x{geo.n_theta}x{geo.n_det}"
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def tiling_for(geo, path: str = DEFAULT_CACHE):
+    ent = load_cache(path).get(size_key(geo))
+    if not ent:
+        return -1, -1
+    return int(ent["proj_variant"]), int(ent["adj_variant"])
+
+
+def _time(fn, reps: int):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
+    """Times every applicable variant; returns the record stored in the cache."""
+    import torch
+    rng = np.random.default_rng(0)
+    x = torch.as_tensor(rng.standard_normal((2, geo.n, geo.n)).astype(np.float32), device="cuda")
+    y = torch.as_tensor(rng.standard_normal((2, geo.n_theta, geo.n_det)).astype(np.float32),
+                        device="cuda")
+    res = {"proj": {}, "adj": {}}
+    for v, shape in enumerate(ops.variants(0)):
+        try:
+            plan = ops.Plan(geo, proj_variant=v, adj_variant=0)
+        except L.EitError:
+            continue                      # window wider than this variant's pitch
+        out = torch.empty(plan.sino_shape, device="cuda")
+        ws = plan.workspace(L.EIT_OP_PROJECT)
+        ms = _time(lambda: plan.project(x, out=out, ws=ws), reps)
+        res["proj"][v] = ms
+        if verbose:
+            print(f"  project variant {v} {shape}: {ms * 1e3:.1f} us", flush=True)
+        plan.close()
+    for v, shape in enumerate(ops.variants(1)):
+        try:
+            plan = ops.Plan(geo, adj_variant=v)
+        except L.EitError:
+            continue
+        out = torch.empty(plan.x_shape, device="cuda")
+        ws = plan.workspace(L.EIT_OP_BACKPROJECT)
+        ms = _time(lambda: plan.backproject(y, out=out, ws=ws), reps)
+        res["adj"][v] = ms
+        if verbose:
+            print(f"  backproject variant {v} {shape}: {ms * 1e3:.1f} us", flush=True)
+        plan.close()
+    pv = min(res["proj"], key=res["proj"].get)
+    av = min(res["adj"], key=res["adj"].get)
+    return {"proj_variant": pv, "adj_variant": av,
+            "proj_us": {str(k): round(v * 1e3, 2) for k, v in res["proj"].items()},
+            "adj_us": {str(k): round(v * 1e3, 2) for k, v in res["adj"].items()}}
+
+
+def tune_and_store(geo, path: str = DEFAULT_CACHE, reps: int = 20, verbose: bool = True) -> dict:
+    rec = tune(geo, reps, verbose)
+    cache = load_cache(path)
+    cache[size_key(geo)] = rec
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return rec
+
+
+def geometry_for(n: int, n_theta: int, n_det: int | None = None, n_mask: int = 8):
+    nd = n if n_det is None else n_det
+    return ops.Geometry(n, n_theta, nd, n_mask, 10.0, synth.angles(n_theta),
+                        synth.mask_positions(n_mask), np.ones(nd), np.zeros(nd), np.full(nd, 0.6))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, nargs="+", default=[512])
+    ap.add_argument("--n-theta", type=int, nargs="+", default=[720])
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args()
+    for n, nt in zip(a.n, a.n_theta):
+        geo = geometry_for(n, nt)
+        print(f"tuning {size_key(geo)}", flush=True)
+        rec = tune_and_store(geo, a.cache, a.reps)
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -585,9 +585,9 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev = nullptr) {
         return EIT_OK;
     };
     if (int rc = mark(0)) return rc;
-    HIP_TRY(launch_lb_direction(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+    // direction, trial point, its transposed copy and ||zt||^2 partials in one pass
+    HIP_TRY(launch_lb_direction(sp.L, sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
     if (int rc = mark(1)) return rc;
-    HIP_TRY(launch_transpose(sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
     if (int rc = mark(2)) return rc;
     for (const auto& l : sp.proj)
         HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));

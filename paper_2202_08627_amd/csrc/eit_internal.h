@@ -77,7 +77,7 @@ using Item = int4;
 
 // ---------------------------------------------------------------- optimiser state
 constexpr int kMaxM = 20;                // largest L-BFGS memory
-constexpr int kVecChunk = 1024;          // vector elements per work item (256 threads x 4)
+constexpr int kVecChunk = 2048;          // vector elements per work item (256 threads x 8)
 constexpr int kVecThreads = 256;
 constexpr int kDotsFixed = 7;            // gg, ss, yy, sy, zz, s.g, y.g
 constexpr int max_dots(int m) { return kDotsFixed + 4 * m; }
@@ -106,7 +106,7 @@ struct LbDesc {
     float scale_mu, scale_de;
     float* z;  float* zt;  float* g;  float* gt;  float* d;
     float* S;  float* Y;         // [(m+1)][nv] each
-    double* part;                // [max_dots(m)][n_vblocks]
+    double* part;                // [n_vblocks][max_dots(m)]
     SolverState* st;
     float* x_user;               // raw-unit iterate (in/out)
     double* cost_hist;           // optional [max_iter + 1]
@@ -116,8 +116,8 @@ hipError_t launch_lb_init(const LbDesc* L, int n_slices, int m, int max_iter, in
                           double tol, hipStream_t s);
 hipError_t launch_lb_scale(const LbDesc* L, const Item* items, int n_items, int grid, int to_z,
                            hipStream_t s);
-hipError_t launch_lb_direction(const LbDesc* L, const Item* items, int n_items, int grid,
-                               hipStream_t s);
+hipError_t launch_lb_direction(const LbDesc* L, const SliceDesc* D, const Item* items, int n_items,
+                               int grid, hipStream_t s);
 hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s);
 hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int grid,
                             hipStream_t s);

@@ -108,43 +108,82 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_scale(const LbDesc* __restri
 }
 
 // ------------------------------------------------------------------------ direction + trial point
-// INIT: zt = z. NEW_DIR: d = -gamma g - sum ee_r s_r + sum cc_r y_r, zt = z + alpha d.
-// BACKTRACK: zt = z + alpha d (alpha already halved).
-__global__ __launch_bounds__(kVecThreads) void k_lb_direction(const LbDesc* __restrict__ L,
+// Item (slice, tile_x, tile_y, -): a 32 x 32 tile of both maps.
+// INIT: zt = z. NEW_DIR: d = -gamma g - sum ee_r s_r + sum cc_r y_r (FP64 accumulation: the
+// combination has cancellation), zt = z + alpha d. BACKTRACK: zt = z + alpha d.
+// The tile of zt is also written transposed (the projector's source for column-stepping
+// angles) and its sums of squares go to the regulariser partials, replacing a separate
+// transpose pass over the trial point.
+__global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __restrict__ L,
+                                                            const SliceDesc* __restrict__ D,
                                                             const Item* __restrict__ items,
                                                             int n_items) {
+    __shared__ float tile[2][kTrTile][kTrTile + 1];
+    __shared__ double red[kTrThreads / 64];
+    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const LbDesc& l = L[w.x];
+        const SliceDesc& dsc = D[w.x];
         const SolverState& s = *l.st;
         if (s.skip) continue;
         const int mode = s.mode;
         const int mc = s.m_cur;
-        const double alpha = s.alpha;
-        const double gamma = s.gamma;
-        const int64_t e0 = (int64_t)w.y * kVecChunk;
-        const int64_t e1 = min(e0 + kVecChunk, l.nv);
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
-            const float z = l.z[e];
-            if (mode == MODE_INIT) {
-                l.zt[e] = z;
-                continue;
-            }
-            double dv;
-            if (mode == MODE_NEW_DIR) {
-                // the direction is a combination with cancellation: accumulate in FP64
-                dv = -gamma * (double)l.g[e];
-                for (int r = 0; r < mc; ++r) {
-                    const int64_t o = (int64_t)s.order[r] * l.nv + e;
-                    dv = fma(-s.ee[r], (double)l.S[o], dv);
-                    dv = fma(s.cc[r], (double)l.Y[o], dv);
+        const double alpha = s.alpha, gamma = s.gamma;
+        const int n = l.n, tx = w.y, ty = w.z;
+        const size_t nn = (size_t)n * n;
+        double sq[2] = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int rr = 0; rr < kTrTile / 8; ++rr) {
+                const int r = ly + rr * 8;
+                const int j = ty * kTrTile + r, i = tx * kTrTile + lx;
+                float zt = 0.f;
+                if (j < n && i < n) {
+                    const size_t e = c * nn + (size_t)j * n + i;
+                    const float z = l.z[e];
+                    if (mode == MODE_INIT) {
+                        zt = z;
+                    } else {
+                        double dv;
+                        if (mode == MODE_NEW_DIR) {
+                            dv = -gamma * (double)l.g[e];
+                            for (int q = 0; q < mc; ++q) {
+                                const int64_t o = (int64_t)s.order[q] * l.nv + e;
+                                dv = fma(-s.ee[q], (double)l.S[o], dv);
+                                dv = fma(s.cc[q], (double)l.Y[o], dv);
+                            }
+                            l.d[e] = (float)dv;
+                        } else {
+                            dv = (double)l.d[e];
+                        }
+                        zt = (float)fma(alpha, dv, (double)z);
+                    }
+                    l.zt[e] = zt;
                 }
-                l.d[e] = (float)dv;
-            } else {
-                dv = (double)l.d[e];
+                tile[c][r][lx] = zt;
+                sq[c] = fma((double)zt, (double)zt, sq[c]);
             }
-            l.zt[e] = (float)fma(alpha, dv, (double)z);
         }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float* dst = dsc.xT + c * nn;
+            for (int r = ly; r < kTrTile; r += 8) {
+                const int i = tx * kTrTile + r, j = ty * kTrTile + lx;
+                if (i < n && j < n) dst[(size_t)i * n + j] = tile[c][lx][r];
+            }
+        }
+        sq[0] = block_sum(sq[0], red);
+        sq[1] = block_sum(sq[1], red);
+        if (threadIdx.x == 0) {
+            const int ntx = (n + kTrTile - 1) / kTrTile;
+            double* p = dsc.part_reg + 2 * (size_t)(ty * ntx + tx);
+            p[0] = sq[0];
+            p[1] = sq[1];
+        }
+        __syncthreads();
     }
 }
 
@@ -207,10 +246,14 @@ __global__ __launch_bounds__(256) void k_lb_decide(const SliceDesc* __restrict__
 // s_new = zt - z, y_new = gt - g into the spare slot; z <- zt, g <- gt; per-block partial
 // inner products: [0] g.g [1] s.s [2] y.y [3] s.y [4] z_old.z_old [5] s.g [6] y.g and, for
 // every committed slot r: [7+4r] s_r.y [8+4r] y_r.y [9+4r] s_r.g [10+4r] y_r.g (g = new g).
+// Each product is reduced across the wavefront with shuffles as soon as it is complete; the
+// four wavefront sums meet once in LDS. Partials are stored [block][product].
 __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restrict__ L,
                                                          const Item* __restrict__ items,
                                                          int n_items) {
-    __shared__ double red[kVecThreads / 64];
+    constexpr int NW = kVecThreads / 64;
+    __shared__ double wsum[NW][max_dots(kMaxM)];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const LbDesc& l = L[w.x];
@@ -222,40 +265,40 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
         const int64_t e0 = (int64_t)w.y * kVecChunk;
         const int64_t e1 = min(e0 + kVecChunk, nv);
         constexpr int PER = kVecChunk / kVecThreads;
-        float sv[PER], yv[PER], gv[PER];
+        float yv[PER], gv[PER];
         double acc[kDotsFixed];
+#pragma unroll
         for (int q = 0; q < kDotsFixed; ++q) acc[q] = 0.0;
         const int64_t sp = (int64_t)st.spare * nv;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
-            sv[u] = 0.f; yv[u] = 0.f; gv[u] = 0.f;
+            yv[u] = 0.f; gv[u] = 0.f;
             if (e < e1) {
                 const float gt = l.gt[e];
                 gv[u] = gt;
                 acc[0] = fma((double)gt, (double)gt, acc[0]);
                 if (!init) {
                     const float zo = l.z[e], zn = l.zt[e], go = l.g[e];
-                    const float s = zn - zo, y = gt - go;
-                    sv[u] = s; yv[u] = y;
-                    l.S[sp + e] = s;
+                    const float sv = zn - zo, y = gt - go;
+                    yv[u] = y;
+                    l.S[sp + e] = sv;
                     l.Y[sp + e] = y;
                     l.z[e] = zn;
-                    acc[1] = fma((double)s, (double)s, acc[1]);
+                    acc[1] = fma((double)sv, (double)sv, acc[1]);
                     acc[2] = fma((double)y, (double)y, acc[2]);
-                    acc[3] = fma((double)s, (double)y, acc[3]);
+                    acc[3] = fma((double)sv, (double)y, acc[3]);
                     acc[4] = fma((double)zo, (double)zo, acc[4]);
-                    acc[5] = fma((double)s, (double)gt, acc[5]);
+                    acc[5] = fma((double)sv, (double)gt, acc[5]);
                     acc[6] = fma((double)y, (double)gt, acc[6]);
                 }
                 l.g[e] = gt;
             }
         }
-        double* part = l.part + w.y - (int64_t)0;   // column w.y of [dot][n_vblocks]
-        const int nb = l.n_vblocks;
+#pragma unroll
         for (int q = 0; q < kDotsFixed; ++q) {
-            const double v = block_sum(acc[q], red);
-            if (threadIdx.x == 0) part[(int64_t)q * nb] = v;
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) wsum[wid][q] = v;
         }
         for (int r = 0; r < mc; ++r) {
             const int64_t o = (int64_t)st.order[r] * nv;
@@ -271,18 +314,27 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
                     a3 = fma(yr, (double)gv[u], a3);
                 }
             }
-            a0 = block_sum(a0, red);
-            a1 = block_sum(a1, red);
-            a2 = block_sum(a2, red);
-            a3 = block_sum(a3, red);
-            if (threadIdx.x == 0) {
-                part[(int64_t)(kDotsFixed + 4 * r + 0) * nb] = a0;
-                part[(int64_t)(kDotsFixed + 4 * r + 1) * nb] = a1;
-                part[(int64_t)(kDotsFixed + 4 * r + 2) * nb] = a2;
-                part[(int64_t)(kDotsFixed + 4 * r + 3) * nb] = a3;
+            a0 = wave_sum(a0);
+            a1 = wave_sum(a1);
+            a2 = wave_sum(a2);
+            a3 = wave_sum(a3);
+            if (lane == 0) {
+                wsum[wid][kDotsFixed + 4 * r + 0] = a0;
+                wsum[wid][kDotsFixed + 4 * r + 1] = a1;
+                wsum[wid][kDotsFixed + 4 * r + 2] = a2;
+                wsum[wid][kDotsFixed + 4 * r + 3] = a3;
             }
         }
-        (void)sv;
+        __syncthreads();
+        const int nd = kDotsFixed + 4 * mc;
+        double* part = l.part + (int64_t)w.y * max_dots(st.m);   // row w.y of [block][dot]
+        for (int q = threadIdx.x; q < nd; q += kVecThreads) {
+            double v = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) v += wsum[ww][q];
+            part[q] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -294,6 +346,7 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
 __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
     constexpr int W = kMaxM + 1;
     __shared__ double dots[max_dots(kMaxM)];
+    __shared__ double red4[4][max_dots(kMaxM)];
     __shared__ double sSY[W * W], sYY[W * W];
     __shared__ double oSY[kMaxM * kMaxM], oYY[kMaxM * kMaxM];
     __shared__ double av[kMaxM], bv[kMaxM], cs[kMaxM], vs[kMaxM], es[kMaxM];
@@ -305,13 +358,28 @@ __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ 
     const int init = s.mode == MODE_INIT;
     const int mc = init ? 0 : s.m_cur;
     const int nd = kDotsFixed + 4 * mc;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = wid; q < nd; q += 4) {
-        double v = 0.0;
-        for (int b = lane; b < l.n_vblocks; b += 64) v += l.part[(int64_t)q * l.n_vblocks + b];
-        v = wave_sum(v);
-        if (lane == 0) dots[q] = v;
+    const int stride = max_dots(s.m);
+    // product q: thread t sums blocks t, t+256, ... (independent loads), then the block sums
+    // the 256 per-thread values in a fixed tree order
+    for (int q0 = 0; q0 < nd; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = 0.0;
+        for (int b = threadIdx.x; b < l.n_vblocks; b += blockDim.x) {
+            const double* row = l.part + (int64_t)b * stride;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (q0 + q < nd) v[q] += row[q0 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double t = wave_sum(v[q]);
+            if ((threadIdx.x & 63) == 0 && q0 + q < nd) red4[threadIdx.x >> 6][q0 + q] = t;
+        }
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nd; q += blockDim.x)
+        dots[q] = red4[0][q] + red4[1][q] + red4[2][q] + red4[3][q];
     for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
         sSY[i] = s.SY[i];
         sYY[i] = s.YY[i];
@@ -418,9 +486,9 @@ hipError_t launch_lb_scale(const LbDesc* L, const Item* items, int n_items, int 
     k_lb_scale<<<grid, kVecThreads, 0, s>>>(L, items, n_items, to_z);
     return hipGetLastError();
 }
-hipError_t launch_lb_direction(const LbDesc* L, const Item* items, int n_items, int grid,
-                               hipStream_t s) {
-    k_lb_direction<<<grid, kVecThreads, 0, s>>>(L, items, n_items);
+hipError_t launch_lb_direction(const LbDesc* L, const SliceDesc* D, const Item* items, int n_items,
+                               int grid, hipStream_t s) {
+    k_lb_direction<<<grid, kTrThreads, 0, s>>>(L, D, items, n_items);
     return hipGetLastError();
 }
 hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s) {
