@@ -120,7 +120,9 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
                                                             int n_items) {
     __shared__ float tile[2][kTrTile][kTrTile + 1];
     __shared__ double red[kTrThreads / 64];
-    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
+    // thread -> 4 consecutive columns (cx .. cx+3) of row ry of the 32 x 32 tile, both maps
+    const int cx = (threadIdx.x & 7) * 4, ry = threadIdx.x >> 3;
+    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const LbDesc& l = L[w.x];
@@ -128,51 +130,117 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
         const SolverState& s = *l.st;
         if (s.skip) continue;
         const int mode = s.mode;
-        const int mc = s.m_cur;
+        const int mc = mode == MODE_NEW_DIR ? s.m_cur : 0;
         const double alpha = s.alpha, gamma = s.gamma;
         const int n = l.n, tx = w.y, ty = w.z;
         const size_t nn = (size_t)n * n;
+        const int j = ty * kTrTile + ry, i0 = tx * kTrTile + cx;
+        const bool vec = (n & 3) == 0 && j < n && i0 + 3 < n;   // whole aligned float4 in range
+        // element e(c, q) of this thread: map c, column i0 + q, row j
+        float zt[2][4];
+        if (vec) {
+            double dv[2][4];
+            const size_t e0 = (size_t)j * n + i0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float4 g4 = mode == MODE_NEW_DIR ? *(const float4*)(l.g + c * nn + e0)
+                                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 d4 = mode == MODE_BACKTRACK ? *(const float4*)(l.d + c * nn + e0)
+                                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                dv[c][0] = mode == MODE_NEW_DIR ? -gamma * g4.x : (double)d4.x;
+                dv[c][1] = mode == MODE_NEW_DIR ? -gamma * g4.y : (double)d4.y;
+                dv[c][2] = mode == MODE_NEW_DIR ? -gamma * g4.z : (double)d4.z;
+                dv[c][3] = mode == MODE_NEW_DIR ? -gamma * g4.w : (double)d4.w;
+            }
+            // history combination, next slot's vectors loaded while this one is applied
+            float4 sv[2], yv[2];
+            auto load_slot = [&](int q) {
+                const size_t o = (size_t)s.order[q] * l.nv + e0;
+                sv[0] = *(const float4*)(l.S + o);
+                yv[0] = *(const float4*)(l.Y + o);
+                sv[1] = *(const float4*)(l.S + o + nn);
+                yv[1] = *(const float4*)(l.Y + o + nn);
+            };
+            if (mc > 0) load_slot(0);
+            for (int q = 0; q < mc; ++q) {
+                const float4 s0 = sv[0], y0 = yv[0], s1 = sv[1], y1 = yv[1];
+                if (q + 1 < mc) load_slot(q + 1);
+                const double ee = -s.ee[q], cc = s.cc[q];
+                dv[0][0] = fma(cc, (double)y0.x, fma(ee, (double)s0.x, dv[0][0]));
+                dv[0][1] = fma(cc, (double)y0.y, fma(ee, (double)s0.y, dv[0][1]));
+                dv[0][2] = fma(cc, (double)y0.z, fma(ee, (double)s0.z, dv[0][2]));
+                dv[0][3] = fma(cc, (double)y0.w, fma(ee, (double)s0.w, dv[0][3]));
+                dv[1][0] = fma(cc, (double)y1.x, fma(ee, (double)s1.x, dv[1][0]));
+                dv[1][1] = fma(cc, (double)y1.y, fma(ee, (double)s1.y, dv[1][1]));
+                dv[1][2] = fma(cc, (double)y1.z, fma(ee, (double)s1.z, dv[1][2]));
+                dv[1][3] = fma(cc, (double)y1.w, fma(ee, (double)s1.w, dv[1][3]));
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float4 z4 = *(const float4*)(l.z + c * nn + e0);
+                float4 t4;
+                if (mode == MODE_INIT) {
+                    t4 = z4;
+                } else {
+                    t4.x = (float)fma(alpha, dv[c][0], (double)z4.x);
+                    t4.y = (float)fma(alpha, dv[c][1], (double)z4.y);
+                    t4.z = (float)fma(alpha, dv[c][2], (double)z4.z);
+                    t4.w = (float)fma(alpha, dv[c][3], (double)z4.w);
+                    if (mode == MODE_NEW_DIR)
+                        *(float4*)(l.d + c * nn + e0) =
+                            make_float4((float)dv[c][0], (float)dv[c][1], (float)dv[c][2], (float)dv[c][3]);
+                }
+                *(float4*)(l.zt + c * nn + e0) = t4;
+                zt[c][0] = t4.x; zt[c][1] = t4.y; zt[c][2] = t4.z; zt[c][3] = t4.w;
+            }
+        } else {
+            // edge tiles or n not a multiple of 4: element by element
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u;
+                    float t = 0.f;
+                    if (j < n && i < n) {
+                        const size_t e = c * nn + (size_t)j * n + i;
+                        const float z = l.z[e];
+                        if (mode == MODE_INIT) {
+                            t = z;
+                        } else {
+                            double dv;
+                            if (mode == MODE_NEW_DIR) {
+                                dv = -gamma * (double)l.g[e];
+                                for (int q = 0; q < mc; ++q) {
+                                    const int64_t o = (int64_t)s.order[q] * l.nv + e;
+                                    dv = fma(-s.ee[q], (double)l.S[o], dv);
+                                    dv = fma(s.cc[q], (double)l.Y[o], dv);
+                                }
+                                l.d[e] = (float)dv;
+                            } else {
+                                dv = (double)l.d[e];
+                            }
+                            t = (float)fma(alpha, dv, (double)z);
+                        }
+                        l.zt[e] = t;
+                    }
+                    zt[c][u] = t;
+                }
+        }
         double sq[2] = {0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int rr = 0; rr < kTrTile / 8; ++rr) {
-                const int r = ly + rr * 8;
-                const int j = ty * kTrTile + r, i = tx * kTrTile + lx;
-                float zt = 0.f;
-                if (j < n && i < n) {
-                    const size_t e = c * nn + (size_t)j * n + i;
-                    const float z = l.z[e];
-                    if (mode == MODE_INIT) {
-                        zt = z;
-                    } else {
-                        double dv;
-                        if (mode == MODE_NEW_DIR) {
-                            dv = -gamma * (double)l.g[e];
-                            for (int q = 0; q < mc; ++q) {
-                                const int64_t o = (int64_t)s.order[q] * l.nv + e;
-                                dv = fma(-s.ee[q], (double)l.S[o], dv);
-                                dv = fma(s.cc[q], (double)l.Y[o], dv);
-                            }
-                            l.d[e] = (float)dv;
-                        } else {
-                            dv = (double)l.d[e];
-                        }
-                        zt = (float)fma(alpha, dv, (double)z);
-                    }
-                    l.zt[e] = zt;
-                }
-                tile[c][r][lx] = zt;
-                sq[c] = fma((double)zt, (double)zt, sq[c]);
+            for (int u = 0; u < 4; ++u) {
+                tile[c][ry][cx + u] = zt[c][u];
+                sq[c] = fma((double)zt[c][u], (double)zt[c][u], sq[c]);
             }
-        }
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             float* dst = dsc.xT + c * nn;
             for (int r = ly; r < kTrTile; r += 8) {
-                const int i = tx * kTrTile + r, j = ty * kTrTile + lx;
-                if (i < n && j < n) dst[(size_t)i * n + j] = tile[c][lx][r];
+                const int i = tx * kTrTile + r, jj = ty * kTrTile + lx;
+                if (i < n && jj < n) dst[(size_t)i * n + jj] = tile[c][lx][r];
             }
         }
         sq[0] = block_sum(sq[0], red);
@@ -300,19 +368,29 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
             const double v = wave_sum(acc[q]);
             if (lane == 0) wsum[wid][q] = v;
         }
-        for (int r = 0; r < mc; ++r) {
+        float sb[PER], yb[PER];
+        auto load_slot = [&](int r) {
             const int64_t o = (int64_t)st.order[r] * nv;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
-                if (e < e1) {
-                    const double sr = l.S[o + e], yr = l.Y[o + e];
-                    a0 = fma(sr, (double)yv[u], a0);
-                    a1 = fma(yr, (double)yv[u], a1);
-                    a2 = fma(sr, (double)gv[u], a2);
-                    a3 = fma(yr, (double)gv[u], a3);
-                }
+                sb[u] = e < e1 ? l.S[o + e] : 0.f;
+                yb[u] = e < e1 ? l.Y[o + e] : 0.f;
+            }
+        };
+        if (mc > 0) load_slot(0);
+        for (int r = 0; r < mc; ++r) {
+            float sr[PER], yr[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) { sr[u] = sb[u]; yr[u] = yb[u]; }
+            if (r + 1 < mc) load_slot(r + 1);          // in flight during this slot's sums
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                a0 = fma((double)sr[u], (double)yv[u], a0);
+                a1 = fma((double)yr[u], (double)yv[u], a1);
+                a2 = fma((double)sr[u], (double)gv[u], a2);
+                a3 = fma((double)yr[u], (double)gv[u], a3);
             }
             a0 = wave_sum(a0);
             a1 = wave_sum(a1);
@@ -352,9 +430,16 @@ __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ 
     __shared__ double av[kMaxM], bv[kMaxM], cs[kMaxM], vs[kMaxM], es[kMaxM];
     __shared__ int sorder[kMaxM];
     __shared__ int go, sm2;
+    __shared__ SolverState s;          // working copy: the scalar logic touches LDS only
     const LbDesc& l = L[blockIdx.x];
-    SolverState& s = *l.st;
-    if (s.skip_adj) return;
+    SolverState& gs = *l.st;
+    if (gs.skip_adj) return;
+    {
+        const int* src = (const int*)&gs;
+        int* dst = (int*)&s;
+        for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 4); i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
     const int init = s.mode == MODE_INIT;
     const int mc = init ? 0 : s.m_cur;
     const int nd = kDotsFixed + 4 * mc;
@@ -452,22 +537,28 @@ __global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ 
         }
     }
     __syncthreads();
-    // write back the (possibly updated) matrices; gather the ring-ordered blocks
     for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
         s.SY[i] = sSY[i];
         s.YY[i] = sYY[i];
     }
-    if (!go) return;
-    const int m2 = sm2;      // via LDS: thread 0's global writes are not read back here
-    for (int i = threadIdx.x; i < m2 * m2; i += blockDim.x) {
-        const int r = i / m2, q = i % m2;
-        oSY[r * kMaxM + q] = sSY[sorder[r] * W + sorder[q]];
-        oYY[r * kMaxM + q] = sYY[sorder[r] * W + sorder[q]];
+    if (go) {
+        const int m2 = sm2;
+        for (int i = threadIdx.x; i < m2 * m2; i += blockDim.x) {
+            const int r = i / m2, q = i % m2;
+            oSY[r * kMaxM + q] = sSY[sorder[r] * W + sorder[q]];
+            oYY[r * kMaxM + q] = sYY[sorder[r] * W + sorder[q]];
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (go && threadIdx.x == 0) {
         compact_direction(s, av, bv, oSY, oYY, cs, vs, es);
         s.skip_adj = 1;
+    }
+    __syncthreads();
+    {   // write the working copy back
+        const int* src = (const int*)&s;
+        int* dst = (int*)&gs;
+        for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 4); i += blockDim.x) dst[i] = src[i];
     }
 }
 
