@@ -6,36 +6,10 @@
 //   backproject-- gather-form R^T (+ regulariser term of the gradient), LDS-staged windows
 // Every kernel walks a list of work items (slice, a, b, c) with a grid-stride loop, so one
 // launch can cover one slice or a batch of slices of different sizes.
-#include "eit_internal.h"
-#include "reduce.h"
+#include "device_common.h"
+#include "solver_dev.h"
 
 namespace eit {
-
-__device__ __forceinline__ bool skipped(const SliceDesc& d) {
-    return d.skip != nullptr && *d.skip != 0;
-}
-__device__ __forceinline__ bool skipped_adj(const SliceDesc& d) {
-    return (d.skip != nullptr && *d.skip != 0) || (d.skip_adj != nullptr && *d.skip_adj != 0);
-}
-
-// Pointers read out of a descriptor are generic; these casts let the compiler use global
-// (vector) loads and, for wavefront-uniform addresses of read-only tables, scalar loads.
-typedef const __attribute__((address_space(1))) float gfloat;
-__device__ __forceinline__ gfloat* as_global(const float* p) { return (gfloat*)p; }
-template <class T>
-__device__ __forceinline__ T cld(const T* p) {
-    return *(const __attribute__((address_space(4))) T*)p;
-}
-
-// Raw buffer resource over `bytes` bytes from `p` (gfx9 descriptor word 3): loads at offsets
-// >= bytes return 0 without touching memory. Every offset is carried in the VGPR operand.
-constexpr int kBufOOB = 0x7ffffff0;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, bytes, 0x00020000);
-}
-__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
-}
 
 // ------------------------------------------------------------------------ transpose
 // Item (slice, tile_x, tile_y, -): 32x32 tile of both maps through LDS. Also writes the
@@ -211,9 +185,10 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
 // P holds scale * R x on input (scale folded in here) and the seeds times scale on output
 // (chain rule for scaled unknowns), overwritten in place.
 constexpr int kMaxDetLds = 4096;
+template <bool FUSE_DECIDE>
 __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items,
-                                                  int want_seeds) {
+                                                  int want_seeds, const LbDesc* __restrict__ L) {
     __shared__ float gdl[kMaxDetLds];
     __shared__ double red[kIcThreads / 64];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -260,6 +235,10 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
         }
         r2 = block_sum(r2, red);
         if (threadIdx.x == 0) d.part_ic[a] = r2;
+        if constexpr (FUSE_DECIDE) {
+            // the block finishing the slice's last angle reduces the cost and decides
+            if (finish_item(&L[w.x].st->cnt_ic, d.n_theta)) decide_body(d, *L[w.x].st);
+        }
         __syncthreads();
     }
 }
@@ -521,9 +500,10 @@ hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, in
 }
 
 hipError_t launch_ic(const SliceDesc* D, const Item* items, int n_items, int grid, int want_seeds,
-                     hipStream_t s) {
+                     hipStream_t s, const LbDesc* L) {
     if (n_items <= 0) return hipSuccess;
-    k_ic<<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds);
+    if (L) k_ic<true><<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds, L);
+    else k_ic<false><<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds, nullptr);
     return hipGetLastError();
 }
 

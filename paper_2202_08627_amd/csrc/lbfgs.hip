@@ -7,73 +7,9 @@
 // m x m algebra runs in one thread. Inner products accumulate in FP64. The line search
 // (Armijo backtracking) is a device-side state machine: each replay of the evaluation
 // sequence either starts a new direction or halves the step, with no host round trip.
-#include "eit_internal.h"
-#include "reduce.h"
-#include "eitomo.h"
+#include "solver_dev.h"
 
 namespace eit {
-
-// ------------------------------------------------------------------------ helpers
-__device__ void steepest(SolverState& s) {
-    s.gamma = 1.0;
-    for (int r = 0; r < kMaxM; ++r) { s.cc[r] = 0.0; s.ee[r] = 0.0; }
-    s.gd = -s.gg;
-    s.alpha = 1.0 / sqrt(s.gg);
-    s.trials = 0;
-    s.mode = MODE_NEW_DIR;
-}
-
-__device__ void reset_memory(SolverState& s) {
-    s.m_cur = 0;
-    s.spare = 0;
-}
-
-// Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first). SY and YY
-// are the ring-ordered m_cur x m_cur matrices (row stride kMaxM) in LDS; c, v, e are LDS
-// scratch. Runs in one thread.
-__device__ void compact_direction(SolverState& s, const double* a, const double* b,
-                                  const double* SY, const double* YY, double* c, double* v,
-                                  double* e) {
-    const int mc = s.m_cur;
-    const int W = kMaxM;
-    const double gamma = SY[(mc - 1) * W + (mc - 1)] / YY[(mc - 1) * W + (mc - 1)];
-    for (int r = mc - 1; r >= 0; --r) {                 // c = R^{-1} a (back substitution)
-        double acc = a[r];
-        for (int q = r + 1; q < mc; ++q) acc -= SY[r * W + q] * c[q];
-        c[r] = acc / SY[r * W + r];
-    }
-    for (int r = 0; r < mc; ++r) {                      // v = (D + gamma Y^T Y) c - gamma b
-        double acc = SY[r * W + r] * c[r] - gamma * b[r];
-        for (int q = 0; q < mc; ++q) acc += gamma * YY[r * W + q] * c[q];
-        v[r] = acc;
-    }
-    for (int r = 0; r < mc; ++r) {                      // e = R^{-T} v (forward substitution)
-        double acc = v[r];
-        for (int q = 0; q < r; ++q) acc -= SY[q * W + r] * e[q];
-        e[r] = acc / SY[r * W + r];
-    }
-    double gHg = gamma * s.gg;
-    for (int r = 0; r < mc; ++r) gHg += a[r] * e[r] - gamma * b[r] * c[r];
-    for (int r = 0; r < kMaxM; ++r) {
-        s.ee[r] = r < mc ? e[r] : 0.0;
-        s.cc[r] = r < mc ? gamma * c[r] : 0.0;
-    }
-    s.gamma = gamma;
-    s.gd = -gHg;
-    s.alpha = 1.0;
-    s.trials = 0;
-    s.mode = MODE_NEW_DIR;
-    if (!(s.gd < 0.0)) {                                // not a descent direction
-        reset_memory(s);
-        steepest(s);
-    }
-}
-
-__device__ void finish(SolverState& s, int status) {
-    s.status = status;
-    s.skip = 1;
-    s.skip_adj = 1;
-}
 
 // ------------------------------------------------------------------------ init / scale
 __global__ void k_lb_init(const LbDesc* __restrict__ L, int m, int max_iter, int max_ls,
@@ -87,6 +23,7 @@ __global__ void k_lb_init(const LbDesc* __restrict__ L, int m, int max_iter, int
     s.k = 0; s.evals = 0; s.trials = 0; s.mode = MODE_INIT; s.status = ST_RUNNING;
     s.m_cur = 0; s.m = m; s.max_iter = max_iter; s.max_ls = max_ls; s.accept = 0;
     s.spare = 0; s.launches = 0; s.skip = 0; s.skip_adj = 0;
+    s.cnt_ic = 0; s.cnt_up = 0;
 }
 
 // to_z: z = x_user / scale; else x_user = z * scale.
@@ -255,61 +192,6 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
     }
 }
 
-// ------------------------------------------------------------------------ decision
-// One block per slice: reduce the cost at the trial point (FP64, fixed order) and run the
-// Armijo test F(zt) <= F(z) + c1 alpha g.d.
-__global__ __launch_bounds__(256) void k_lb_decide(const SliceDesc* __restrict__ D,
-                                                  const LbDesc* __restrict__ L) {
-    __shared__ double red[4];
-    const SliceDesc& d = D[blockIdx.x];
-    SolverState& s = *L[blockIdx.x].st;
-    if (s.skip) return;
-    double a = 0.0, r0 = 0.0, r1 = 0.0;
-    for (int i = threadIdx.x; i < d.n_theta; i += 256) a += d.part_ic[i];
-    for (int b = threadIdx.x; b < d.n_reg_blocks; b += 256) {
-        r0 += d.part_reg[2 * b];
-        r1 += d.part_reg[2 * b + 1];
-    }
-    a = block_sum(a, red);
-    r0 = block_sum(r0, red);
-    r1 = block_sum(r1, red);
-    if (threadIdx.x != 0) return;
-    const double ft = a + d.lam_mu * r0 + d.lam_de * r1;
-    s.f_t = ft;
-    s.launches += 1;
-    s.evals += 1;
-    if (s.mode == MODE_INIT) {
-        if (!isfinite(ft)) {
-            s.accept = 0;
-            finish(s, EIT_ERR_NONFINITE);
-        } else {
-            s.accept = 1;
-            s.skip_adj = 0;
-        }
-        return;
-    }
-    s.trials += 1;
-    const bool ok = ft <= s.f + s.c1 * s.alpha * s.gd;      // false for NaN
-    if (ok) {
-        s.accept = 1;
-        s.skip_adj = 0;
-        return;
-    }
-    s.accept = 0;
-    s.skip_adj = 1;
-    if (s.trials >= s.max_ls) {
-        if (s.m_cur > 0) {           // drop the memory, retry along -g
-            reset_memory(s);
-            steepest(s);
-        } else {
-            finish(s, EIT_ERR_LINESEARCH);
-        }
-    } else {
-        s.alpha *= 0.5;
-        s.mode = MODE_BACKTRACK;
-    }
-}
-
 // ------------------------------------------------------------------------ accept: update + dots
 // s_new = zt - z, y_new = gt - g into the spare slot; z <- zt, g <- gt; per-block partial
 // inner products: [0] g.g [1] s.s [2] y.y [3] s.y [4] z_old.z_old [5] s.g [6] y.g and, for
@@ -412,153 +294,8 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
             for (int ww = 0; ww < NW; ++ww) v += wsum[ww][q];
             part[q] = v;
         }
+        if (finish_item(&l.st->cnt_up, l.n_vblocks)) finalize_body(l);
         __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------------ accept: finalize
-// One block per slice: reduce the partial inner products (one wavefront per product, fixed
-// order), commit the pair if s.y > 1e-10 ||s|| ||y||, advance the iteration counter, test
-// the stopping rules and compute the next direction's coefficients. The scalar logic runs in
-// one thread on LDS copies of the state's small matrices.
-__global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
-    constexpr int W = kMaxM + 1;
-    __shared__ double dots[max_dots(kMaxM)];
-    __shared__ double red4[4][max_dots(kMaxM)];
-    __shared__ double sSY[W * W], sYY[W * W];
-    __shared__ double oSY[kMaxM * kMaxM], oYY[kMaxM * kMaxM];
-    __shared__ double av[kMaxM], bv[kMaxM], cs[kMaxM], vs[kMaxM], es[kMaxM];
-    __shared__ int sorder[kMaxM];
-    __shared__ int go, sm2;
-    __shared__ SolverState s;          // working copy: the scalar logic touches LDS only
-    const LbDesc& l = L[blockIdx.x];
-    SolverState& gs = *l.st;
-    if (gs.skip_adj) return;
-    {
-        const int* src = (const int*)&gs;
-        int* dst = (int*)&s;
-        for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 4); i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
-    const int init = s.mode == MODE_INIT;
-    const int mc = init ? 0 : s.m_cur;
-    const int nd = kDotsFixed + 4 * mc;
-    const int stride = max_dots(s.m);
-    // product q: thread t sums blocks t, t+256, ... (independent loads), then the block sums
-    // the 256 per-thread values in a fixed tree order
-    for (int q0 = 0; q0 < nd; q0 += 16) {
-        double v[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = 0.0;
-        for (int b = threadIdx.x; b < l.n_vblocks; b += blockDim.x) {
-            const double* row = l.part + (int64_t)b * stride;
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (q0 + q < nd) v[q] += row[q0 + q];
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const double t = wave_sum(v[q]);
-            if ((threadIdx.x & 63) == 0 && q0 + q < nd) red4[threadIdx.x >> 6][q0 + q] = t;
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nd; q += blockDim.x)
-        dots[q] = red4[0][q] + red4[1][q] + red4[2][q] + red4[3][q];
-    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
-        sSY[i] = s.SY[i];
-        sYY[i] = s.YY[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        go = 0;
-        s.f = s.f_t;
-        s.gg = dots[0];
-        if (init) {
-            if (s.cost_hist) s.cost_hist[0] = s.f;
-            reset_memory(s);
-            steepest(s);
-            if (s.max_iter <= 0) finish(s, ST_DONE);
-            else if (s.max_ls <= 0) finish(s, EIT_ERR_LINESEARCH);
-            else s.skip_adj = 1;
-        } else {
-            const double ss = dots[1], yy = dots[2], sy = dots[3], zz = dots[4];
-            for (int r = 0; r < mc; ++r) {
-                av[r] = dots[kDotsFixed + 4 * r + 2];
-                bv[r] = dots[kDotsFixed + 4 * r + 3];
-                sorder[r] = s.order[r];
-            }
-            int m_new = mc;
-            if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
-                const int sp = s.spare;
-                for (int r = 0; r < mc; ++r) {
-                    const int o = sorder[r];
-                    sSY[o * W + sp] = dots[kDotsFixed + 4 * r + 0];
-                    const double yyr = dots[kDotsFixed + 4 * r + 1];
-                    sYY[o * W + sp] = yyr;
-                    sYY[sp * W + o] = yyr;
-                }
-                sSY[sp * W + sp] = sy;
-                sYY[sp * W + sp] = yy;
-                if (mc < s.m) {
-                    sorder[mc] = sp;
-                    av[mc] = dots[5];
-                    bv[mc] = dots[6];
-                    m_new = mc + 1;
-                    int nxt = 0;                      // smallest slot id not in the ring
-                    for (;; ++nxt) {
-                        bool used = false;
-                        for (int r = 0; r < m_new; ++r) used |= (sorder[r] == nxt);
-                        if (!used) break;
-                    }
-                    s.spare = nxt;
-                } else {
-                    const int evict = sorder[0];
-                    for (int r = 0; r + 1 < mc; ++r) {
-                        sorder[r] = sorder[r + 1];
-                        av[r] = av[r + 1];
-                        bv[r] = bv[r + 1];
-                    }
-                    sorder[mc - 1] = sp;
-                    av[mc - 1] = dots[5];
-                    bv[mc - 1] = dots[6];
-                    s.spare = evict;
-                }
-            }
-            s.m_cur = m_new;
-            sm2 = m_new;
-            for (int r = 0; r < m_new; ++r) s.order[r] = sorder[r];
-            s.k += 1;
-            if (s.cost_hist) s.cost_hist[s.k] = s.f;
-            if (s.k >= s.max_iter) finish(s, ST_DONE);
-            else if (s.tol > 0.0 && zz > 0.0 && sqrt(ss / zz) < s.tol) finish(s, ST_DONE);
-            else if (s.m_cur == 0) { steepest(s); s.skip_adj = 1; }
-            else go = 1;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
-        s.SY[i] = sSY[i];
-        s.YY[i] = sYY[i];
-    }
-    if (go) {
-        const int m2 = sm2;
-        for (int i = threadIdx.x; i < m2 * m2; i += blockDim.x) {
-            const int r = i / m2, q = i % m2;
-            oSY[r * kMaxM + q] = sSY[sorder[r] * W + sorder[q]];
-            oYY[r * kMaxM + q] = sYY[sorder[r] * W + sorder[q]];
-        }
-    }
-    __syncthreads();
-    if (go && threadIdx.x == 0) {
-        compact_direction(s, av, bv, oSY, oYY, cs, vs, es);
-        s.skip_adj = 1;
-    }
-    __syncthreads();
-    {   // write the working copy back
-        const int* src = (const int*)&s;
-        int* dst = (int*)&gs;
-        for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 4); i += blockDim.x) dst[i] = src[i];
     }
 }
 
@@ -582,17 +319,9 @@ hipError_t launch_lb_direction(const LbDesc* L, const SliceDesc* D, const Item* 
     k_lb_direction<<<grid, kTrThreads, 0, s>>>(L, D, items, n_items);
     return hipGetLastError();
 }
-hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s) {
-    k_lb_decide<<<n_slices, 256, 0, s>>>(D, L);
-    return hipGetLastError();
-}
 hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int grid,
                             hipStream_t s) {
     k_lb_update<<<grid, kVecThreads, 0, s>>>(L, items, n_items);
-    return hipGetLastError();
-}
-hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s) {
-    k_lb_finalize<<<n_slices, 256, 0, s>>>(L);
     return hipGetLastError();
 }
 hipError_t launch_store_desc(const SliceDesc& v, SliceDesc* dst, hipStream_t s) {
