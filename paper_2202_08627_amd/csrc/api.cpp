@@ -592,16 +592,16 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev = nullptr) {
     for (const auto& l : sp.proj)
         HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
     if (int rc = mark(3)) return rc;
-    // IC model; the block finishing a slice's last angle reduces its cost and decides
-    HIP_TRY(launch_ic(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st, sp.L));
+    HIP_TRY(launch_ic(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
     if (int rc = mark(4)) return rc;
+    HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
     if (int rc = mark(5)) return rc;
     for (const auto& l : sp.adj)
         HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 1, st));
     if (int rc = mark(6)) return rc;
-    // accepted step; the block finishing a slice's last chunk updates the memory and direction
     HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
     if (int rc = mark(7)) return rc;
+    HIP_TRY(launch_lb_finalize(sp.L, sp.n_slices, st));
     return mark(8);
 }
 

@@ -32,25 +32,4 @@ __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff) {
 }
 
 
-// Completion counting for "last work item finishes the slice" epilogues: every block that
-// completes an item of a slice bumps the slice's counter (release); the block that brings it
-// to `total` resets it and returns true (acquire), after which all its threads may read what
-// the other blocks wrote. Must be called by all threads of the block.
-__device__ __forceinline__ bool finish_item(int32_t* counter, int total) {
-    __shared__ int last;
-    __threadfence();                                 // this thread's writes are device-visible
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-        last = prev == total - 1;
-        if (last)
-            __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const bool r = last != 0;
-    if (r) __atomic_thread_fence(__ATOMIC_ACQUIRE);  // every thread acquires (device scope)
-    return r;
-}
-
 }  // namespace eit

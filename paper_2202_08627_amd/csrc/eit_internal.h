@@ -97,7 +97,6 @@ struct SolverState {
     int32_t k, evals, trials, mode, status, m_cur, m, max_iter, max_ls, accept, spare, launches;
     int32_t order[kMaxM];
     int32_t skip, skip_adj;                      // step-level no-op flags read by every kernel
-    int32_t cnt_ic, cnt_up;                      // completed work items (last one runs the epilogue)
 };
 
 // Per-slice optimiser buffers.
@@ -121,6 +120,8 @@ hipError_t launch_lb_direction(const LbDesc* L, const SliceDesc* D, const Item* 
                                int grid, hipStream_t s);
 hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int grid,
                             hipStream_t s);
+hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s);
+hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s);
 hipError_t launch_store_desc(const SliceDesc& v, SliceDesc* dst, hipStream_t s);
 hipError_t launch_store_lbdesc(const LbDesc& v, LbDesc* dst, hipStream_t s);
 
@@ -129,10 +130,8 @@ hipError_t launch_transpose(const SliceDesc* d_descs, const Item* items, int n_i
                             int grid, hipStream_t s);
 hipError_t launch_project(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
                           int grid, size_t lds_bytes, hipStream_t s);
-struct LbDesc;
-// L != nullptr: the block completing a slice's angles also runs the optimiser's decision
 hipError_t launch_ic(const SliceDesc* d_descs, const Item* items, int n_items, int grid,
-                     int want_seeds, hipStream_t s, const LbDesc* L = nullptr);
+                     int want_seeds, hipStream_t s);
 hipError_t launch_cost_reduce(const SliceDesc* d_descs, int n_slices, hipStream_t s);
 hipError_t launch_backproject(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
                               int grid, int add_reg, hipStream_t s);

@@ -7,7 +7,6 @@
 // Every kernel walks a list of work items (slice, a, b, c) with a grid-stride loop, so one
 // launch can cover one slice or a batch of slices of different sizes.
 #include "device_common.h"
-#include "solver_dev.h"
 
 namespace eit {
 
@@ -185,10 +184,9 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
 // P holds scale * R x on input (scale folded in here) and the seeds times scale on output
 // (chain rule for scaled unknowns), overwritten in place.
 constexpr int kMaxDetLds = 4096;
-template <bool FUSE_DECIDE>
 __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items,
-                                                  int want_seeds, const LbDesc* __restrict__ L) {
+                                                  int want_seeds) {
     __shared__ float gdl[kMaxDetLds];
     __shared__ double red[kIcThreads / 64];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -235,10 +233,6 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
         }
         r2 = block_sum(r2, red);
         if (threadIdx.x == 0) d.part_ic[a] = r2;
-        if constexpr (FUSE_DECIDE) {
-            // the block finishing the slice's last angle reduces the cost and decides
-            if (finish_item(&L[w.x].st->cnt_ic, d.n_theta)) decide_body(d, *L[w.x].st);
-        }
         __syncthreads();
     }
 }
@@ -500,10 +494,9 @@ hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, in
 }
 
 hipError_t launch_ic(const SliceDesc* D, const Item* items, int n_items, int grid, int want_seeds,
-                     hipStream_t s, const LbDesc* L) {
+                     hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (L) k_ic<true><<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds, L);
-    else k_ic<false><<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds, nullptr);
+    k_ic<<<grid, kIcThreads, 0, s>>>(D, items, n_items, want_seeds);
     return hipGetLastError();
 }
 

@@ -23,7 +23,6 @@ __global__ void k_lb_init(const LbDesc* __restrict__ L, int m, int max_iter, int
     s.k = 0; s.evals = 0; s.trials = 0; s.mode = MODE_INIT; s.status = ST_RUNNING;
     s.m_cur = 0; s.m = m; s.max_iter = max_iter; s.max_ls = max_ls; s.accept = 0;
     s.spare = 0; s.launches = 0; s.skip = 0; s.skip_adj = 0;
-    s.cnt_ic = 0; s.cnt_up = 0;
 }
 
 // to_z: z = x_user / scale; else x_user = z * scale.
@@ -294,9 +293,34 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
             for (int ww = 0; ww < NW; ++ww) v += wsum[ww][q];
             part[q] = v;
         }
-        if (finish_item(&l.st->cnt_up, l.n_vblocks)) finalize_body(l);
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------------------ decision / finalize
+// One block per slice. (Running these as the epilogue of the last block of the preceding
+// kernel needs device-scope release/acquire, which on a multi-XCD GPU writes back and
+// invalidates L2 per block and costs far more than the extra launch.)
+__global__ __launch_bounds__(kIcThreads) void k_lb_decide(const SliceDesc* __restrict__ D,
+                                                         const LbDesc* __restrict__ L) {
+    SolverState& s = *L[blockIdx.x].st;
+    if (s.skip) return;
+    decide_body(D[blockIdx.x], s);
+}
+
+__global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
+    const LbDesc& l = L[blockIdx.x];
+    if (l.st->skip_adj) return;
+    finalize_body(l);
+}
+
+hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s) {
+    k_lb_decide<<<n_slices, kIcThreads, 0, s>>>(D, L);
+    return hipGetLastError();
+}
+hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s) {
+    k_lb_finalize<<<n_slices, 256, 0, s>>>(L);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------ descriptor upload
