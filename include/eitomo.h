@@ -178,6 +178,18 @@ int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, 
                       double lam_delta, double* cost_dev, float* grad, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* Non-iterative reconstruction (the paper's single-shot route: retrieve each projection
+ * pixel, then filtered backprojection), used as the start of the learned warm start.
+ * With several mask positions per IC both channels are retrieved per pixel: a weighted
+ * least-squares fit of log s_j (weights s_j) to the log of the shifted, attenuated Gaussian
+ * flat IC gives T and Delta; P_mu = -log T, P_delta = trapezoid integral of Delta/kappa along
+ * t minus the ramp that zeroes both ends; each is filtered with the Ram-Lak kernel (Kak &
+ * Slaney, unit spacing), scaled by pi/n_theta and backprojected with R^T.
+ * s_exp device float[n_theta][n_mask][n_det] -> x_out device float[2][n][n].
+ * Workspace: eit_workspace_bytes(plan, EIT_OP_SINGLE_SHOT, 0). Asynchronous. */
+int eit_single_shot(const eit_plan* plan, const float* s_exp, float* x_out, void* ws,
+                    size_t ws_bytes, void* stream);
+
 /* Minimise the cost from x (device float[2][n][n], raw units): x holds the start on entry
  * and x_K on return. L-BFGS (memory opts->lbfgs_m, compact representation, FP64 dot
  * products) with Armijo backtracking, entirely device-resident; one accepted step per

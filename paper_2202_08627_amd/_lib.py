@@ -85,6 +85,7 @@ _PROTOS = {
     "eit_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(VP), C.c_int32]),
     "eit_reconstruct_batch": (C.c_int, [C.c_int32, C.POINTER(VP), C.POINTER(VP), C.POINTER(VP),
                                         C.POINTER(Opts), C.POINTER(Report), VP, C.c_size_t, VP]),
+    "eit_single_shot": (C.c_int, [VP, VP, VP, VP, C.c_size_t, VP]),
     "eit_last_error": (C.c_char_p, []),
     "eit_variant_info": (C.c_int, [C.c_int32, C.c_int32, IP, IP, IP, IP]),
     "eit_plan_inspect": (C.c_int, [C.POINTER(Dims), C.POINTER(Setup), C.POINTER(Tiling),

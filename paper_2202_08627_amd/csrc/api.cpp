@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "eit_internal.h"
@@ -456,6 +458,7 @@ extern "C" size_t eit_workspace_bytes(const eit_plan* p, int32_t op, int32_t m) 
         case EIT_OP_PROJECT: return eval_layout(p, false).end;
         case EIT_OP_BACKPROJECT: return eval_layout(p, false).end;
         case EIT_OP_COST_GRAD: return eval_layout(p, true).end;
+        case EIT_OP_SINGLE_SHOT: return eval_layout(p, true).end;
         case EIT_OP_RECONSTRUCT:
             if (m < 1 || m > EIT_MAX_LBFGS_M) return 0;
             return solve_layout(p, m).end;
@@ -544,6 +547,27 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
     if (grad)
         HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp,
                                    grid_for(p->n_it_bp, kGridCap), 1, st));
+    return EIT_OK;
+}
+
+extern "C" int eit_single_shot(const eit_plan* p, const float* s_exp, float* x_out, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!p) return fail(EIT_ERR_INVALID_ARG, "plan is NULL");
+    if (!s_exp || !x_out) return fail(EIT_ERR_INVALID_ARG, "s_exp or x_out is NULL");
+    const EvalLayout L = eval_layout(p, true);
+    if (int rc = check_ws(ws, ws_bytes, L.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    SliceDesc d = base_desc(p);
+    d.P = (float*)at(ws, L.P);
+    d.s_exp = s_exp;
+    d.g = x_out;
+    SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
+    HIP_TRY(launch_store_desc(d, dd, st));
+    const int gi = grid_for(p->n_it_ic, kGridCap);
+    HIP_TRY(launch_ss_retrieve(dd, p->it_ic, p->n_it_ic, gi, st));
+    HIP_TRY(launch_ss_filter(dd, p->it_ic, p->n_it_ic, gi, st));
+    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
+                               0, st));
     return EIT_OK;
 }
 
@@ -725,6 +749,48 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
     return rc;
 }
 
+
+// Descriptors of one slice's optimiser run whose buffers start at `base` with layout S.
+void solver_descs(const eit_plan* p, const eit_opts* o, void* base, const SolveLayout& S,
+                  const float* s_exp, float* x, double* cost_hist, SliceDesc& d, LbDesc& l) {
+    SolverState* state = (SolverState*)at(base, S.state);
+    d = base_desc(p);
+    d.x = (const float*)at(base, S.zt);
+    d.xT = (float*)at(base, S.ev.xT);
+    d.P = (float*)at(base, S.ev.P);
+    d.s_exp = s_exp;
+    d.g = (float*)at(base, S.gt);
+    d.part_ic = (double*)at(base, S.ev.part_ic);
+    d.part_reg = (double*)at(base, S.ev.part_reg);
+    d.cost = &state->f_t;
+    d.scale_mu = o->mu_scale; d.scale_de = o->delta_scale;
+    d.lam_mu = o->lam; d.lam_de = o->lam;
+    d.reg_mu = 2.0 * o->lam; d.reg_de = 2.0 * o->lam;
+    d.skip = &state->skip;
+    d.skip_adj = &state->skip_adj;
+    l = LbDesc{};
+    l.nv = p->nv; l.n = p->n; l.n_vblocks = p->n_vblocks;
+    l.scale_mu = (float)o->mu_scale; l.scale_de = (float)o->delta_scale;
+    l.z = (float*)at(base, S.z); l.zt = (float*)at(base, S.zt); l.g = (float*)at(base, S.g);
+    l.gt = (float*)at(base, S.gt); l.d = (float*)at(base, S.d);
+    l.S = (float*)at(base, S.S); l.Y = (float*)at(base, S.Y);
+    l.part = (double*)at(base, S.part);
+    l.st = state;
+    l.x_user = x;
+    l.cost_hist = cost_hist;
+}
+
+void fill_report(const SolverState& hs, int launches, eit_report* rep) {
+    rep->status = hs.status == ST_DONE ? EIT_OK : hs.status;
+    rep->iters = hs.k;
+    rep->evals = hs.evals;
+    rep->launches = launches;
+    rep->cost = hs.f;
+    rep->gnorm = std::sqrt(hs.gg);
+    for (int i = 0; i < EIT_N_PHASES; ++i) rep->phase_ms[i] = 0.0;
+    rep->phase_steps = 0;
+}
+
 }  // namespace
 
 extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_opts* o, float* x,
@@ -738,32 +804,9 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     hipStream_t st = (hipStream_t)stream;
 
     SolverState* state = (SolverState*)at(ws, S.state);
-    SliceDesc d = base_desc(p);
-    d.x = (const float*)at(ws, S.zt);
-    d.xT = (float*)at(ws, S.ev.xT);
-    d.P = (float*)at(ws, S.ev.P);
-    d.s_exp = s_exp;
-    d.g = (float*)at(ws, S.gt);
-    d.part_ic = (double*)at(ws, S.ev.part_ic);
-    d.part_reg = (double*)at(ws, S.ev.part_reg);
-    d.cost = &state->f_t;
-    d.scale_mu = o->mu_scale; d.scale_de = o->delta_scale;
-    d.lam_mu = o->lam; d.lam_de = o->lam;
-    d.reg_mu = 2.0 * o->lam; d.reg_de = 2.0 * o->lam;
-    d.skip = &state->skip;
-    d.skip_adj = &state->skip_adj;
-
-    LbDesc l{};
-    l.nv = p->nv; l.n = p->n; l.n_vblocks = p->n_vblocks;
-    l.scale_mu = (float)o->mu_scale; l.scale_de = (float)o->delta_scale;
-    l.z = (float*)at(ws, S.z); l.zt = (float*)at(ws, S.zt); l.g = (float*)at(ws, S.g);
-    l.gt = (float*)at(ws, S.gt); l.d = (float*)at(ws, S.d);
-    l.S = (float*)at(ws, S.S); l.Y = (float*)at(ws, S.Y);
-    l.part = (double*)at(ws, S.part);
-    l.st = state;
-    l.x_user = x;
-    l.cost_hist = cost_hist;
-
+    SliceDesc d;
+    LbDesc l;
+    solver_descs(p, o, ws, S, s_exp, x, cost_hist, d, l);
     SliceDesc* dd = (SliceDesc*)at(ws, S.ev.desc);
     LbDesc* ld = (LbDesc*)at(ws, S.lbdesc);
     HIP_TRY(launch_store_desc(d, dd, st));
@@ -789,14 +832,7 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     HIP_TRY(hipMemcpyAsync(&hs, state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (rep) {
-        rep->status = hs.status == ST_DONE ? EIT_OK : hs.status;
-        rep->iters = hs.k;
-        rep->evals = hs.evals;
-        rep->launches = launches;
-        rep->cost = hs.f;
-        rep->gnorm = std::sqrt(hs.gg);
-        for (int i = 0; i < EIT_N_PHASES; ++i) rep->phase_ms[i] = 0.0;
-        rep->phase_steps = 0;
+        fill_report(hs, launches, rep);
         if (pt) {
             if (int rc = pt->collect()) return rc;
             for (int i = 0; i < EIT_N_PHASES; ++i) rep->phase_ms[i] = pt->ms[i];
@@ -839,9 +875,157 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
     return 0;
 }
 
-extern "C" size_t eit_batch_workspace_bytes(int32_t, const eit_plan* const*, int32_t) { return 0; }
-extern "C" int eit_reconstruct_batch(int32_t, const eit_plan* const*, const float* const*,
-                                     float* const*, const eit_opts*, eit_report*, void*, size_t,
-                                     void*) {
-    return fail(EIT_ERR_INVALID_ARG, "batched reconstruction not built yet");
+// ============================================================================ batch
+namespace {
+
+struct BatchLayout {
+    size_t descs = 0, lbdescs = 0, items = 0, end = 0;
+    std::vector<size_t> slice;        // per-slice solve layout base
+    std::vector<int> order;           // slices by decreasing work
+    std::vector<Item> items_h;        // all work items, grouped by launch
+    // item ranges (offset, count) in items_h
+    std::pair<int, int> r_dir, r_ic, r_vec;
+    std::vector<std::tuple<int, int, int, size_t>> r_proj, r_adj;   // variant, off, count, lds
+};
+
+int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout& B) {
+    if (n < 1) return fail(EIT_ERR_INVALID_ARG, "n_slices must be >= 1");
+    if (!plans) return fail(EIT_ERR_INVALID_ARG, "plans is NULL");
+    if (m < 1 || m > EIT_MAX_LBFGS_M) return fail(EIT_ERR_INVALID_ARG, "lbfgs_m=%d out of range", m);
+    for (int i = 0; i < n; ++i)
+        if (!plans[i]) return fail(EIT_ERR_INVALID_ARG, "plans[%d] is NULL", i);
+    B.order.resize(n);
+    for (int i = 0; i < n; ++i) B.order[i] = i;
+    auto work = [&](int i) { return (double)plans[i]->n * plans[i]->n * plans[i]->n_theta; };
+    std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) { return work(a) > work(b); });
+    // items: direction tiles, IC angles, vector chunks, then projector / adjoint per variant
+    auto& H = B.items_h;
+    H.clear();
+    B.r_dir.first = 0;
+    for (int i : B.order)
+        for (int ty = 0; ty < plans[i]->n_trx; ++ty)
+            for (int tx = 0; tx < plans[i]->n_trx; ++tx) H.push_back(make_int4(i, tx, ty, 0));
+    B.r_dir.second = (int)H.size();
+    B.r_ic.first = (int)H.size();
+    for (int i : B.order)
+        for (int a = 0; a < plans[i]->n_theta; ++a) H.push_back(make_int4(i, a, 0, 0));
+    B.r_ic.second = (int)H.size() - B.r_ic.first;
+    B.r_vec.first = (int)H.size();
+    for (int i : B.order)
+        for (int b = 0; b < plans[i]->n_vblocks; ++b) H.push_back(make_int4(i, b, 0, 0));
+    B.r_vec.second = (int)H.size() - B.r_vec.first;
+    B.r_proj.clear();
+    B.r_adj.clear();
+    for (int v = 0; v < proj_variant_count(); ++v) {
+        const int off = (int)H.size();
+        size_t lds = 0;
+        for (int i : B.order) {
+            const eit_plan* p = plans[i];
+            if (p->proj_v != v) continue;
+            lds = std::max(lds, p->proj_lds);
+            for (int g = 0; g < p->n_groups; ++g)
+                for (int b = 0; b < p->n_dblk; ++b) H.push_back(make_int4(i, g, b, 0));
+        }
+        if ((int)H.size() > off) B.r_proj.emplace_back(v, off, (int)H.size() - off, lds);
+    }
+    for (int v = 0; v < adj_variant_count(); ++v) {
+        const int off = (int)H.size();
+        for (int i : B.order) {
+            const eit_plan* p = plans[i];
+            if (p->adj_v != v) continue;
+            for (int ty = 0; ty < p->n_ty; ++ty)
+                for (int tx = 0; tx < p->n_tx; ++tx) H.push_back(make_int4(i, tx, ty, 0));
+        }
+        if ((int)H.size() > off) B.r_adj.emplace_back(v, off, (int)H.size() - off, (size_t)0);
+    }
+    Layout L;
+    B.descs = L.take(sizeof(SliceDesc) * n);
+    B.lbdescs = L.take(sizeof(LbDesc) * n);
+    B.items = L.take(sizeof(Item) * H.size());
+    B.slice.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t base = L.off;
+        B.slice[i] = base;
+        L.off = base + solve_layout(plans[i], m).end;
+        L.off = align_up(L.off, 256);
+    }
+    B.end = L.off;
+    return EIT_OK;
+}
+
+}  // namespace
+
+extern "C" size_t eit_batch_workspace_bytes(int32_t n, const eit_plan* const* plans, int32_t m) {
+    BatchLayout B;
+    if (batch_layout(n, plans, m, B)) return 0;
+    return B.end;
+}
+
+extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
+                                     const float* const* s_exp, float* const* x,
+                                     const eit_opts* o, eit_report* reps, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    if (int rc = validate_opts(o)) return rc;
+    BatchLayout B;
+    if (int rc = batch_layout(n, plans, o->lbfgs_m, B)) return rc;
+    if (!s_exp || !x) return fail(EIT_ERR_INVALID_ARG, "s_exp or x is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!s_exp[i] || !x[i]) return fail(EIT_ERR_INVALID_ARG, "s_exp[%d] or x[%d] is NULL", i, i);
+    if (int rc = check_ws(ws, ws_bytes, B.end)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+
+    std::vector<SliceDesc> dh(n);
+    std::vector<LbDesc> lh(n);
+    std::vector<SolverState*> states(n);
+    for (int i = 0; i < n; ++i) {
+        void* base = at(ws, B.slice[i]);
+        const SolveLayout S = solve_layout(plans[i], o->lbfgs_m);
+        solver_descs(plans[i], o, base, S, s_exp[i], x[i], nullptr, dh[i], lh[i]);
+        states[i] = lh[i].st;
+    }
+    SliceDesc* dd = (SliceDesc*)at(ws, B.descs);
+    LbDesc* ld = (LbDesc*)at(ws, B.lbdescs);
+    Item* it = (Item*)at(ws, B.items);
+    HIP_TRY(hipMemcpyAsync(dd, dh.data(), sizeof(SliceDesc) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ld, lh.data(), sizeof(LbDesc) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(it, B.items_h.data(), sizeof(Item) * B.items_h.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));      // host staging arrays may be released after this
+
+    HIP_TRY(launch_lb_init(ld, n, o->lbfgs_m, o->max_iter, o->max_ls_trials, o->c1, o->tol_rel_step, st));
+    const Item* it_vec = it + B.r_vec.first;
+    const int n_vec = B.r_vec.second;
+    HIP_TRY(launch_lb_scale(ld, it_vec, n_vec, grid_for(n_vec, kGridCap), 1, st));
+
+    StepPlan sp;
+    sp.D = dd; sp.L = ld; sp.n_slices = n;
+    for (auto& r : B.r_proj)
+        sp.proj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r)});
+    for (auto& r : B.r_adj)
+        sp.adj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r)});
+    sp.it_tr = it + B.r_dir.first; sp.n_tr = B.r_dir.second;
+    sp.it_ic = it + B.r_ic.first; sp.n_ic = B.r_ic.second;
+    sp.it_vec = it_vec; sp.n_vec = n_vec;
+    int launches = 0;
+    PhaseTimer timer;
+    PhaseTimer* pt = o->profile ? &timer : nullptr;
+    if (int rc = drive(sp, states, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches, pt))
+        return rc;
+    HIP_TRY(launch_lb_scale(ld, it_vec, n_vec, grid_for(n_vec, kGridCap), 0, st));
+    std::vector<SolverState> hs(n);
+    for (int i = 0; i < n; ++i)
+        HIP_TRY(hipMemcpyAsync(&hs[i], states[i], sizeof(SolverState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int worst = EIT_OK;
+    for (int i = 0; i < n; ++i) {
+        if (reps) fill_report(hs[i], launches, &reps[i]);
+        if (hs[i].status < 0 && worst == EIT_OK) worst = hs[i].status;
+    }
+    if (pt && reps) {
+        if (int rc = pt->collect()) return rc;
+        for (int i = 0; i < EIT_N_PHASES; ++i) reps[0].phase_ms[i] = pt->ms[i];
+        reps[0].phase_steps = pt->steps;
+    }
+    if (worst) return fail(worst, "at least one slice stopped with an error (see reports)");
+    return EIT_OK;
 }

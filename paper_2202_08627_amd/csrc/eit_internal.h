@@ -136,6 +136,12 @@ hipError_t launch_cost_reduce(const SliceDesc* d_descs, int n_slices, hipStream_
 hipError_t launch_backproject(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
                               int grid, int add_reg, hipStream_t s);
 
+// single-shot reconstruction (single_shot.hip)
+hipError_t launch_ss_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,
+                              hipStream_t s);
+hipError_t launch_ss_filter(const SliceDesc* D, const Item* items, int n_items, int grid,
+                            hipStream_t s);
+
 // projector/adjoint variant registry
 int proj_variant_count();
 ProjTile proj_variant(int v);

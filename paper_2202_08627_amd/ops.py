@@ -193,6 +193,15 @@ class Plan:
                                           ws.numel(), _stream()))
         return cost, grad
 
+    def single_shot(self, s_exp, out=None, ws=None):
+        """Single-shot (retrieve + filtered backprojection) reconstruction [2][n][n]."""
+        _require(s_exp, self.data_shape, name="s_exp")
+        out = torch.empty(self.x_shape, dtype=torch.float32, device=s_exp.device) if out is None else out
+        ws = self.workspace(L.EIT_OP_SINGLE_SHOT) if ws is None else ws
+        L.check(L.lib().eit_single_shot(self.handle, _ptr(s_exp), _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream()))
+        return out
+
     def reconstruct(self, s_exp, x0=None, iters: int = 50, lam: float = 1e-2, mu_scale: float = 0.05,
                     delta_scale: float = 1e-3, m: int = 10, max_ls: int = 20, tol_rel_step: float = 0.0,
                     c1: float = 1e-4, use_graph: bool = True, cost_hist: bool = False, ws=None,
@@ -218,6 +227,47 @@ class Plan:
             L.check(rc)
         report["rc"] = rc
         return x, report, hist
+
+
+def reconstruct_batch(plans, s_exps, x0s=None, iters: int = 50, lam: float = 1e-2,
+                      mu_scale=0.05, delta_scale=1e-3, m: int = 10, max_ls: int = 20,
+                      tol_rel_step: float = 0.0, c1: float = 1e-4, use_graph: bool = True,
+                      profile: bool = False, ws=None):
+    """Many independent slices (any mix of sizes) in one sequence of persistent launches.
+    The optimiser options are shared; mu_scale/delta_scale may be scalars (all slices share
+    one scaling; pass per-size scalings by grouping batches). Returns (list of x_K, reports)."""
+    n = len(plans)
+    if n == 0 or len(s_exps) != n:
+        raise ValueError("plans and s_exps must be non-empty and of equal length")
+    xs = []
+    for i, (p, s) in enumerate(zip(plans, s_exps)):
+        _require(s, p.data_shape, name=f"s_exps[{i}]")
+        if x0s is None:
+            xs.append(torch.zeros(p.x_shape, dtype=torch.float32, device=s.device))
+        else:
+            _require(x0s[i], p.x_shape, name=f"x0s[{i}]")
+            xs.append(x0s[i].clone())
+    H = (C.c_void_p * n)(*[p.handle for p in plans])
+    SP = (C.c_void_p * n)(*[s.data_ptr() for s in s_exps])
+    XP = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    mm = min(max(m, 1), 20)
+    nb = int(L.lib().eit_batch_workspace_bytes(n, H, mm))
+    if nb == 0:
+        L.check(L.EIT_ERR_INVALID_ARG)
+    ws = torch.empty(nb, dtype=torch.uint8, device=s_exps[0].device) if ws is None else ws
+    opts = L.Opts(iters, m, max_ls, 1 if use_graph else 0, lam, float(mu_scale), float(delta_scale),
+                  tol_rel_step, c1, 1 if profile else 0, 0)
+    reps = (L.Report * n)()
+    rc = L.lib().eit_reconstruct_batch(n, H, SP, XP, C.byref(opts), reps, _ptr(ws), ws.numel(),
+                                       _stream())
+    if rc not in (L.EIT_OK, L.EIT_ERR_LINESEARCH, L.EIT_ERR_NONFINITE):
+        L.check(rc)
+    out = []
+    for r in reps:
+        d = {f: getattr(r, f) for f, _ in L.Report._fields_ if f not in ("phase_ms", "pad")}
+        d["phase_ms"] = dict(zip(L.PHASES, list(r.phase_ms)))
+        out.append(d)
+    return xs, out
 
 
 class EITCost(torch.autograd.Function):
