@@ -237,6 +237,54 @@ const char* eit_last_error(void);
  * fills a/b/c/d (each may be NULL) for index v if in range. */
 int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c, int32_t* d);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned warm start. Not part of the paper's method: a 2-D U-Net maps the two-channel
+ * single-shot reconstruction (eq. 3 style retrieval followed by filtered backprojection,
+ * eit_single_shot) to a starting point for the iterative minimisation of eq. 5.
+ * Architecture: 4 levels with base, 2*base, 4*base, 8*base channels; two 3x3 convolutions
+ * (zero padding) with ReLU per level; 2x2 max pooling down; 2x2 stride-2 transposed
+ * convolutions up, concatenated before the skip connection ([up, skip] channel order); a
+ * 1x1 head with two outputs added to the input (residual). Products in BF16 on the matrix
+ * cores with FP32 accumulation; parameters, gradients and Adam moments in FP32.
+ *
+ * Parameter vector (FP32, device): layers in the order returned by eit_unet_layers, each
+ * its weights followed directly by its bias (cout floats):
+ *   kind 0, 3x3 conv:        W[cout][ky*3 + kx][cin]
+ *   kind 1, 2x2 up-conv:     W[cout][dy*2 + dx][cin]   (output pixel (2y + dy, 2x + dx))
+ *   kind 2, 1x1 head:        W[2][cin]
+ * Images: FP32 [batch][2][h][w] (channel 0 = mu, channel 1 = delta, both normalised by the
+ * caller), h and w multiples of 8. Workspace: eit_unet_workspace_bytes, device memory owned
+ * by the caller; contents on return are scratch. All device pointers must stay valid until
+ * the stream has drained. Errors as for the reconstruction calls (EIT_ERR_SHAPE for sizes,
+ * EIT_ERR_NOMEM for a short workspace, EIT_ERR_DEVICE for a failed launch). */
+typedef struct eit_unet eit_unet;
+typedef struct {
+    int32_t kind, cin, cout, pad;
+    int64_t w_off, b_off;   /* offsets (in floats) of weights and bias in the parameter vector */
+} eit_unet_layer;
+
+/* base: channels of the first level, a power of two in [8, 64]. Host-only. */
+int eit_unet_create(int32_t base, eit_unet** out);
+void eit_unet_destroy(eit_unet* net);
+int64_t eit_unet_param_count(const eit_unet* net);
+/* Fills up to cap entries of out (may be NULL) and returns the number of layers. */
+int eit_unet_layers(const eit_unet* net, eit_unet_layer* out, int32_t cap);
+/* 0 for invalid sizes; train != 0 sizes the workspace of eit_unet_train_step. */
+size_t eit_unet_workspace_bytes(const eit_unet* net, int32_t batch, int32_t h, int32_t w,
+                                int32_t train);
+/* y = net(x) for a batch; params is the FP32 parameter vector. Asynchronous on stream. */
+int eit_unet_forward(const eit_unet* net, const float* params, const float* x, float* y,
+                     int32_t batch, int32_t h, int32_t w, void* ws, size_t ws_bytes, void* stream);
+/* One step on the mean squared error over all batch*2*h*w outputs: writes grad (FP32, the
+ * parameter layout, overwritten) and *loss (device double). If step >= 1, also applies Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias correction for that step number) with learning
+ * rate lr to params in place, updating adam_m and adam_v; step <= 0 computes the gradient
+ * only (adam_m / adam_v may then be NULL). Asynchronous on stream. */
+int eit_unet_train_step(const eit_unet* net, float* params, float* adam_m, float* adam_v,
+                        float* grad, int32_t step, double lr, const float* x,
+                        const float* target, int32_t batch, int32_t h, int32_t w, double* loss,
+                        void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,13 +22,20 @@ BF16 emulation (bf16=True): the device multiplies BF16 operands and accumulates 
 The same values are produced here by rounding, to BF16 with round-to-nearest-even, exactly
 the tensors the device stores in BF16: the packed input, the conv and up-conv weights
 (straight-through: the gradient goes to the FP32 master weight), every conv / up-conv /
-pool output, and the gradient arriving at each of those tensors. The head, the loss and all
-weight gradients stay in full precision. With bf16=False this is a plain FP64 U-Net.
+pool output, and the gradient arriving at each of those tensors. The gradient reaching a
+skip tensor through the concatenation is rounded on its own before the pooled path's
+gradient is added to it and the sum is rounded again (the device stores the first in BF16
+and accumulates the second onto it). The head, the loss and all weight gradients stay in
+full precision. With bf16=False this is a plain FP64 U-Net. dtype=float32 runs the same
+emulation with FP32 accumulation: the gap between the two measures how far any other
+accumulation order may drift after BF16 rounding.
 
 Pins (tests/test_oracle_unet.py): autograd gradient vs central finite differences of the
-FP64 loss; a brute-force loop convolution and transposed convolution with the documented
-weight layouts; zero head => output equals input; translation equivariance of the
-convolutional trunk; the Adam update against its closed form on a scalar.
+FP64 loss; brute-force loop convolution and transposed convolution with the documented
+weight layouts; zero head => output equals input; spatial transposition of image and
+kernels transposes the output (tap order); batch items independent; padded input channels
+get zero gradient; max-pool gradient to the first maximum; BF16 rounding to nearest even;
+the Adam update against its closed form.
 """
 from __future__ import annotations
 
@@ -144,7 +151,7 @@ def forward(params: torch.Tensor, x: torch.Tensor, base: int, bf16_emul: bool = 
     skips = []
     for lvl in range(3):
         h = conv(conv(h))
-        skips.append(h)
+        skips.append(q(h))          # forward: no-op; backward: rounds the concat-path gradient
         h = q(F.max_pool2d(h, 2))
     h = conv(conv(h))
     for lvl in range(3):
@@ -156,21 +163,23 @@ def forward(params: torch.Tensor, x: torch.Tensor, base: int, bf16_emul: bool = 
 
 
 def loss_and_grad(params: np.ndarray, x: np.ndarray, target: np.ndarray, base: int,
-                  bf16_emul: bool = False):
-    """Mean squared error over all outputs and its gradient with respect to params (FP64)."""
-    p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
-    xt = torch.tensor(np.asarray(x, dtype=np.float64))
-    tt = torch.tensor(np.asarray(target, dtype=np.float64))
+                  bf16_emul: bool = False, dtype=torch.float64):
+    """Mean squared error over all outputs and its gradient with respect to params."""
+    p = torch.tensor(np.asarray(params, dtype=np.float64), dtype=dtype, requires_grad=True)
+    xt = torch.tensor(np.asarray(x, dtype=np.float64), dtype=dtype)
+    tt = torch.tensor(np.asarray(target, dtype=np.float64), dtype=dtype)
     out = forward(p, xt, base, bf16_emul)
     loss = torch.mean((out - tt) ** 2)
     loss.backward()
-    return float(loss.detach()), p.grad.numpy().copy()
+    return float(loss.detach()), p.grad.double().numpy().copy()
 
 
-def predict(params: np.ndarray, x: np.ndarray, base: int, bf16_emul: bool = False) -> np.ndarray:
+def predict(params: np.ndarray, x: np.ndarray, base: int, bf16_emul: bool = False,
+            dtype=torch.float64) -> np.ndarray:
     with torch.no_grad():
-        p = torch.tensor(np.asarray(params, dtype=np.float64))
-        return forward(p, torch.tensor(np.asarray(x, dtype=np.float64)), base, bf16_emul).numpy()
+        p = torch.tensor(np.asarray(params, dtype=np.float64), dtype=dtype)
+        xt = torch.tensor(np.asarray(x, dtype=np.float64), dtype=dtype)
+        return forward(p, xt, base, bf16_emul).double().numpy()
 
 
 def adam(p, m, v, g, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):

@@ -68,6 +68,11 @@ class PlanInfo(C.Structure):
         "n_tx", "n_ty")] + [("proj_lds_bytes", C.c_int64)]
 
 
+class UNetLayer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("cin", C.c_int32), ("cout", C.c_int32), ("pad", C.c_int32),
+                ("w_off", C.c_int64), ("b_off", C.c_int64)]
+
+
 _lib = None
 
 VP = C.c_void_p
@@ -90,6 +95,14 @@ _PROTOS = {
     "eit_variant_info": (C.c_int, [C.c_int32, C.c_int32, IP, IP, IP, IP]),
     "eit_plan_inspect": (C.c_int, [C.POINTER(Dims), C.POINTER(Setup), C.POINTER(Tiling),
                                    C.POINTER(PlanInfo), DP, IP, IP, DP]),
+    "eit_unet_create": (C.c_int, [C.c_int32, C.POINTER(VP)]),
+    "eit_unet_destroy": (None, [VP]),
+    "eit_unet_param_count": (C.c_int64, [VP]),
+    "eit_unet_layers": (C.c_int, [VP, C.POINTER(UNetLayer), C.c_int32]),
+    "eit_unet_workspace_bytes": (C.c_size_t, [VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "eit_unet_forward": (C.c_int, [VP, VP, VP, VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_size_t, VP]),
+    "eit_unet_train_step": (C.c_int, [VP, VP, VP, VP, VP, C.c_int32, C.c_double, VP, VP, C.c_int32,
+                                      C.c_int32, C.c_int32, VP, VP, C.c_size_t, VP]),
 }
 
 

@@ -1029,3 +1029,8 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     if (worst) return fail(worst, "at least one slice stopped with an error (see reports)");
     return EIT_OK;
 }
+
+namespace eit {
+// error reporting for the network entry points (unet.cpp) through the same thread-local message
+int nn_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace eit

@@ -1,0 +1,56 @@
+// Internal declarations of the warm-start network kernels (nn_kernels.hip, nn_misc.hip) and
+// their host orchestration (unet.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace eit {
+namespace nn {
+
+typedef __bf16 bf16;
+
+// NHWC view: element (b, y, x, c) at p[((b*H + y)*W + x)*cs + coff + c]. C is the view's
+// channel count (a power of two >= 8), cs the stride of the underlying buffer, coff the
+// view's first channel (multiples of 8 keep 16-byte alignment).
+struct Tensor {
+    bf16* p;
+    int B, H, W, C, cs, coff;
+};
+
+// GEMM-based layers (nn_kernels.hip)
+hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu, const Tensor& y,
+                    int ksize, hipStream_t s);
+hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s);
+hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
+                      hipStream_t s);
+hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
+                      hipStream_t s);
+hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s);
+hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s);
+
+// element-wise and reduction kernels (nn_misc.hip)
+hipError_t pack_input(const float* x, int B, int H, int W, const Tensor& out, hipStream_t s);
+hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s);
+hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
+                           hipStream_t s);
+hipError_t relu_mask(const Tensor& y, const Tensor& dy, hipStream_t s);     // dy *= (y > 0)
+hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s);
+hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s);
+hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in,
+                    float* out, int B, int H, int W, hipStream_t s);
+hipError_t mse_loss(const float* out, const float* target, size_t n, double* part, int nblk,
+                    double* loss, float* dout, hipStream_t s);
+hipError_t head_bwd(const Tensor& a, const float* w, const float* dout, int B, int H, int W,
+                    float* dw, float* db, float* part, int nblk, const Tensor& da, hipStream_t s);
+hipError_t to_bf16(const float* src, bf16* dst, size_t n, hipStream_t s);
+// dst[i][t][o] = src[o][t][i] for src of shape [O][T][I] (weight transposes for dgrad)
+hipError_t transpose_oti(const float* src, bf16* dst, int O, int T, int I, hipStream_t s);
+hipError_t adam(float* p, float* m, float* v, const float* g, size_t n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s);
+
+constexpr int kSumBlocks = 256;   // partial-sum blocks of the deterministic reductions
+
+}  // namespace nn
+}  // namespace eit

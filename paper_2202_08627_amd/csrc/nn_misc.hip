@@ -1,0 +1,285 @@
+// Element-wise and reduction kernels of the warm-start network: input packing, 2x2 max
+// pooling and its gradient, ReLU masks, deterministic channel sums, split-K reduction, the
+// 1x1 residual head, the MSE loss and Adam with FP32 master weights.
+#include <algorithm>
+
+#include "nn_internal.h"
+#include "reduce.h"
+
+namespace eit {
+namespace nn {
+
+__device__ __forceinline__ size_t at4(const Tensor& t, int b, int y, int x, int c) {
+    return ((size_t)(b * t.H + y) * t.W + x) * t.cs + t.coff + c;
+}
+
+constexpr int kT = 256;
+inline int nblocks(size_t n) { return (int)std::min<size_t>((n + kT - 1) / kT, 65535 * 8); }
+
+// FP32 [B][2][H][W] -> NHWC BF16 with 8 channels (channels 2..7 zero)
+__global__ void k_pack(const float* x, int B, int H, int W, Tensor o) {
+    const size_t n = (size_t)B * H * W;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
+        bf16* q = o.p + at4(o, b, y, xx, 0);
+        q[0] = (bf16)x[((size_t)(b * 2 + 0) * H + y) * W + xx];
+        q[1] = (bf16)x[((size_t)(b * 2 + 1) * H + y) * W + xx];
+        for (int c = 2; c < o.C; ++c) q[c] = (bf16)0.f;
+    }
+}
+
+__global__ void k_pool(Tensor x, Tensor y) {
+    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % y.C;
+        const size_t p = e / y.C;
+        const int xx = p % y.W, yb = p / y.W, yy = yb % y.H, b = yb / y.H;
+        float m = (float)x.p[at4(x, b, 2 * yy, 2 * xx, c)];
+        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy, 2 * xx + 1, c)]);
+        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy + 1, 2 * xx, c)]);
+        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy + 1, 2 * xx + 1, c)]);
+        y.p[at4(y, b, yy, xx, c)] = (bf16)m;
+    }
+}
+
+// The gradient goes to the first input (row-major in the window) equal to the maximum.
+__global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
+    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % y.C;
+        const size_t p = e / y.C;
+        const int xx = p % y.W, yb = p / y.W, yy = yb % y.H, b = yb / y.H;
+        const float m = (float)y.p[at4(y, b, yy, xx, c)];
+        const float g = (float)dy.p[at4(dy, b, yy, xx, c)];
+        bool done = false;
+        for (int q = 0; q < 4; ++q) {
+            const int iy = 2 * yy + (q >> 1), ix = 2 * xx + (q & 1);
+            if (!done && (float)x.p[at4(x, b, iy, ix, c)] == m) {
+                const size_t o = at4(dx, b, iy, ix, c);
+                dx.p[o] = (bf16)((float)dx.p[o] + g);
+                done = true;
+            }
+        }
+    }
+}
+
+__global__ void k_relu_mask(Tensor y, Tensor dy) {
+    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % y.C;
+        const size_t p = e / y.C;
+        if (!((float)y.p[p * y.cs + y.coff + c] > 0.f)) dy.p[p * dy.cs + dy.coff + c] = (bf16)0.f;
+    }
+}
+
+// Stage 1: block k sums pixels [k*P/nblk, (k+1)*P/nblk) of every channel -> part[k][C].
+__global__ __launch_bounds__(kT) void k_chsum1(Tensor t, float* part, int nblk) {
+    __shared__ float red[kT];
+    const size_t P = (size_t)t.B * t.H * t.W;
+    const size_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
+    const int C = t.C;
+    const int per = kT / C > 0 ? kT / C : 1;        // pixel lanes per channel
+    for (int c0 = 0; c0 < C; c0 += kT) {
+        const int c = c0 + (C >= kT ? threadIdx.x : threadIdx.x % C);
+        const int lanep = C >= kT ? 0 : threadIdx.x / C;
+        float s = 0.f;
+        if (c < C && lanep < per)
+            for (size_t p = p0 + lanep; p < p1; p += per) s += (float)t.p[p * t.cs + t.coff + c];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if (C >= kT) {
+            if (c < C) part[(size_t)blockIdx.x * C + c] = red[threadIdx.x];
+        } else if (threadIdx.x < C) {
+            float v = 0.f;
+            for (int q = 0; q < per; ++q) v += red[q * C + threadIdx.x];
+            part[(size_t)blockIdx.x * C + threadIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+__global__ void k_chsum2(const float* part, int nblk, int C, float* out) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < nblk; ++k) s += part[(size_t)k * C + c];
+        out[c] = s;
+    }
+}
+
+__global__ void k_splitk(const float* part, int splits, int n, float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
+        out[i] = s;
+    }
+}
+
+// out[b][o][y][x] = x_in[b][o][y][x] + b[o] + sum_c a[b,y,x,c] w[o][c]   (two outputs)
+__global__ void k_head(Tensor a, const float* w, const float* bias, const float* x_in, float* out,
+                       int B, int H, int W) {
+    const size_t n = (size_t)B * H * W;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
+        const bf16* q = a.p + p * a.cs + a.coff;
+        float s0 = bias[0], s1 = bias[1];
+        for (int c = 0; c < a.C; ++c) {
+            const float v = (float)q[c];
+            s0 = fmaf(v, w[c], s0);
+            s1 = fmaf(v, w[a.C + c], s1);
+        }
+        const size_t o0 = ((size_t)(b * 2 + 0) * H + y) * W + xx, o1 = ((size_t)(b * 2 + 1) * H + y) * W + xx;
+        out[o0] = x_in[o0] + s0;
+        out[o1] = x_in[o1] + s1;
+    }
+}
+
+// MSE: part[k] = sum over the block's slice of (out - target)^2 (FP64); dout = 2 (out - t) / n
+__global__ __launch_bounds__(kT) void k_mse1(const float* out, const float* t, size_t n, double* part,
+                                             int nblk, float* dout) {
+    __shared__ double red[kT / 64];
+    const size_t i0 = n * blockIdx.x / nblk, i1 = n * (blockIdx.x + 1) / nblk;
+    double s = 0.0;
+    for (size_t i = i0 + threadIdx.x; i < i1; i += kT) {
+        const float r = out[i] - t[i];
+        s += (double)r * r;
+        if (dout) dout[i] = 2.f * r / (float)n;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ void k_mse2(const double* part, int nblk, size_t n, double* loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < nblk; ++k) s += part[k];
+        *loss = s / (double)n;
+    }
+}
+
+// head backward: part[k][0..2C) = sum over the block's pixels of dout[o] * a[c] for o = 0, 1;
+// part[k][2C..2C+2) = sum of dout[o]; da = (W^T dout) masked by a > 0 (a is post-ReLU).
+__global__ __launch_bounds__(kT) void k_head_bwd1(Tensor a, const float* w, const float* dout,
+                                                  int B, int H, int W, float* part, int nblk,
+                                                  Tensor da) {
+    __shared__ float red[kT];
+    const size_t P = (size_t)B * H * W;
+    const size_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
+    const int C = a.C;
+    // da for this block's pixels
+    for (size_t p = p0 + threadIdx.x; p < p1; p += kT) {
+        const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
+        const float g0 = dout[((size_t)(b * 2 + 0) * H + y) * W + xx];
+        const float g1 = dout[((size_t)(b * 2 + 1) * H + y) * W + xx];
+        const bf16* q = a.p + p * a.cs + a.coff;
+        bf16* dq = da.p + p * da.cs + da.coff;
+        for (int c = 0; c < C; ++c) {
+            const float v = fmaf(g0, w[c], g1 * w[C + c]);
+            dq[c] = (float)q[c] > 0.f ? (bf16)v : (bf16)0.f;
+        }
+    }
+    // weight / bias sums: thread handles entry e of [2C + 2] for a strided subset of pixels
+    const int E = 2 * C + 2;
+    for (int e0 = 0; e0 < E; e0 += kT) {
+        const int e = e0 + threadIdx.x;
+        float s = 0.f;
+        if (e < E) {
+            const int o = e < 2 * C ? e / C : e - 2 * C;
+            const int c = e < 2 * C ? e % C : -1;
+            for (size_t p = p0; p < p1; ++p) {
+                const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
+                const float g = dout[((size_t)(b * 2 + o) * H + y) * W + xx];
+                s += c >= 0 ? g * (float)a.p[p * a.cs + a.coff + c] : g;
+            }
+            part[(size_t)blockIdx.x * E + e] = s;
+        }
+    }
+}
+
+__global__ void k_tobf16(const float* s, bf16* d, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = (bf16)s[i];
+}
+
+__global__ void k_transpose_oti(const float* s, bf16* d, int O, int T, int I) {
+    const size_t n = (size_t)O * T * I;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = e % I;
+        const size_t r = e / I;
+        const int t = r % T, o = r / T;
+        d[((size_t)i * T + t) * O + o] = (bf16)s[e];
+    }
+}
+
+__global__ void k_adam(float* p, float* m, float* v, const float* g, size_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------------------- launchers
+hipError_t pack_input(const float* x, int B, int H, int W, const Tensor& o, hipStream_t s) {
+    k_pack<<<nblocks((size_t)B * H * W), kT, 0, s>>>(x, B, H, W, o);
+    return hipGetLastError();
+}
+hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s) {
+    k_pool<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(x, y);
+    return hipGetLastError();
+}
+hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
+                           hipStream_t s) {
+    k_pool_bwd<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(x, y, dy, dx);
+    return hipGetLastError();
+}
+hipError_t relu_mask(const Tensor& y, const Tensor& dy, hipStream_t s) {
+    k_relu_mask<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(y, dy);
+    return hipGetLastError();
+}
+hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s) {
+    k_chsum1<<<nblk, kT, 0, s>>>(t, part, nblk);
+    k_chsum2<<<(t.C + kT - 1) / kT, kT, 0, s>>>(part, nblk, t.C, out);
+    return hipGetLastError();
+}
+hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s) {
+    k_splitk<<<nblocks((size_t)n), kT, 0, s>>>(part, splits, n, out);
+    return hipGetLastError();
+}
+hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in, float* out,
+                    int B, int H, int W, hipStream_t s) {
+    k_head<<<nblocks((size_t)B * H * W), kT, 0, s>>>(a, w, b, x_in, out, B, H, W);
+    return hipGetLastError();
+}
+hipError_t mse_loss(const float* out, const float* target, size_t n, double* part, int nblk,
+                    double* loss, float* dout, hipStream_t s) {
+    k_mse1<<<nblk, kT, 0, s>>>(out, target, n, part, nblk, dout);
+    k_mse2<<<1, 64, 0, s>>>(part, nblk, n, loss);
+    return hipGetLastError();
+}
+hipError_t head_bwd(const Tensor& a, const float* w, const float* dout, int B, int H, int W,
+                    float* dw, float* db, float* part, int nblk, const Tensor& da, hipStream_t s) {
+    // the head's bias gradient must directly follow its weight gradient (db == dw + 2C)
+    if (db != dw + 2 * a.C) return hipErrorInvalidValue;
+    const int E = 2 * a.C + 2;
+    k_head_bwd1<<<nblk, kT, 0, s>>>(a, w, dout, B, H, W, part, nblk, da);
+    k_chsum2<<<1, kT, 0, s>>>(part, nblk, E, dw);     // fixed-order reduction of [nblk][E]
+    return hipGetLastError();
+}
+hipError_t to_bf16(const float* src, bf16* dst, size_t n, hipStream_t s) {
+    k_tobf16<<<nblocks(n), kT, 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+hipError_t transpose_oti(const float* src, bf16* dst, int O, int T, int I, hipStream_t s) {
+    k_transpose_oti<<<nblocks((size_t)O * T * I), kT, 0, s>>>(src, dst, O, T, I);
+    return hipGetLastError();
+}
+hipError_t adam(float* p, float* m, float* v, const float* g, size_t n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s) {
+    k_adam<<<nblocks(n), kT, 0, s>>>(p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace eit

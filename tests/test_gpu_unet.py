@@ -1,0 +1,230 @@
+"""Device U-Net (BF16 MFMA forward, data/weight gradients, loss, Adam) against the CPU
+oracle with BF16 storage emulation, through the C-ABI.
+
+Two kinds of check:
+  * Structured (exact): one-hot +-1 weights, biases and inputs on a 1/4 grid, a sparse
+    residual with a power-of-two element count. Every sum the forward pass and the data
+    gradients form is then exact in FP32, so the device output must equal the oracle's bit
+    for bit, and the weight / bias gradients (long FP32 sums over pixels) agree to 1e-5.
+    This pins every index, layout, lane mapping, tap order, concatenation, pooling route
+    and reduction of the kernels.
+  * Random weights (realistic): the device and the oracle round the same tensors to BF16,
+    but after the FP32 (device) or FP64 (oracle) sums, values that sit near a rounding
+    boundary land one BF16 ulp apart, and through 18 layers such flips spread to about an
+    ulp everywhere. The bound is therefore measured, not guessed: the oracle's own
+    emulation run once with FP32 and once with FP64 accumulation gives the drift any
+    other summation order produces, and the device must stay within 3x that drift (and
+    never above 2e-2 / 6e-2 on the output correction / any layer's gradient)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet_ref as U
+
+pytestmark = pytest.mark.gpu
+
+KHOT = 4
+DRIFT_FACTOR = 3.0
+FWD_CAP = 2e-2
+GRAD_CAP = 6e-2
+
+
+def _net(base=32, params=None):
+    from paper_2202_08627_amd.unet import UNet
+    return UNet(base, params)
+
+
+def _params(base, seed=0, head_scale=3.0):
+    p = U.init_params(base, seed)
+    rng = np.random.default_rng(seed + 1)
+    for kind, cin, cout, w, b in U.offsets(base)[0]:
+        p[b:b + cout] = 0.05 * rng.standard_normal(cout)
+        if kind == U.HEAD:
+            p[w:b] *= head_scale
+    return p.astype(np.float32)
+
+
+def _inputs(B, H, W, seed=0):
+    """Smooth-ish two-channel images (blob sums) plus a target offset from them."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:H, 0:W]
+    x = np.zeros((B, 2, H, W))
+    for b in range(B):
+        for c in range(2):
+            for _ in range(5):
+                cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+                r = rng.uniform(2, max(3, min(H, W) / 3))
+                x[b, c] += rng.uniform(0.2, 1.0) * ((yy - cy) ** 2 + (xx - cx) ** 2 < r * r)
+    x += 0.05 * rng.standard_normal(x.shape)
+    t = x + 0.2 * np.roll(x, 1, axis=3) - 0.1
+    return x.astype(np.float32), t.astype(np.float32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+# --------------------------------------------------------------------------- structured, exact
+def _sparse_params(base, seed, k=KHOT):
+    """Each conv output channel reads k (tap, input channel) pairs with weight +-1/2; each
+    up-conv output (channel, phase) k input channels; each head output k channels; biases
+    on a 1/4 grid in [0, 1]. All values then have few significant bits and a small
+    exponent spread, so every FP32 sum of the forward pass and of the data gradients is
+    exact whatever its order."""
+    rng = np.random.default_rng(seed)
+    lay, n = U.offsets(base)
+    p = np.zeros(n, np.float32)
+    for li, (kind, cin, cout, w, b) in enumerate(lay):
+        taps = {U.CONV: 9, U.UP: 4, U.HEAD: 1}[kind]
+        Wm = np.zeros((cout, taps, cin), np.float32)
+        cin_eff = 2 if li == 0 else cin            # the first layer sees 2 real channels
+        for o in range(cout):
+            for d in (range(4) if kind == U.UP else [None]):
+                for _ in range(k):
+                    tap = d if d is not None else rng.integers(taps)
+                    Wm[o, tap, rng.integers(cin_eff)] = rng.choice([-0.5, 0.5])
+        p[w:b] = Wm.ravel()
+        if kind != U.HEAD:
+            p[b:b + cout] = 0.25 * rng.integers(0, 5, cout)
+    return p
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 16, 64), (3, 24, 40)])
+def test_structured_network_is_exact(B, H, W):
+    print(f"[unet exact] B={B} H={H} W={W}", flush=True)
+    base = 32
+    p = _sparse_params(base, seed=H * W + B)
+    rng = np.random.default_rng(B + H)
+    x = (0.25 * rng.integers(-32, 33, (B, 2, H, W))).astype(np.float32)
+    net = _net(base, p)
+    xd = torch.tensor(x, device="cuda")
+    y = net(xd).cpu().numpy()
+    ref = U.predict(p.astype(np.float64), x, base, bf16_emul=True)
+    np.testing.assert_array_equal(y, ref.astype(np.float32))
+    n = B * 2 * H * W
+    if n & (n - 1):
+        return                                  # 2 r / n would not be exact
+    # sparse residual r = out - target on a 1/4 grid at 6 pixels per image and channel
+    r = np.zeros_like(x, dtype=np.float64)
+    for b in range(B):
+        for c in range(2):
+            idx = rng.choice(H * W, 6, replace=False)
+            r[b, c].flat[idx] = 0.25 * rng.choice([-8, -5, -2, -1, 1, 3, 4, 7], 6)
+    t = (ref - r).astype(np.float32)
+    assert np.array_equal(ref - t.astype(np.float64), r)
+    loss = float(net.train_step(xd, torch.tensor(t, device="cuda"), apply=False).cpu())
+    g = net.grad.cpu().numpy()
+    lref, gref = U.loss_and_grad(p.astype(np.float64), x, t, base, bf16_emul=True)
+    assert loss == lref
+    for name, (kind, cin, cout, w, b) in zip(U.NAMES, U.offsets(base)[0]):
+        ew, eb = _rel(g[w:b], gref[w:b]), _rel(g[b:b + cout], gref[b:b + cout])
+        print(f"  {name:5s} dW {ew:.1e} db {eb:.1e} |dW| {np.linalg.norm(gref[w:b]):.2e}")
+        assert ew <= 1e-5 and eb <= 1e-5, name
+
+
+# --------------------------------------------------------------------------- random weights
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40), (3, 16, 8)])
+def test_forward_matches_oracle(B, H, W):
+    print(f"[unet fwd] B={B} H={H} W={W}", flush=True)
+    base = 32
+    p = _params(base)
+    x, _ = _inputs(B, H, W)
+    net = _net(base, p)
+    y = net(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = U.predict(p.astype(np.float64), x, base, bf16_emul=True)
+    ref32 = U.predict(p.astype(np.float64), x, base, bf16_emul=True, dtype=torch.float32)
+    drift = _rel(ref32 - x, ref - x)
+    err = _rel(y - x, ref - x)
+    print(f"  correction rel-L2 {err:.2e} (oracle FP32/FP64 drift {drift:.2e})")
+    assert err <= min(DRIFT_FACTOR * drift, FWD_CAP)
+
+
+def _grad_check(B, H, W, base=32, seed=0):
+    p = _params(base, seed)
+    x, t = _inputs(B, H, W, seed)
+    net = _net(base, p)
+    loss = net.train_step(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), apply=False)
+    g = net.grad.cpu().numpy()
+    p64 = p.astype(np.float64)
+    lref, gref = U.loss_and_grad(p64, x, t, base, bf16_emul=True)
+    l32, g32 = U.loss_and_grad(p64, x, t, base, bf16_emul=True, dtype=torch.float32)
+    lerr, ldrift = abs(float(loss.cpu()) - lref) / lref, abs(l32 - lref) / lref
+    print(f"  loss {float(loss.cpu()):.6e} vs {lref:.6e} (rel {lerr:.1e}, drift {ldrift:.1e})")
+    assert lerr <= max(DRIFT_FACTOR * ldrift, 1e-4)
+    worst = 0.0
+    for name, (kind, cin, cout, w, b) in zip(U.NAMES, U.offsets(base)[0]):
+        ew, eb = _rel(g[w:b], gref[w:b]), _rel(g[b:b + cout], gref[b:b + cout])
+        dw, db = _rel(g32[w:b], gref[w:b]), _rel(g32[b:b + cout], gref[b:b + cout])
+        print(f"  {name:5s} dW {ew:.2e} (drift {dw:.2e})  db {eb:.2e} (drift {db:.2e})")
+        worst = max(worst, ew, eb)
+        assert ew <= min(max(DRIFT_FACTOR * dw, 1e-4), GRAD_CAP), name
+        assert eb <= min(max(DRIFT_FACTOR * db, 1e-4), GRAD_CAP), name
+    return worst
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40)])
+def test_gradients_match_oracle(B, H, W):
+    print(f"[unet grad] B={B} H={H} W={W}", flush=True)
+    _grad_check(B, H, W)
+
+
+def test_gradients_match_oracle_training_shape():
+    """One 256x256 sample, the training resolution: forward and every layer's gradient."""
+    print("[unet grad] B=1 H=256 W=256", flush=True)
+    _grad_check(1, 256, 256, seed=3)
+
+
+def test_gradient_is_deterministic():
+    print("[unet determinism]", flush=True)
+    p = _params(32)
+    x, t = _inputs(2, 32, 48)
+    net = _net(32, p)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    l1 = net.train_step(xd, td, apply=False).cpu()
+    g1 = net.grad.clone()
+    l2 = net.train_step(xd, td, apply=False).cpu()
+    assert torch.equal(g1, net.grad) and torch.equal(l1, l2)
+
+
+def test_batch_items_are_independent():
+    print("[unet batch independence]", flush=True)
+    p = _params(32)
+    x, _ = _inputs(3, 24, 32)
+    net = _net(32, p)
+    full = net(torch.tensor(x, device="cuda"))
+    for i in range(3):
+        one = net(torch.tensor(x[i:i + 1], device="cuda"))
+        assert torch.equal(one[0], full[i])
+
+
+def test_adam_update_relation():
+    """After one applied step from zero moments the device's m, v and parameters follow
+    Adam's closed form from the gradient the step reports (checked in float64)."""
+    print("[unet adam]", flush=True)
+    p = _params(32)
+    x, t = _inputs(2, 16, 16)
+    net = _net(32, p)
+    lr = 2e-3
+    net.train_step(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), lr=lr)
+    g = net.grad.cpu().numpy().astype(np.float64)
+    m = net.m.cpu().numpy().astype(np.float64)
+    v = net.v.cpu().numpy().astype(np.float64)
+    pn = net.params.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=3e-5, atol=1e-37)
+    step = lr * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+    np.testing.assert_allclose(p.astype(np.float64) - pn, step, rtol=2e-3, atol=2e-7)
+    assert net.step == 1
+
+
+def test_overfits_four_samples():
+    print("[unet overfit]", flush=True)
+    base = 32
+    p = _params(base, head_scale=0.1)
+    x, t = _inputs(4, 32, 32, seed=11)
+    net = _net(base, p)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    losses = [float(net.train_step(xd, td, lr=1e-3).cpu()) for _ in range(150)]
+    print(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.1 * losses[0]
