@@ -66,6 +66,21 @@ class UNet:
         except Exception:
             pass
 
+    def init_he(self, seed: int = 0, head_scale: float = 0.1):
+        """He-normal weights (fan-in; the 2x2 transposed convolution counts one tap per
+        output), zero biases, head weights scaled by head_scale so that the residual network
+        starts close to the identity map."""
+        rng = np.random.default_rng(seed)
+        p = np.zeros(self.n_params, dtype=np.float32)
+        for l in self.layers:
+            taps = {"conv3x3": 9, "upconv2x2": 1, "head1x1": 1}[l["kind"]]
+            std = np.sqrt(2.0 / (taps * l["cin"])) * (head_scale if l["kind"] == "head1x1" else 1.0)
+            p[l["w_off"]:l["b_off"]] = rng.standard_normal(l["b_off"] - l["w_off"]) * std
+        self.set_params(p)
+        self.m.zero_()
+        self.v.zero_()
+        self.step = 0
+
     def set_params(self, p):
         t = torch.as_tensor(np.asarray(p, dtype=np.float32) if not isinstance(p, torch.Tensor) else p)
         if t.numel() != self.n_params:
