@@ -1,19 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark: plain iterative EI reconstruction of one 512^2 slice (720 angles over 180 deg,
 512 detector pixels, 8 mask positions, Shepp-Logan-style phantom, Poisson at 1e4 counts),
-FP32 projector/adjoint with FP64 cost and optimiser reductions, L-BFGS m = 10.
+FP32 projector/adjoint with FP64 cost and optimiser reductions, L-BFGS m = 10; and the time
+to 1e-3 relative L2 of the plain solution from the zero, single-shot and learned starts.
 
 A step is one accepted L-BFGS iteration of the slice (its line-search evaluations
 included): projector, IC model/residual, FP64 cost reduction, adjoint backprojection and the
 optimiser's vector updates. `--steps K` iterations are timed from the zero start with the
 inputs resident in HBM; the value is slice-iterations per second.
 
-Printed as one JSON line. Extra keys: `roofline` for the dominant kernel (per-launch device
-time from hipEvent phase timers of a profiled replay of the same workload), `cpu_baseline`
-(the FP64 oracle on this host's cores, one cost+gradient evaluation as the sample)."""
+Printed as one JSON line. Extra keys:
+  roofline      the dominant kernel's algorithmic FLOP rate against the FP32 vector peak,
+                from per-launch device times of hipEvents recorded on the library's stream
+                around every kernel of a replay of the same K iterations; `traffic` = HBM
+                bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
+                plain copy's counts (recorded with the kernel source's hash: null once the
+                source differs);
+  cpu_baseline  the FP64 oracle on this host, single thread, two cost+gradient evaluations
+                of the same slice, scaled to slice-iterations/s;
+  time_to_tol   iterations and wall time to 1e-3 relative L2 (scaled units) of the plain
+                run's converged solution, per start, on this slice and three held-out
+                random-ellipse 512^2 slices (learned start: committed trained weights, guard on).
+"""
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -27,14 +39,26 @@ if ROOT not in sys.path:
 METRIC = "slice-iters/s (512², 720 angles) and time-to-1e-3 tol, plain vs warm start"
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
-# algorithmic work per unit: projector fused sample (both maps) and
-# adjoint voxel-angle pair (both maps)
+# algorithmic work per unit: projector fused sample (both maps: 2 x (2 mul + 2 add) for the
+# interpolation weights applied to two voxels, plus the strip accumulation) and adjoint
+# voxel-angle pair (both maps, two detector bins each)
 FLOPS_PER_SAMPLE = 12.0
 FLOPS_PER_VOXEL_ANGLE = 18.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2202_08627_amd", "csrc", "kernels.hip")
+WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.npz")
+# HBM bytes per launch at this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
+# each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
+# this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.
+TRAFFIC = {}
 
 
-def cpu_baseline_child():
-    """Time the CPU oracle on one cost+gradient evaluation of the benchmark slice."""
+def _src_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def cpu_baseline_child(n_evals: int):
+    """Time the CPU oracle on n_evals cost+gradient evaluations of the benchmark slice."""
     import platform
     import numpy as np
     from paper_2202_08627_amd import configs, synth
@@ -44,10 +68,12 @@ def cpu_baseline_child():
     geo = model.Geometry(cfg.n, c.theta, cfg.n_det, c.mask_pos, c.flat_amp, c.flat_ctr,
                          c.flat_sigma, cfg.kappa)
     prob = model.ScaledProblem(c.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
-    z = np.zeros((2, cfg.n, cfg.n))
+    rng = np.random.default_rng(0)
+    zs = [np.zeros((2, cfg.n, cfg.n))] + [rng.uniform(0, 1, (2, cfg.n, cfg.n)) for _ in range(n_evals - 1)]
     t0 = time.perf_counter()
-    prob(z)
-    t = time.perf_counter() - t0
+    for z in zs:
+        prob(z)
+    t = (time.perf_counter() - t0) / len(zs)
     cpu = platform.processor() or ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -57,7 +83,46 @@ def cpu_baseline_child():
                     break
     except OSError:
         pass
-    print(json.dumps({"eval_s": t, "cores": 1, "cpu": cpu}), flush=True)
+    print(json.dumps({"eval_s": t, "n_evals": len(zs), "cores": 1, "cpu": cpu}), flush=True)
+
+
+def time_to_tol(plan, s_exp, cfg, extra_seeds, log):
+    """Warm-start comparison on this slice plus held-out random slices (medians)."""
+    import numpy as np
+    import torch
+    from paper_2202_08627_amd import ops, warmstart as WS
+    net = WS.load_net(WEIGHTS)
+    recs = []
+    r = WS.evaluate_case(plan, s_exp, net, cfg, tol=1e-3)
+    r["slice"] = "bench slice"
+    recs.append(r)
+    wcfg = WS.slice_config(cfg.n, cfg.n_theta, cfg.n_mask)
+    for seed in extra_seeds:
+        _, s, g = WS._make_case((wcfg, seed))
+        p = ops.Plan(WS._geometry(wcfg, g))
+        r = WS.evaluate_case(p, torch.tensor(s, device="cuda"), net, wcfg, tol=1e-3)
+        r["slice"] = f"random ellipses, seed {seed}"
+        recs.append(r)
+        p.close()
+        log(f"# time-to-tol seed {seed}: " + ", ".join(f"{k} {r[k]['iters']}" for k in ("zero", "single_shot", "unet")))
+    starts = ("zero", "single_shot", "unet")
+
+    def med(key, k):
+        v = [rr[k][key] for rr in recs if rr[k]["iters"] is not None]
+        return float(np.median(v)) if v else None
+    out = {"tol": 1e-3, "error": "relative L2 in scaled units [mu/mu_scale; delta/delta_scale] "
+                                 "to the plain run from zero (run until no step passes)",
+           "slices": [rr["slice"] for rr in recs],
+           "median_iters": {k: med("iters", k) for k in starts},
+           "median_ms": {k: (round(1e3 * med("t_total_s", k), 3) if med("t_total_s", k) else None) for k in starts},
+           "median_err0": {k: round(float(np.median([rr[k]["err0"] for rr in recs])), 4) for k in starts},
+           "guard_choices": [rr["unet"]["choice"] for rr in recs]}
+    both = [rr for rr in recs if rr["zero"]["iters"] and rr["unet"]["iters"] is not None]
+    out["ratio_time_warm_vs_plain"] = round(float(np.median(
+        [rr["unet"]["t_total_s"] / rr["zero"]["t_total_s"] for rr in both])), 4) if both else None
+    out["ratio_iters_warm_vs_plain"] = round(float(np.median(
+        [rr["unet"]["iters"] / rr["zero"]["iters"] for rr in both])), 4) if both else None
+    return out
 
 
 def main():
@@ -66,10 +131,14 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with a plain 256 MiB device copy (HBM counter scaling)")
+    ap.add_argument("--cpu-evals", type=int, default=2)
     ap.add_argument("--cpu-baseline-child", action="store_true")
     args = ap.parse_args()
     if args.cpu_baseline_child:
-        cpu_baseline_child()
+        cpu_baseline_child(args.cpu_evals)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs one slice problem per GPU and "
@@ -77,70 +146,90 @@ def main():
               file=sys.stderr)
         return 2
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     child = None
     if not args.no_cpu_baseline:
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
         # started before this process touches the GPU
-        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child"],
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                                  "--cpu-evals", str(args.cpu_evals)],
                                  env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
 
-    import numpy as np
     import torch
-    from paper_2202_08627_amd import _lib, configs, ops, synth
+    from paper_2202_08627_amd import _lib, autotune, configs, ops, synth
 
     cfg = configs.SLICE_512
-    print(f"# building inputs {cfg.n}^2 x {cfg.n_theta} x {cfg.n_det} x M={cfg.n_mask}", file=sys.stderr, flush=True)
+    log(f"# building inputs {cfg.n}^2 x {cfg.n_theta} x {cfg.n_det} x M={cfg.n_mask}")
     case = synth.make_case(cfg)
     torch.cuda.set_device(0)
-    plan = ops.Plan.from_case(case)
+    geo = ops.Geometry.from_case(case)
+    tiling = autotune.tiling_for(geo)
+    plan = ops.Plan(geo, *tiling)
+    info = ops.inspect(geo, *tiling)
     s_exp = torch.as_tensor(case.s_exp, device="cuda")
     ws = plan.workspace(_lib.EIT_OP_RECONSTRUCT, 10)
     kw = dict(lam=cfg.lam, mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale, m=10, ws=ws)
 
-    print("# warmup", file=sys.stderr, flush=True)
+    log("# warmup")
     plan.reconstruct(s_exp, iters=max(args.warmup, 1), **kw)
     torch.cuda.synchronize()
 
-    print("# timed", file=sys.stderr, flush=True)
+    log("# timed")
     t0 = time.perf_counter()
     x, rep, _ = plan.reconstruct(s_exp, iters=args.steps, **kw)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     if rep["rc"] != 0 or rep["iters"] != args.steps:
-        print(f"reconstruction stopped early: {rep}", file=sys.stderr)
+        log(f"reconstruction stopped early: {rep}")
         return 1
     value = rep["iters"] / t
 
-    print("# profiled replay", file=sys.stderr, flush=True)
+    log("# replay with per-kernel hipEvents")
     _, prep, _ = plan.reconstruct(s_exp, iters=args.steps, profile=True, **kw)
-    steps = max(prep["phase_steps"], 1)
-    ph = {k: v / steps for k, v in prep["phase_ms"].items()}     # ms per launch
     n, nt, nd = cfg.n, cfg.n_theta, cfg.n_det
-    units = float(n) * nt * nd
+    evals = max(prep["phase_steps"], 1)        # projector launches (one per evaluation)
+    accepted = prep["iters"] + 1               # adjoint launches that do work (accepted trials)
     kern = {
-        "project": (units * FLOPS_PER_SAMPLE, ph["project"]),
-        "backproject": (float(n) * n * nt * FLOPS_PER_VOXEL_ANGLE, ph["backproject"] * steps / max(prep["iters"], 1)),
+        "project": (float(n) * nt * nd * FLOPS_PER_SAMPLE, prep["phase_ms"]["project"] / evals,
+                    f"k_project<{info['proj_a']}, {info['proj_w']}, {info['proj_r']}, ...>"),
+        "backproject": (float(n) * n * nt * FLOPS_PER_VOXEL_ANGLE, prep["phase_ms"]["backproject"] / accepted,
+                        f"k_backproject<{info['adj_tx']}, {info['adj_ty']}, {info['adj_ac']}, ...>"),
     }
-    # the adjoint runs only for accepted trials: its per-launch time is its total over the
-    # accepted evaluations (one launch each)
-    accepted = prep["iters"] + 1
-    kern["backproject"] = (float(n) * n * nt * FLOPS_PER_VOXEL_ANGLE,
-                           prep["phase_ms"]["backproject"] / accepted)
-    dom = max(kern, key=lambda k: kern[k][1])
-    flops, ms = kern[dom]
+    dom = max(kern, key=lambda k: kern[k][1] * (evals if k == "project" else accepted))
+    flops, ms, kname = kern[dom]
     achieved = flops / (ms * 1e-3) / 1e12
-    # HBM view of the same two kernels: algorithmic bytes = maps in + sinograms out (projector),
-    # seeds in + gradient out + iterate in (adjoint)
-    hbm_bytes = {"project": 4.0 * (2 * n * n + 2 * nt * nd),
-                 "backproject": 4.0 * (2 * nt * nd + 4 * n * n)}
+    # algorithmic HBM bytes: maps in + sinograms out (projector); seeds in + gradient out +
+    # iterate in (adjoint)
+    hbm_alg = {"project": 4.0 * (2 * n * n + 2 * nt * nd), "backproject": 4.0 * (2 * nt * nd + 4 * n * n)}
+    tr = TRAFFIC.get(dom)
+    traffic = None
+    if tr and tr.get("src") == _src_hash() and tr.get("variant") == (info["proj_variant"] if dom == "project" else info["adj_variant"]):
+        traffic = tr["bytes"]
     roof = {
-        "bound": "alu", "kernel": "k_project" if dom == "project" else "k_backproject",
+        "bound": "alu", "kernel": kname,
         "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-        "launch_ms": round(ms, 5),
-        "hbm_frac": round(hbm_bytes[dom] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5),
-        "phase_ms_per_step": {k: round(v, 5) for k, v in ph.items()},
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "launch_us": round(ms * 1e3, 2),
+        "hbm_alg_bytes": hbm_alg[dom],
+        "hbm_frac": round(hbm_alg[dom] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5),
+        "other_kernel": {k: {"launch_us": round(v[1] * 1e3, 2),
+                             "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3)} for k, v in kern.items() if k != dom},
+        "phase_ms_per_iter": {k: round(v / max(prep["iters"], 1), 5) for k, v in prep["phase_ms"].items()},
+        "tiling": {"proj_variant": info["proj_variant"], "adj_variant": info["adj_variant"]},
     }
+
+    ttt = None
+    if not args.no_warm_start:
+        log("# time to tolerance (zero / single-shot / learned start)")
+        ttt = time_to_tol(plan, s_exp, cfg, [1_000_000, 1_000_001, 1_000_002], log)
+
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")        # 256 MiB read + 256 MiB written
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
 
     cpu = None
     if child is not None:
@@ -150,11 +239,12 @@ def main():
             evals_per_iter = rep["evals"] / max(rep["iters"], 1)
             cpu = {"value": round(1.0 / (cb["eval_s"] * evals_per_iter), 6), "unit": "slice-iters/s",
                    "cores": cb["cores"], "kind": "oracle",
-                   "sample": (f"one FP64 cost+gradient evaluation of the same slice at z=0 took "
-                              f"{cb['eval_s']:.1f} s on 1 thread ({cb['cpu']}); scaled by the "
-                              f"{evals_per_iter:.3f} evaluations per iteration of the timed run")}
+                   "sample": (f"{cb['n_evals']} FP64 cost+gradient evaluations of the same slice "
+                              f"(zero and a random point) at {cb['eval_s']:.1f} s each on 1 thread "
+                              f"({cb['cpu']}); scaled by the {evals_per_iter:.3f} evaluations per "
+                              f"iteration of the timed run")}
         else:
-            print(f"cpu baseline failed: {err[-2000:]}", file=sys.stderr)
+            log(f"cpu baseline failed: {err[-2000:]}")
 
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "slice-iters/s", "n_gpus": 1,
@@ -168,6 +258,7 @@ def main():
                    "iterations": args.steps, "evals": rep["evals"], "final_cost": rep["cost"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "time_to_tol": ttt,
     }
     print(json.dumps(line), flush=True)
     return 0

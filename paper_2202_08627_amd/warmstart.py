@@ -159,10 +159,20 @@ def warm_start(plan: ops.Plan, s_exp: torch.Tensor, net: UNet | None, cfg, lam: 
         cands["unet"] = (net(z)[0] * sc).contiguous()
     costs = {k: float(plan.cost_and_grad(v, s_exp, lam_mu, lam_de, want_grad=False)[0].cpu())
              for k, v in cands.items()}
-    best = min(("zero", "single_shot"), key=lambda k: costs[k])
-    choice = "unet" if "unet" in costs and np.isfinite(costs["unet"]) and \
-        costs["unet"] <= costs["single_shot"] and costs["unet"] <= costs["zero"] else best
+    choice = guard_choice(costs)
     return cands[choice], choice, costs
+
+
+def guard_choice(costs: dict) -> str:
+    """The network's start is taken only if its cost is finite and no larger than both the
+    single-shot start's and the zero start's; otherwise the cheaper of those two (zero on a
+    non-finite single-shot cost)."""
+    ss = costs.get("single_shot", float("inf"))
+    best = "single_shot" if np.isfinite(ss) and ss <= costs["zero"] else "zero"
+    u = costs.get("unet")
+    if u is not None and np.isfinite(u) and u <= costs["zero"] and (not np.isfinite(ss) or u <= ss):
+        return "unet"
+    return best
 
 
 def rel_err(x: torch.Tensor, x_ref: torch.Tensor, cfg) -> float:

@@ -123,7 +123,7 @@ def test_structured_network_is_exact(B, H, W):
 
 
 # --------------------------------------------------------------------------- random weights
-@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40), (3, 16, 8)])
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40), (3, 16, 8), (1, 512, 512)])
 def test_forward_matches_oracle(B, H, W):
     print(f"[unet fwd] B={B} H={H} W={W}", flush=True)
     base = 32
