@@ -232,9 +232,11 @@ int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_til
 const char* eit_last_error(void);
 
 /* Compiled tile variants: kind 0 = projector (a = angles per group, b = detectors per
- * block, c = rows per strip, d = staged pairs per row), kind 1 = adjoint (a, b = voxel tile,
- * c = angles per chunk, d = voxels per thread). Returns the number of variants of that kind;
- * fills a/b/c/d (each may be NULL) for index v if in range. */
+ * block, c = rows per strip, d = staged entries per row), kind 1 = adjoint (a, b = voxel tile,
+ * c = angles per chunk, d = voxels per thread), kind 2 = projector LDS layout (a = 1 if a
+ * sample reads one 16-byte entry holding both neighbouring columns, 0 if it reads two 8-byte
+ * (mu, delta) pairs). Returns the number of variants of that kind; fills a/b/c/d (each may
+ * be NULL) for index v if in range. */
 int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c, int32_t* d);
 
 /* ---------------------------------------------------------------------------------------

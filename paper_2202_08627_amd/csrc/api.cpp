@@ -253,7 +253,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     p->win_w = win_w;
     p->win_shift = 0;
     while ((1 << p->win_shift) < p->pt.PW) ++p->win_shift;
-    p->proj_lds = (size_t)R * (size_t)p->pt.PW * sizeof(float2);
+    p->proj_lds = (size_t)R * (size_t)p->pt.PW * (p->pt.DUP ? sizeof(float4) : sizeof(float2));
     if (win_w > p->pt.PW) {
         return fail(EIT_ERR_SHAPE, "projector window %d wider than variant %d's pitch %d", win_w,
                     pv, p->pt.PW);
@@ -274,6 +274,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         q.iw = (float)(1.0 / wv);
         q.iw2 = (float)(1.0 / (wv * wv));
         q.iwm = (float)(1.0 / wv - 1.0 / (wv * wv));
+        q.omw = (float)(1.0 - 1.0 / wv);
         aang[a] = q;
         span = std::max(span, (p->at.TX - 1) * std::fabs(cs) + (p->at.TY - 1) * std::fabs(sn));
     }
@@ -859,6 +860,11 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
             if (c) *c = t.R;
             if (dd) *dd = t.PW;
         }
+        return n;
+    }
+    if (kind == 2) {                       // projector LDS layout
+        const int n = proj_variant_count();
+        if (v >= 0 && v < n && a) *a = proj_variant(v).DUP;
         return n;
     }
     if (kind == 1) {

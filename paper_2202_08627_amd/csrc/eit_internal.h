@@ -28,11 +28,11 @@ struct AdjAngle {
     double cs, sn, cd;         // FP64 for the per-tile window origin
     float cs_f, sn_f;          // FP32 for the inner loop
     float iw, iw2, iwm;        // 1/w, 1/w^2, 1/w - 1/w^2
-    float pad;
+    float omw;                 // 1 - 1/w
 };
 
 // Tile shapes (compile-time variants, chosen per grid-size class).
-struct ProjTile { int A, W, R, PW; };     // angles per group, detectors per block, rows per strip, pitch
+struct ProjTile { int A, W, R, PW, DUP; };     // angles per group, detectors per block, rows per strip, pitch
 struct AdjTile  { int TX, TY, AC, VPT; }; // voxel tile, angles per staged chunk, voxels per thread
 
 // ---------------------------------------------------------------- per-slice descriptor

@@ -6,6 +6,8 @@
 //   backproject-- gather-form R^T (+ regulariser term of the gradient), LDS-staged windows
 // Every kernel walks a list of work items (slice, a, b, c) with a grid-stride loop, so one
 // launch can cover one slice or a batch of slices of different sizes.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace eit {
@@ -62,15 +64,19 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // Item (slice, group, detector block, -). Thread (angle slot al, detector kl) follows one
 // ray. The block walks the stepped axis in strips of R rows; for each strip it stages the
 // window [lo, lo + win_w) of the interpolation axis (host-computed lo, conservative in FP64)
-// as interleaved (mu, delta) pairs in LDS, PW pairs per row; a sample is then two 8-byte LDS
-// reads of the neighbouring pairs and four FMAs. The next strip's window is loaded into
-// registers (buffer loads: rows past the map read as zero) while the current one is consumed.
+// in LDS, PW entries per row, and a sample applies the two interpolation weights to the
+// neighbouring columns with four FMAs. Two LDS layouts (a tile-shape option):
+//   DUP = 0: interleaved (mu, delta) pairs; a sample is two 8-byte LDS reads;
+//   DUP = 1: 16-byte entries (mu, delta of column c, mu, delta of column c + 1), each column
+//            stored twice; a sample is one aligned 16-byte read, staging loads twice as much.
+// The next strip's window is loaded into registers (buffer loads: rows past the map read as
+// zero) while the current one is consumed.
 //
 // Index safety: every LDS index is ioff + (int)u (+1) with u in [1 - 1e-5, win_w - ioff - 1)
 // for all rays of the block; the host builds lo and win_w from FP64 extremes with a 1e-3
 // margin, and the host tests replay this exact FP32/FP64 arithmetic for every work item of
 // the benchmark and test geometries.
-template <int A, int W, int R, int PW>
+template <int A, int W, int R, int PW, int DUP>
 __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
     constexpr int NT = A * W;
@@ -82,7 +88,8 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
     constexpr int CS = WIDE ? 1 : PW / NT;   // columns per thread and row
     static_assert(R % RS == 0, "strip must tile the block");
     constexpr int SLOTS = R / RS * CS;
-    __shared__ float2 win[R * PW];
+    typedef typename std::conditional<DUP != 0, float4, float2>::type Entry;
+    __shared__ Entry win[R * PW];
     const int tid = threadIdx.x;
     const int al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
     const int kl = tid % W;
@@ -110,25 +117,37 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
         const int win_w = d.win_w, ns = d.n_strips;
         const int rstep4 = RS * n * 4;
 
-        float2 buf[SLOTS];
+        // DUP: entry c needs columns c and c + 1, both loaded (a window column past win_w - 1
+        // or outside the map reads as zero; entry win_w - 1's second half is never used)
+        Entry buf[SLOTS];
+        auto load_pair = [&](int q, int vo, int vo1) {
+            if constexpr (DUP != 0)
+                buf[q] = make_float4(buf_ld(bm, vo), buf_ld(bd, vo), buf_ld(bm, vo1), buf_ld(bd, vo1));
+            else
+                buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
+        };
         auto load_strip = [&](int s) {
             const int lo = cld(lo_tab + s);
             if constexpr (WIDE) {
                 const int col = lo + sc;
                 const bool ok = sc < win_w && (unsigned)col < (unsigned)n;
+                const bool ok1 = DUP != 0 && sc + 1 < win_w && (unsigned)(col + 1) < (unsigned)n;
                 int vo = ok ? ((s * R + sr) * n + col) * 4 : kBufOOB;
+                int vo1 = ok1 ? vo + 4 : kBufOOB;
 #pragma unroll
                 for (int q = 0; q < SLOTS; ++q) {
-                    buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
-                    vo += rstep4;
+                    load_pair(q, vo, vo1);
+                    vo += ok ? rstep4 : 0;
+                    vo1 += ok1 ? rstep4 : 0;
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < SLOTS; ++q) {
                     const int c = tid + (q % CS) * NT, col = lo + c;
                     const bool ok = c < win_w && (unsigned)col < (unsigned)n;
+                    const bool ok1 = DUP != 0 && c + 1 < win_w && (unsigned)(col + 1) < (unsigned)n;
                     const int vo = ok ? ((s * R + q / CS) * n + col) * 4 : kBufOOB;
-                    buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
+                    load_pair(q, vo, ok1 ? ((s * R + q / CS) * n + col + 1) * 4 : kBufOOB);
                 }
             }
         };
@@ -151,19 +170,25 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             const double up0 = fma((double)(s * R), slope, ut0);
             const double fl0 = floor(up0 + fmin(0.0, (double)(R - 1) * slope)) - 1.0;
             const float uf = (float)(up0 - fl0);
-            const float2* rowp = win + ((int)fl0 - lo);
+            const Entry* rowp = win + ((int)fl0 - lo);
             float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const float u = fmaf((float)r, slope_f, uf);
                 const float ph = __builtin_amdgcn_fractf(u);
-                const float2* q = rowp + r * PW + (int)u;
-                const float2 v0 = q[0], v1 = q[1];
+                const Entry* q = rowp + r * PW + (int)u;
+                float4 v;
+                if constexpr (DUP != 0) {
+                    v = *(const float4*)q;
+                } else {
+                    const float2 v0 = ((const float2*)q)[0], v1 = ((const float2*)q)[1];
+                    v = make_float4(v0.x, v0.y, v1.x, v1.y);
+                }
                 const float om = 1.f - ph;
-                c0 = fmaf(om, v0.x, c0);
-                c1 = fmaf(om, v0.y, c1);
-                c2 = fmaf(ph, v1.x, c2);
-                c3 = fmaf(ph, v1.y, c3);
+                c0 = fmaf(om, v.x, c0);
+                c1 = fmaf(om, v.y, c1);
+                c2 = fmaf(ph, v.z, c2);
+                c3 = fmaf(ph, v.w, c3);
             }
             acc_m += (double)c0 + (double)c2;     // strip sums combined in FP64
             acc_d += (double)c1 + (double)c3;
@@ -259,8 +284,13 @@ __global__ __launch_bounds__(256) void k_cost_reduce(const SliceDesc* __restrict
 // Item (slice, tile_x, tile_y, -). A TX x TY voxel tile; thread (il, jl) owns VPT voxels of
 // column il (rows jl + q TY/VPT). For each chunk of AC angles the block stages, per angle, the
 // kwin detector bins the tile can reach (starting at lo = floor(min over the tile of u) - 1,
-// FP64) as interleaved (G_mu, G_delta) pairs in LDS, plus the angle's FP32 constants; a voxel
-// then reads its two bins with one 16-byte LDS read and applies the Joseph triangle weights.
+// FP64) in LDS, premultiplied by the angle's 1/w, as 16-byte entries (G_mu, G_delta of bin
+// c, G_mu, G_delta of bin c + 1) -- each bin stored twice so that a voxel's two bins are one
+// aligned 16-byte LDS read -- plus the angle's FP32 constants; a voxel then applies the
+// Joseph triangle weights. With the 1/w factor staged, each weight
+// (1/w) max(0, 1 - d/w) is one FMA whose result the hardware clamps to [0, 1]:
+//   bin floor(u):     max(0, 1 - f/w),   bin floor(u)+1:   max(0, (1 - 1/w) + f/w)
+// (f = frac(u); neither exceeds 1 since f in [0, 1) and 1/w >= 1).
 // No atomics: each voxel's sum is accumulated in a fixed angle order by one thread, chunk
 // sums in FP64. The next chunk's bins are loaded into registers during the current chunk.
 constexpr int isqrt_ceil(int v) {
@@ -295,13 +325,14 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     constexpr int NT = TX * TY / VPT;
     constexpr int PK = adj_pitch_max<TX, TY>();
     static_assert(NT % PK == 0, "staging must tile the block");
+    static_assert(64 % PK == 0, "a staged angle row must not straddle wavefronts");
     constexpr int AS = NT / PK;              // angles staged per slot step
     static_assert(AC % AS == 0, "chunk must tile the block");
     constexpr int SLOTS = AC / AS;
     constexpr int JS = TY / VPT;
-    __shared__ float2 gw[AC * PK];
+    __shared__ float4 gw[AC * PK];
     __shared__ float4 rec[2][AC];            // cs, sn, offset, 1/w   (double-buffered by chunk)
-    __shared__ float2 rec2[2][AC];           // 1/w^2, 1/w - 1/w^2
+    __shared__ float rec2[2][AC];            // 1 - 1/w
     __shared__ int los[2][AC];
     const int tid = threadIdx.x;
     const int il = tid % TX, jl = tid / TX;
@@ -323,14 +354,15 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
         auto angle_setup = [&](int ch) {
             if (tid < AC) {
                 const int a = ch * AC + tid;
-                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);   // padding angle: zero weights
-                float2 r2 = make_float2(0.f, 0.f);
+                // padding angle: 1/w = 0 zeroes its staged bins
+                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);
+                float r2 = 0.f;
                 int lo = -(1 << 20);
                 if (a < nth) {
                     const AdjAngle* q = aang + a;
                     const TileWin tw = tile_window(q, i0, j0, TX, TY);
                     r1 = make_float4(cld(&q->cs_f), cld(&q->sn_f), tw.off, cld(&q->iw));
-                    r2 = make_float2(cld(&q->iw2), cld(&q->iwm));
+                    r2 = cld(&q->omw);
                     lo = tw.lo;
                 }
                 rec[ch & 1][tid] = r1;
@@ -361,7 +393,14 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
         for (int ch = 0; ch < nchunks; ++ch) {
             __syncthreads();                           // previous chunk fully consumed
 #pragma unroll
-            for (int q = 0; q < SLOTS; ++q) gw[(sa + q * AS) * PK + sb] = buf[q];
+            for (int q = 0; q < SLOTS; ++q) {
+                // bin sb + 1 of the same angle is held by the next lane (PK divides 64)
+                const float iw = rec[ch & 1][sa + q * AS].w;
+                const float gm = iw * buf[q].x, gd = iw * buf[q].y;
+                float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
+                if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
+                gw[(sa + q * AS) * PK + sb] = make_float4(gm, gd, nm, nd1);
+            }
             if (ch + 1 < nchunks) angle_setup(ch + 1);
             __syncthreads();
             if (ch + 1 < nchunks) load_chunk(ch + 1);  // in flight during this chunk
@@ -372,19 +411,18 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 #pragma unroll 4
             for (int aa = 0; aa < AC; ++aa) {
                 const float4 r1 = rec[cb][aa];
-                const float2 r2 = rec2[cb][aa];
+                const float omw = rec2[cb][aa];
                 const float u0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
-                const float2* row = gw + aa * PK;
+                const float4* row = gw + aa * PK;
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
                     const float u = q == 0 ? u0 : fmaf((float)(q * JS), r1.y, u0);
                     const float f = __builtin_amdgcn_fractf(u);
-                    const float w0 = fmaxf(0.f, fmaf(-f, r2.x, r1.w));
-                    const float w1 = fmaxf(0.f, fmaf(f, r2.x, r2.y));
-                    const float2* p = row + (int)u;
-                    const float2 g0 = p[0], g1 = p[1];
-                    am[q] = fmaf(w0, g0.x, fmaf(w1, g1.x, am[q]));
-                    ad[q] = fmaf(w0, g0.y, fmaf(w1, g1.y, ad[q]));
+                    const float w0 = __builtin_amdgcn_fmed3f(fmaf(-f, r1.w, 1.f), 0.f, 1.f);
+                    const float w1 = __builtin_amdgcn_fmed3f(fmaf(f, r1.w, omw), 0.f, 1.f);
+                    const float4 g = row[(int)u];
+                    am[q] = fmaf(w0, g.x, fmaf(w1, g.z, am[q]));
+                    ad[q] = fmaf(w0, g.y, fmaf(w1, g.w, ad[q]));
                 }
             }
 #pragma unroll
@@ -413,17 +451,21 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 }
 
 // ------------------------------------------------------------------------ registry
-// Projector variants (A angles x W detectors threads, R rows per strip, PW staged pairs per row).
-#define EIT_PROJ_VARIANTS(X) \
-    X(0, 8, 64, 16, 256)     \
-    X(1, 4, 64, 16, 128)     \
-    X(2, 16, 64, 8, 256)     \
-    X(3, 8, 64, 8, 256)      \
-    X(4, 4, 128, 16, 256)    \
-    X(5, 8, 64, 32, 256)     \
-    X(6, 16, 64, 16, 256)    \
-    X(7, 2, 64, 16, 128)     \
-    X(8, 1, 64, 16, 128)
+// Projector variants (A angles x W detectors threads, R rows per strip, PW staged entries per
+// row, DUP = duplicated 16-byte entries).
+#define EIT_PROJ_VARIANTS(X)   \
+    X(0, 8, 64, 16, 256, 0)    \
+    X(1, 4, 64, 16, 128, 0)    \
+    X(2, 16, 64, 8, 256, 0)    \
+    X(3, 8, 64, 8, 256, 0)     \
+    X(4, 4, 128, 16, 256, 0)   \
+    X(5, 8, 64, 32, 256, 0)    \
+    X(6, 16, 64, 16, 256, 0)   \
+    X(7, 2, 64, 16, 128, 0)    \
+    X(8, 1, 64, 16, 128, 0)    \
+    X(9, 16, 64, 16, 256, 1)   \
+    X(10, 16, 64, 8, 256, 1)   \
+    X(11, 8, 64, 8, 256, 1)
 
 // Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
@@ -438,17 +480,17 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 
 int proj_variant_count() {
     int c = 0;
-#define X(id, A, W, R, PW) ++c;
+#define X(id, A, W, R, PW, DUP) ++c;
     EIT_PROJ_VARIANTS(X)
 #undef X
     return c;
 }
 ProjTile proj_variant(int v) {
-#define X(id, A, W, R, PW) \
-    if (v == id) return ProjTile{A, W, R, PW};
+#define X(id, A, W, R, PW, DUP) \
+    if (v == id) return ProjTile{A, W, R, PW, DUP};
     EIT_PROJ_VARIANTS(X)
 #undef X
-    return ProjTile{0, 0, 0};
+    return ProjTile{0, 0, 0, 0, 0};
 }
 int adj_pitch_limit(int v) {
 #define X(id, TX, TY, AC, VPT) \
@@ -482,10 +524,10 @@ hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, 
 hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, int n_items,
                           int grid, size_t lds, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, A, W, R, PW)                                                       \
+#define X(id, A, W, R, PW, DUP)                                                  \
     if (variant == id) {                                                         \
         (void)lds;                                                               \
-        k_project<A, W, R, PW><<<grid, A * W, 0, s>>>(D, items, n_items);        \
+        k_project<A, W, R, PW, DUP><<<grid, A * W, 0, s>>>(D, items, n_items);   \
         return hipGetLastError();                                                \
     }
     EIT_PROJ_VARIANTS(X)

@@ -94,14 +94,19 @@ def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, tables
 
 def variants(kind: int):
     """Tile shapes of the compiled variants: projector (kind 0) as (angles per group,
-    detectors per block, rows per strip); adjoint (kind 1) as (tile x, tile y, angles per
-    chunk, voxels per thread)."""
+    detectors per block, rows per strip, duplicated 16-byte LDS entries 0/1); adjoint
+    (kind 1) as (tile x, tile y, angles per chunk, voxels per thread)."""
     n = L.lib().eit_variant_info(kind, -1, None, None, None, None)
     out = []
     for v in range(n):
         a, b, c, e = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         L.lib().eit_variant_info(kind, v, C.byref(a), C.byref(b), C.byref(c), C.byref(e))
-        out.append((a.value, b.value, c.value) if kind == 0 else (a.value, b.value, c.value, e.value))
+        if kind == 0:
+            dup = C.c_int32()
+            L.lib().eit_variant_info(2, v, C.byref(dup), None, None, None)
+            out.append((a.value, b.value, c.value, dup.value))
+        else:
+            out.append((a.value, b.value, c.value, e.value))
     return out
 
 

@@ -92,8 +92,8 @@ def test_variant_registry():
     pv = ops.variants(0)
     av = ops.variants(1)
     assert len(pv) >= 3 and len(av) >= 3
-    for a, w, r in pv:
-        assert a * w <= 1024 and w % 64 == 0
+    for a, w, r, dup in pv:
+        assert a * w <= 1024 and w % 64 == 0 and dup in (0, 1)
     for tx, ty, ac, vpt in av:
         assert tx * ty // vpt <= 1024 and (tx * ty // vpt) % 64 == 0
 
