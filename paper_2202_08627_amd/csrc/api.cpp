@@ -663,6 +663,7 @@ struct PhaseTimer {
 // Replays the step until every slice's optimiser has stopped. Reads back (status, k) of each
 // slice only between rounds of launches; each round enqueues as many steps as the slowest
 // slice still needs iterations (every accepted iteration needs at least one evaluation).
+constexpr int kStepsPerGraph = 4;
 int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
              bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt);
 
@@ -697,9 +698,13 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
              bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt) {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    // A graph holds kStepsPerGraph consecutive steps: the launch gap between graphs is
+    // larger than between kernels of one graph. Steps past a slice's end are no-ops (its
+    // skip flags are set), so a round may run up to kStepsPerGraph - 1 idle steps.
     if (use_graph) {
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(sp, st);
+        int rc = EIT_OK;
+        for (int q = 0; q < kStepsPerGraph && !rc; ++q) rc = enqueue_step(sp, st);
         hipError_t e = hipStreamEndCapture(st, &graph);
         if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
         if (e != hipSuccess) return fail(EIT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -715,16 +720,19 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
     int want = max_iter + 1;
     std::vector<int32_t> host(5 * states.size());
     while (rc == EIT_OK) {
-        for (int i = 0; i < want && rc == EIT_OK; ++i) {
+        for (int i = 0; i < want && rc == EIT_OK;) {
             if (use_graph) {
                 hipError_t e = hipGraphLaunch(exec, st);
                 if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+                i += kStepsPerGraph;
+                total += kStepsPerGraph;
             } else {
                 hipEvent_t* ev = nullptr;
                 if (pt) rc = pt->next(&ev);
                 if (!rc) rc = enqueue_step(sp, st, ev);
+                ++i;
+                ++total;
             }
-            ++total;
         }
         if (rc) break;
         for (size_t q = 0; q < states.size(); ++q) {

@@ -80,6 +80,7 @@ constexpr int kMaxM = 20;                // largest L-BFGS memory
 constexpr int kVecChunk = 2048;          // vector elements per work item (256 threads x 8)
 constexpr int kVecThreads = 256;
 constexpr int kDotsFixed = 7;            // gg, ss, yy, sy, zz, s.g, y.g
+constexpr int kSlotBatch = 10;           // history slots whose vectors are loaded together
 constexpr int max_dots(int m) { return kDotsFixed + 4 * m; }
 
 enum SolverMode : int32_t { MODE_INIT = 0, MODE_NEW_DIR = 1, MODE_BACKTRACK = 2 };

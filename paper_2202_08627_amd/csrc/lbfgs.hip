@@ -88,28 +88,34 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
                 dv[c][2] = mode == MODE_NEW_DIR ? -gamma * g4.z : (double)d4.z;
                 dv[c][3] = mode == MODE_NEW_DIR ? -gamma * g4.w : (double)d4.w;
             }
-            // history combination, next slot's vectors loaded while this one is applied
-            float4 sv[2], yv[2];
-            auto load_slot = [&](int q) {
-                const size_t o = (size_t)s.order[q] * l.nv + e0;
-                sv[0] = *(const float4*)(l.S + o);
-                yv[0] = *(const float4*)(l.Y + o);
-                sv[1] = *(const float4*)(l.S + o + nn);
-                yv[1] = *(const float4*)(l.Y + o + nn);
-            };
-            if (mc > 0) load_slot(0);
-            for (int q = 0; q < mc; ++q) {
-                const float4 s0 = sv[0], y0 = yv[0], s1 = sv[1], y1 = yv[1];
-                if (q + 1 < mc) load_slot(q + 1);
-                const double ee = -s.ee[q], cc = s.cc[q];
-                dv[0][0] = fma(cc, (double)y0.x, fma(ee, (double)s0.x, dv[0][0]));
-                dv[0][1] = fma(cc, (double)y0.y, fma(ee, (double)s0.y, dv[0][1]));
-                dv[0][2] = fma(cc, (double)y0.z, fma(ee, (double)s0.z, dv[0][2]));
-                dv[0][3] = fma(cc, (double)y0.w, fma(ee, (double)s0.w, dv[0][3]));
-                dv[1][0] = fma(cc, (double)y1.x, fma(ee, (double)s1.x, dv[1][0]));
-                dv[1][1] = fma(cc, (double)y1.y, fma(ee, (double)s1.y, dv[1][1]));
-                dv[1][2] = fma(cc, (double)y1.z, fma(ee, (double)s1.z, dv[1][2]));
-                dv[1][3] = fma(cc, (double)y1.w, fma(ee, (double)s1.w, dv[1][3]));
+            // history combination: the vectors of a batch of slots are requested together
+            // (one memory round trip per batch), then applied oldest first
+            for (int r0 = 0; r0 < mc; r0 += kSlotBatch) {
+                float4 sv[kSlotBatch][2], yv[kSlotBatch][2];
+#pragma unroll
+                for (int b = 0; b < kSlotBatch; ++b) {
+                    if (r0 + b < mc) {
+                        const size_t o = (size_t)s.order[r0 + b] * l.nv + e0;
+                        sv[b][0] = *(const float4*)(l.S + o);
+                        yv[b][0] = *(const float4*)(l.Y + o);
+                        sv[b][1] = *(const float4*)(l.S + o + nn);
+                        yv[b][1] = *(const float4*)(l.Y + o + nn);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < kSlotBatch; ++b) {
+                    if (r0 + b < mc) {
+                        const double ee = -s.ee[r0 + b], cc = s.cc[r0 + b];
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const float4 sq = sv[b][c], yq = yv[b][c];
+                            dv[c][0] = fma(cc, (double)yq.x, fma(ee, (double)sq.x, dv[c][0]));
+                            dv[c][1] = fma(cc, (double)yq.y, fma(ee, (double)sq.y, dv[c][1]));
+                            dv[c][2] = fma(cc, (double)yq.z, fma(ee, (double)sq.z, dv[c][2]));
+                            dv[c][3] = fma(cc, (double)yq.w, fma(ee, (double)sq.w, dv[c][3]));
+                        }
+                    }
+                }
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -195,12 +201,37 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
 // s_new = zt - z, y_new = gt - g into the spare slot; z <- zt, g <- gt; per-block partial
 // inner products: [0] g.g [1] s.s [2] y.y [3] s.y [4] z_old.z_old [5] s.g [6] y.g and, for
 // every committed slot r: [7+4r] s_r.y [8+4r] y_r.y [9+4r] s_r.g [10+4r] y_r.g (g = new g).
-// Each product is reduced across the wavefront with shuffles as soon as it is complete; the
-// four wavefront sums meet once in LDS. Partials are stored [block][product].
+// A thread owns 8 consecutive elements (two float4 when aligned). The committed slots'
+// vectors are requested a batch at a time (one memory round trip per batch). Each product is
+// reduced across the wavefront as soon as it is complete; the four wavefront sums meet once
+// in LDS. Partials are stored [block][product].
+__device__ __forceinline__ void ld8(const float* __restrict__ p, int64_t e, int64_t nv, bool vec,
+                                    float* v) {
+    if (vec) {
+        const float4 a = *(const float4*)(p + e), b = *(const float4*)(p + e + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = e + u < nv ? p[e + u] : 0.f;
+    }
+}
+__device__ __forceinline__ void st8(float* __restrict__ p, int64_t e, int64_t nv, bool vec,
+                                    const float* v) {
+    if (vec) {
+        *(float4*)(p + e) = make_float4(v[0], v[1], v[2], v[3]);
+        *(float4*)(p + e + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e + u < nv) p[e + u] = v[u];
+    }
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restrict__ L,
                                                          const Item* __restrict__ items,
                                                          int n_items) {
     constexpr int NW = kVecThreads / 64;
+    static_assert(kVecChunk == 8 * kVecThreads, "8 elements per thread");
     __shared__ double wsum[NW][max_dots(kMaxM)];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -211,77 +242,89 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
         const int init = st.mode == MODE_INIT;
         const int mc = init ? 0 : st.m_cur;
         const int64_t nv = l.nv;
-        const int64_t e0 = (int64_t)w.y * kVecChunk;
-        const int64_t e1 = min(e0 + kVecChunk, nv);
-        constexpr int PER = kVecChunk / kVecThreads;
-        float yv[PER], gv[PER];
+        const int64_t e = (int64_t)w.y * kVecChunk + 8 * (int64_t)threadIdx.x;
+        // slot offsets k * nv keep 16-byte alignment when nv % 4 == 0
+        const bool vec = (nv & 3) == 0 && e + 8 <= nv;
+        float yv[8], gv[8];
         double acc[kDotsFixed];
 #pragma unroll
         for (int q = 0; q < kDotsFixed; ++q) acc[q] = 0.0;
-        const int64_t sp = (int64_t)st.spare * nv;
+        if (e < nv) {
+            ld8(l.gt, e, nv, vec, gv);
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
-            yv[u] = 0.f; gv[u] = 0.f;
-            if (e < e1) {
-                const float gt = l.gt[e];
-                gv[u] = gt;
-                acc[0] = fma((double)gt, (double)gt, acc[0]);
-                if (!init) {
-                    const float zo = l.z[e], zn = l.zt[e], go = l.g[e];
-                    const float sv = zn - zo, y = gt - go;
-                    yv[u] = y;
-                    l.S[sp + e] = sv;
-                    l.Y[sp + e] = y;
-                    l.z[e] = zn;
-                    acc[1] = fma((double)sv, (double)sv, acc[1]);
-                    acc[2] = fma((double)y, (double)y, acc[2]);
-                    acc[3] = fma((double)sv, (double)y, acc[3]);
-                    acc[4] = fma((double)zo, (double)zo, acc[4]);
-                    acc[5] = fma((double)sv, (double)gt, acc[5]);
-                    acc[6] = fma((double)y, (double)gt, acc[6]);
+            for (int u = 0; u < 8; ++u) acc[0] = fma((double)gv[u], (double)gv[u], acc[0]);
+            if (!init) {
+                float zo[8], zn[8], go[8], sv[8];
+                ld8(l.z, e, nv, vec, zo);
+                ld8(l.zt, e, nv, vec, zn);
+                ld8(l.g, e, nv, vec, go);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    sv[u] = zn[u] - zo[u];
+                    yv[u] = gv[u] - go[u];
+                    acc[1] = fma((double)sv[u], (double)sv[u], acc[1]);
+                    acc[2] = fma((double)yv[u], (double)yv[u], acc[2]);
+                    acc[3] = fma((double)sv[u], (double)yv[u], acc[3]);
+                    acc[4] = fma((double)zo[u], (double)zo[u], acc[4]);
+                    acc[5] = fma((double)sv[u], (double)gv[u], acc[5]);
+                    acc[6] = fma((double)yv[u], (double)gv[u], acc[6]);
                 }
-                l.g[e] = gt;
+                const int64_t sp = (int64_t)st.spare * nv;
+                st8(l.S + sp, e, nv, vec, sv);
+                st8(l.Y + sp, e, nv, vec, yv);
+                st8(l.z, e, nv, vec, zn);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) yv[u] = 0.f;
             }
+            st8(l.g, e, nv, vec, gv);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { yv[u] = 0.f; gv[u] = 0.f; }
         }
 #pragma unroll
         for (int q = 0; q < kDotsFixed; ++q) {
             const double v = wave_sum(acc[q]);
             if (lane == 0) wsum[wid][q] = v;
         }
-        float sb[PER], yb[PER];
-        auto load_slot = [&](int r) {
-            const int64_t o = (int64_t)st.order[r] * nv;
+        for (int r0 = 0; r0 < mc; r0 += kSlotBatch) {
+            float sb[kSlotBatch][8], yb[kSlotBatch][8];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int64_t e = e0 + threadIdx.x + (int64_t)u * kVecThreads;
-                sb[u] = e < e1 ? l.S[o + e] : 0.f;
-                yb[u] = e < e1 ? l.Y[o + e] : 0.f;
+            for (int b = 0; b < kSlotBatch; ++b) {
+                if (r0 + b < mc) {
+                    const int64_t o = (int64_t)st.order[r0 + b] * nv;
+                    if (e < nv) {
+                        ld8(l.S + o, e, nv, vec, sb[b]);
+                        ld8(l.Y + o, e, nv, vec, yb[b]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) { sb[b][u] = 0.f; yb[b][u] = 0.f; }
+                    }
+                }
             }
-        };
-        if (mc > 0) load_slot(0);
-        for (int r = 0; r < mc; ++r) {
-            float sr[PER], yr[PER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) { sr[u] = sb[u]; yr[u] = yb[u]; }
-            if (r + 1 < mc) load_slot(r + 1);          // in flight during this slot's sums
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            for (int b = 0; b < kSlotBatch; ++b) {
+                if (r0 + b < mc) {
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                a0 = fma((double)sr[u], (double)yv[u], a0);
-                a1 = fma((double)yr[u], (double)yv[u], a1);
-                a2 = fma((double)sr[u], (double)gv[u], a2);
-                a3 = fma((double)yr[u], (double)gv[u], a3);
-            }
-            a0 = wave_sum(a0);
-            a1 = wave_sum(a1);
-            a2 = wave_sum(a2);
-            a3 = wave_sum(a3);
-            if (lane == 0) {
-                wsum[wid][kDotsFixed + 4 * r + 0] = a0;
-                wsum[wid][kDotsFixed + 4 * r + 1] = a1;
-                wsum[wid][kDotsFixed + 4 * r + 2] = a2;
-                wsum[wid][kDotsFixed + 4 * r + 3] = a3;
+                    for (int u = 0; u < 8; ++u) {
+                        a0 = fma((double)sb[b][u], (double)yv[u], a0);
+                        a1 = fma((double)yb[b][u], (double)yv[u], a1);
+                        a2 = fma((double)sb[b][u], (double)gv[u], a2);
+                        a3 = fma((double)yb[b][u], (double)gv[u], a3);
+                    }
+                    a0 = wave_sum(a0);
+                    a1 = wave_sum(a1);
+                    a2 = wave_sum(a2);
+                    a3 = wave_sum(a3);
+                    if (lane == 0) {
+                        const int r = r0 + b;
+                        wsum[wid][kDotsFixed + 4 * r + 0] = a0;
+                        wsum[wid][kDotsFixed + 4 * r + 1] = a1;
+                        wsum[wid][kDotsFixed + 4 * r + 2] = a2;
+                        wsum[wid][kDotsFixed + 4 * r + 3] = a3;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -308,7 +351,7 @@ __global__ __launch_bounds__(kIcThreads) void k_lb_decide(const SliceDesc* __res
     decide_body(D[blockIdx.x], s);
 }
 
-__global__ __launch_bounds__(256) void k_lb_finalize(const LbDesc* __restrict__ L) {
+__global__ __launch_bounds__(kFinThreads) void k_lb_finalize(const LbDesc* __restrict__ L) {
     const LbDesc& l = L[blockIdx.x];
     if (l.st->skip_adj) return;
     finalize_body(l);
@@ -319,7 +362,7 @@ hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, h
     return hipGetLastError();
 }
 hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s) {
-    k_lb_finalize<<<n_slices, 256, 0, s>>>(L);
+    k_lb_finalize<<<n_slices, kFinThreads, 0, s>>>(L);
     return hipGetLastError();
 }
 

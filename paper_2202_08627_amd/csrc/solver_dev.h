@@ -2,6 +2,7 @@
 // the kernels whose last finishing block runs a slice's decision and memory update.
 #pragma once
 #include "device_common.h"
+#include "reduce.h"
 #include "eitomo.h"
 
 namespace eit {
@@ -22,43 +23,52 @@ __device__ inline void reset_memory(SolverState& s) {
 }
 
 // Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first). SY and YY
-// are the ring-ordered m_cur x m_cur matrices (row stride kMaxM) in LDS; c, v, e are LDS
-// scratch. Runs in one thread.
+// are the ring-ordered m_cur x m_cur matrices (row stride kMaxM) in LDS. Runs in the first
+// wavefront of the block: lane r owns row r, and each substitution step broadcasts the newly
+// solved component to the other lanes (m_cur <= kMaxM < 64).
+//   c = R^{-1} a (back substitution), v = (D + gamma Y^T Y) c - gamma b,
+//   e = R^{-T} v (forward substitution), g.Hg = gamma g.g + sum_r (a_r e_r - gamma b_r c_r).
 __device__ inline void compact_direction(SolverState& s, const double* a, const double* b,
-                                  const double* SY, const double* YY, double* c, double* v,
-                                  double* e) {
+                                         const double* SY, const double* YY) {
+    const int lane = threadIdx.x;
     const int mc = s.m_cur;
     const int W = kMaxM;
     const double gamma = SY[(mc - 1) * W + (mc - 1)] / YY[(mc - 1) * W + (mc - 1)];
-    for (int r = mc - 1; r >= 0; --r) {                 // c = R^{-1} a (back substitution)
-        double acc = a[r];
-        for (int q = r + 1; q < mc; ++q) acc -= SY[r * W + q] * c[q];
-        c[r] = acc / SY[r * W + r];
+    const bool on = lane < mc;
+    const double Rrr = on ? SY[lane * W + lane] : 1.0;
+    const double ar = on ? a[lane] : 0.0, br = on ? b[lane] : 0.0;
+    double acc = ar, c = 0.0;
+    for (int q = mc - 1; q >= 0; --q) {               // c_q known once rows > q are folded in
+        const double cq = __shfl(acc / Rrr, q);
+        if (lane == q) c = cq;
+        if (lane < q) acc -= SY[lane * W + q] * cq;
     }
-    for (int r = 0; r < mc; ++r) {                      // v = (D + gamma Y^T Y) c - gamma b
-        double acc = SY[r * W + r] * c[r] - gamma * b[r];
-        for (int q = 0; q < mc; ++q) acc += gamma * YY[r * W + q] * c[q];
-        v[r] = acc;
+    double v = on ? Rrr * c - gamma * br : 0.0;
+    for (int q = 0; q < mc; ++q) {
+        const double cq = __shfl(c, q);
+        if (on) v += gamma * YY[lane * W + q] * cq;
     }
-    for (int r = 0; r < mc; ++r) {                      // e = R^{-T} v (forward substitution)
-        double acc = v[r];
-        for (int q = 0; q < r; ++q) acc -= SY[q * W + r] * e[q];
-        e[r] = acc / SY[r * W + r];
+    double acc2 = v, e = 0.0;
+    for (int q = 0; q < mc; ++q) {
+        const double eq = __shfl(acc2 / Rrr, q);
+        if (lane == q) e = eq;
+        if (on && lane > q) acc2 -= SY[q * W + lane] * eq;
     }
-    double gHg = gamma * s.gg;
-    for (int r = 0; r < mc; ++r) gHg += a[r] * e[r] - gamma * b[r] * c[r];
-    for (int r = 0; r < kMaxM; ++r) {
-        s.ee[r] = r < mc ? e[r] : 0.0;
-        s.cc[r] = r < mc ? gamma * c[r] : 0.0;
+    const double t = wave_sum(on ? ar * e - gamma * br * c : 0.0);
+    if (lane < kMaxM) {
+        s.ee[lane] = on ? e : 0.0;
+        s.cc[lane] = on ? gamma * c : 0.0;
     }
-    s.gamma = gamma;
-    s.gd = -gHg;
-    s.alpha = 1.0;
-    s.trials = 0;
-    s.mode = MODE_NEW_DIR;
-    if (!(s.gd < 0.0)) {                                // not a descent direction
-        reset_memory(s);
-        steepest(s);
+    if (lane == 0) {
+        s.gamma = gamma;
+        s.gd = -(gamma * s.gg + t);
+        s.alpha = 1.0;
+        s.trials = 0;
+        s.mode = MODE_NEW_DIR;
+        if (!(s.gd < 0.0)) {                            // not a descent direction
+            reset_memory(s);
+            steepest(s);
+        }
     }
 }
 
@@ -120,7 +130,8 @@ __device__ inline void decide_body(const SliceDesc& d, SolverState& s) {
 }
 
 // ------------------------------------------------------------------------ accept: finalize
-// Block-wide (256 threads), run by the block that completes a slice's update work items:
+constexpr int kFinThreads = 1024;
+// Block-wide (kFinThreads threads), one block per slice:
 // reduce the partial inner products in a fixed order, commit the pair if
 // s.y > 1e-10 ||s|| ||y||, advance the iteration counter, test the stopping rules and
 // compute the next direction's coefficients. The scalar logic runs in one thread on an LDS
@@ -128,10 +139,11 @@ __device__ inline void decide_body(const SliceDesc& d, SolverState& s) {
 __device__ inline void finalize_body(const LbDesc& l) {
     constexpr int W = kMaxM + 1;
     __shared__ double dots[max_dots(kMaxM)];
-    __shared__ double red4[4][64];
+    constexpr int NSUB = kFinThreads / 64;
+    __shared__ double redp[NSUB][64];
     __shared__ double sSY[W * W], sYY[W * W];
     __shared__ double oSY[kMaxM * kMaxM], oYY[kMaxM * kMaxM];
-    __shared__ double av[kMaxM], bv[kMaxM], cs[kMaxM], vs[kMaxM], es[kMaxM];
+    __shared__ double av[kMaxM], bv[kMaxM];
     __shared__ int sorder[kMaxM];
     __shared__ int go, sm2;
     __shared__ SolverState s;          // working copy: the scalar logic touches LDS only
@@ -146,20 +158,26 @@ __device__ inline void finalize_body(const LbDesc& l) {
     const int mc = init ? 0 : s.m_cur;
     const int nd = kDotsFixed + 4 * mc;
     const int stride = max_dots(s.m);
-    // product q = t % 64 summed by the four threads t = q, q+64, q+128, q+192 over interleaved
-    // block rows (independent loads), then combined in a fixed order
-    {
-        const int q = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    // products q0 .. q0+63 at a time: product q = q0 + t % 64 summed by the NSUB threads
+    // t = q - q0 + 64 k over interleaved block rows (independent loads, all in flight), then
+    // combined in a fixed order
+    for (int q0 = 0; q0 < nd; q0 += 64) {
+        const int ql = threadIdx.x & 63, sub = threadIdx.x >> 6, q = q0 + ql;
         double v = 0.0;
         if (q < nd) {
-#pragma unroll 8
-            for (int b = sub; b < l.n_vblocks; b += 4) v += l.part[(int64_t)b * stride + q];
+#pragma unroll 16
+            for (int b = sub; b < l.n_vblocks; b += NSUB) v += l.part[(int64_t)b * stride + q];
         }
-        red4[sub][q] = v;
+        redp[sub][ql] = v;
+        __syncthreads();
+        if ((int)threadIdx.x < 64 && q < nd) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NSUB; ++k) t += redp[k][ql];
+            dots[q] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nd; q += blockDim.x)
-        dots[q] = red4[0][q] + red4[1][q] + red4[2][q] + red4[3][q];
     for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
         sSY[i] = s.SY[i];
         sYY[i] = s.YY[i];
@@ -245,9 +263,9 @@ __device__ inline void finalize_body(const LbDesc& l) {
         }
     }
     __syncthreads();
-    if (go && threadIdx.x == 0) {
-        compact_direction(s, av, bv, oSY, oYY, cs, vs, es);
-        s.skip_adj = 1;
+    if (go && threadIdx.x < 64) {
+        compact_direction(s, av, bv, oSY, oYY);
+        if (threadIdx.x == 0) s.skip_adj = 1;
     }
     __syncthreads();
     {   // write the working copy back

@@ -164,6 +164,25 @@ def test_reconstruct_parity_small(ops, use_graph):
     assert np.all(np.diff(h) <= 0)
 
 
+@pytest.mark.parametrize("m", [3, 20])
+def test_reconstruct_parity_memory_sizes(ops, m):
+    """Smallest and largest L-BFGS memory: with m = 20 the update produces 7 + 4*20 = 87
+    inner products per block, more than one 64-wide pass of the finalize reduction."""
+    cfg = configs.SMALL_64
+    iters = 30
+    say("reconstruct small m=", m)
+    c = synth.make_case(cfg)
+    plan = ops.Plan.from_case(c)
+    x, rep, hist = plan.reconstruct(dev(c.s_exp), iters=iters, lam=cfg.lam, mu_scale=cfg.mu_scale,
+                                    delta_scale=cfg.delta_scale, m=m, cost_hist=True)
+    xo, st, tr = _oracle_recon(c, cfg, iters, m=m)
+    assert rep["rc"] == 0 and rep["iters"] == iters
+    X = host(x)
+    assert rel_l2(X[0], xo[0]) < 1e-3
+    assert rel_l2(X[1], xo[1]) < 1e-3
+    assert np.allclose(host(hist)[1:], tr.cost, rtol=1e-4)
+
+
 def test_reconstruct_forced_line_search_failure(ops):
     cfg = configs.SMALL_64
     c = synth.make_case(cfg)
