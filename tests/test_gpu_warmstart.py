@@ -31,7 +31,8 @@ def test_trained_network_beats_starts_without_it(seed):
     r = WS.evaluate_case(plan, s, net, cfg, tol=1e-3, reps=1)
     print({k: (r[k]["iters"], round(r[k]["err0"], 3), r[k]["choice"]) for k in ("zero", "single_shot", "unet")})
     assert r["unet"]["choice"] == "unet"
-    assert r["unet"]["err0"] < 0.5 * r["single_shot"]["err0"] < 0.5
+    # the network's start is much closer to the plain solution than either start without it
+    assert r["unet"]["err0"] < 0.5 * min(r["single_shot"]["err0"], r["zero"]["err0"])
     for k in ("zero", "single_shot", "unet"):
         assert r[k]["iters"] is not None and r[k]["err"] <= 1e-3
     assert r["unet"]["iters"] < r["zero"]["iters"]
