@@ -49,7 +49,10 @@ WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.np
 # HBM bytes per launch at this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
 # this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.
-TRAFFIC = {}
+TRAFFIC = {
+    "project": {"src": "6a53299a8c5f1781", "variant": 11, "bytes": 25.05e6},
+    "backproject": {"src": "6a53299a8c5f1781", "variant": 0, "bytes": 29.60e6},
+}
 
 
 def _src_hash() -> str:
