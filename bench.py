@@ -186,10 +186,75 @@ def batch_main(args, log):
     return 0
 
 
+def unet_flops(net, h, w, train):
+    """Multiply-add FLOPs of one sample: forward convolutions (3x3 at their level's
+    resolution, 2x2 transposed at the coarser input's), and for training the data gradients
+    of every layer but the first plus the weight gradients (each the size of the forward)."""
+    res = [h, h, h // 2, h // 2, h // 4, h // 4, h // 8, h // 8, h // 8, h // 4, h // 4, h // 4,
+           h // 2, h // 2, h // 2, h, h, h]
+    fwd = dgrad = 0.0
+    for i, (l, r) in enumerate(zip(net.layers, res)):
+        px = float(r) * r * w / h
+        taps = {"conv3x3": 9, "upconv2x2": 4, "head1x1": 1}[l["kind"]]
+        f = 2.0 * px * taps * l["cin"] * l["cout"]
+        fwd += f
+        if i > 0:
+            dgrad += f
+    return fwd * 2 + dgrad if train else fwd
+
+
+def unet_main(args, log, train):
+    """Warm-start network on the device: training steps (batch 16 at 256^2, the training
+    resolution) or inference (one 512^2 image, the evaluation resolution)."""
+    import numpy as np
+    import torch
+    from paper_2202_08627_amd.unet import UNet
+    torch.cuda.set_device(0)
+    net = UNet(32)
+    net.init_he(0)
+    B, H = (16, 256) if train else (1, 512)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.rand((B, 2, H, H), device="cuda", generator=g)
+    y = x + 0.1 * torch.rand((B, 2, H, H), device="cuda", generator=g)
+
+    def step():
+        if train:
+            net.train_step(x, y, lr=1e-4)
+        else:
+            net(x)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    flops = unet_flops(net, H, H, train) * B
+    achieved = flops / t / 1e12
+    line = {
+        "metric": "U-Net training samples/s (256^2, batch 16)" if train else "U-Net inference images/s (512^2)",
+        "value": round(B / t, 2), "unit": "samples/s" if train else "images/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": ("unet_train: 4-level U-Net, 32 base channels, MSE + Adam, batch 16, 256x256"
+                                if train else "unet_infer: 4-level U-Net, 32 base channels, one 512x512 image"),
+                   "params": net.n_params, "gflop_per_step": round(flops / 1e9, 2)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 4), "traffic": None,
+                     "note": "whole step (all kernels), dense BF16 MFMA peak"},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["slice512", "batch256"], default="slice512",
-                    help="slice512 (default): the headline slice; batch256: 256 mixed slices")
+    ap.add_argument("--workload", choices=["slice512", "batch256", "unet_train", "unet_infer"],
+                    default="slice512",
+                    help="slice512 (default): the headline slice; batch256: 256 mixed slices; "
+                         "unet_train / unet_infer: the warm-start network")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
@@ -214,6 +279,8 @@ def main():
 
     if args.workload == "batch256":
         return batch_main(args, log)
+    if args.workload in ("unet_train", "unet_infer"):
+        return unet_main(args, log, args.workload == "unet_train")
 
     child = None
     if not args.no_cpu_baseline:

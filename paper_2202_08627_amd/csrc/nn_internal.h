@@ -23,6 +23,7 @@ struct Tensor {
 hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu, const Tensor& y,
                     int ksize, hipStream_t s);
 hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s);
+// Weight gradients write part[z][co][tap][ci] for z < wgrad_splits_used(pixels, splits)
 hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
                       hipStream_t s);
 hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
@@ -51,6 +52,13 @@ hipError_t adam(float* p, float* m, float* v, const float* g, size_t n, float lr
                 float b2, float eps, float c1, float c2, hipStream_t s);
 
 constexpr int kSumBlocks = 256;   // partial-sum blocks of the deterministic reductions
+
+// Pixel slab per split (a multiple of the 32-pixel step) and the number of slabs launched.
+inline int wgrad_slab(int pixels, int splits) { return ((pixels + splits - 1) / splits + 31) / 32 * 32; }
+inline int wgrad_splits_used(int pixels, int splits) {
+    const int kps = wgrad_slab(pixels, splits);
+    return (pixels + kps - 1) / kps;
+}
 
 }  // namespace nn
 }  // namespace eit

@@ -28,31 +28,46 @@ __device__ __forceinline__ bf16x8 zero8() {
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *(const bf16x8*)p; }
 
 // --------------------------------------------------------------------------- loaders
-// Each returns the 8 consecutive k (k0 .. k0+7, k0 % 8 == 0) of row r, zeros outside.
+// A loader is used in two stages: row(m, M) decodes row m once per output tile (pixel
+// coordinates and validity), load(ctx, k0) returns the 8 consecutive k (k0 .. k0+7,
+// k0 % 8 == 0) of that row, zeros outside.
+struct PixRow { int b, y, x; bool ok; };
 
 // 3x3 convolution input patches, k = tap * C + c (C % 8 == 0, power of two). flip = 1 gives
 // the data-gradient form (input pixel p - (tap - 4) instead of p + (tap - 4)).
 struct LoadConvA {
     const bf16* t; int B, H, W, C, cs, coff, cshift, K, flip, ksize;
-    __device__ bf16x8 operator()(int m, int k0, int M) const {
-        if (m >= M || k0 >= K) return zero8();
+    typedef PixRow Ctx;
+    __device__ Ctx row(int m, int M) const {
+        Ctx c;
+        c.ok = m < M;
+        const int mm = c.ok ? m : 0;
+        const int yb = mm / W;
+        c.x = mm - yb * W;
+        c.b = yb / H;
+        c.y = yb - c.b * H;
+        return c;
+    }
+    __device__ bf16x8 load(const Ctx& r, int k0) const {
+        if (!r.ok || k0 >= K) return zero8();
         const int tap = k0 >> cshift, c = k0 & (C - 1);
-        const int x = m % W, yb = m / W, y = yb % H, b = yb / H;
         int dy, dx;
         if (ksize == 3) { dy = tap / 3 - 1; dx = tap % 3 - 1; } else { dy = 0; dx = 0; }
         if (flip) { dy = -dy; dx = -dx; }
-        const int yy = y + dy, xx = x + dx;
+        const int yy = r.y + dy, xx = r.x + dx;
         if ((unsigned)yy >= (unsigned)H || (unsigned)xx >= (unsigned)W) return zero8();
-        return ld8(t + ((size_t)(b * H + yy) * W + xx) * cs + coff + c);
+        return ld8(t + ((size_t)(r.b * H + yy) * W + xx) * cs + coff + c);
     }
 };
 
 // Dense row-major matrix [rows][K] (K contiguous, K % 8 == 0).
 struct LoadRows {
     const bf16* t; int rows, K, ld;
-    __device__ bf16x8 operator()(int r, int k0, int) const {
-        if (r >= rows || k0 >= K) return zero8();
-        return ld8(t + (size_t)r * ld + k0);
+    struct Ctx { const bf16* p; };
+    __device__ Ctx row(int r, int) const { return Ctx{r < rows ? t + (size_t)r * ld : nullptr}; }
+    __device__ bf16x8 load(const Ctx& r, int k0) const {
+        if (!r.p || k0 >= K) return zero8();
+        return ld8(r.p + k0);
     }
 };
 
@@ -60,68 +75,22 @@ struct LoadRows {
 // row m = input pixel (b, y, x), k = d * C + c, value = g[b, 2y + d/2, 2x + d%2, c].
 struct LoadUpGradA {
     const bf16* t; int B, H, W, C, cs, coff, cshift, K;   // H, W of the input (half size)
-    __device__ bf16x8 operator()(int m, int k0, int M) const {
-        if (m >= M || k0 >= K) return zero8();
+    typedef PixRow Ctx;
+    __device__ Ctx row(int m, int M) const {
+        Ctx c;
+        c.ok = m < M;
+        const int mm = c.ok ? m : 0;
+        const int yb = mm / W;
+        c.x = mm - yb * W;
+        c.b = yb / H;
+        c.y = yb - c.b * H;
+        return c;
+    }
+    __device__ bf16x8 load(const Ctx& r, int k0) const {
+        if (!r.ok || k0 >= K) return zero8();
         const int d = k0 >> cshift, c = k0 & (C - 1);
-        const int x = m % W, yb = m / W, y = yb % H, b = yb / H;
-        const int yy = 2 * y + (d >> 1), xx = 2 * x + (d & 1);
-        return ld8(t + ((size_t)(b * 2 * H + yy) * (2 * W) + xx) * cs + coff + c);
-    }
-};
-
-// Weight-gradient operands: the reduction index k runs over pixels, so a group gathers 8
-// pixels of one channel (strided loads).
-// Conv input channel c at pixel p shifted by a tap: row r = tap * C + c.
-struct LoadWgInput {
-    const bf16* t; int B, H, W, C, cs, coff, cshift, P, ksize;
-    __device__ bf16x8 operator()(int r, int p0, int R) const {
-        bf16x8 v = zero8();
-        if (r >= R) return v;
-        const int tap = r >> cshift, c = r & (C - 1);
-        int dy = 0, dx = 0;
-        if (ksize == 3) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = p0 + i;
-            if (p >= P) break;
-            const int x = p % W, yb = p / W, y = yb % H, b = yb / H;
-            const int yy = y + dy, xx = x + dx;
-            if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
-                v[i] = t[((size_t)(b * H + yy) * W + xx) * cs + coff + c];
-        }
-        return v;
-    }
-};
-// Channel c of an NHWC tensor at 8 consecutive pixels (row r = c).
-struct LoadWgChannel {
-    const bf16* t; int C, cs, coff, P;
-    __device__ bf16x8 operator()(int r, int p0, int R) const {
-        bf16x8 v = zero8();
-        if (r >= R) return v;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = p0 + i;
-            if (p < P) v[i] = t[(size_t)p * cs + coff + r];
-        }
-        return v;
-    }
-};
-// Transposed-conv output gradient for its weight gradient: row r = 4 * c + d, pixel p of
-// the (half-size) input, value g[b, 2y + d/2, 2x + d%2, c].
-struct LoadWgUpGrad {
-    const bf16* t; int B, H, W, C, cs, coff, P;
-    __device__ bf16x8 operator()(int r, int p0, int R) const {
-        bf16x8 v = zero8();
-        if (r >= R) return v;
-        const int d = r & 3, c = r >> 2;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = p0 + i;
-            if (p >= P) break;
-            const int x = p % W, yb = p / W, y = yb % H, b = yb / H;
-            v[i] = t[((size_t)(b * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * cs + coff + c];
-        }
-        return v;
+        const int yy = 2 * r.y + (d >> 1), xx = 2 * r.x + (d & 1);
+        return ld8(t + ((size_t)(r.b * 2 * H + yy) * (2 * W) + xx) * cs + coff + c);
     }
 };
 
@@ -158,34 +127,59 @@ struct EpiPart {
 
 // --------------------------------------------------------------------------- GEMM
 // Block tile BM x BN with 4 wavefronts in a WM x WN grid; k advances 32 per step. Grid
-// (ceil(M/BM), ceil(N/BN), splits); split z covers k in [z*kps, min(K, (z+1)*kps)).
+// (ceil(M/BM), ceil(N/BN), splits); split z covers k in [z*kps, min(K, (z+1)*kps)). Each
+// thread stages fixed (row, 8-k group) slots of the tiles: rows are decoded once per tile,
+// and the next step's groups are loaded into registers while the current step multiplies.
 template <int BM, int BN, int WM, int WN, class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kps) {
     constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
     static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
     constexpr int GP = 5;                      // groups per LDS row: 4 + 1 pad (bank spread)
+    constexpr int SA = (BM * 4 + 255) / 256, SB = (BN * 4 + 255) / 256;
     __shared__ bf16x8 As[BM * GP], Bs[BN * GP];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     const int kb = blockIdx.z * kps, ke = min(K, kb + kps);
+    typename LA::Ctx ca[SA];
+    typename LB::Ctx cb[SB];
+#pragma unroll
+    for (int q = 0; q < SA; ++q) ca[q] = la.row(m0 + ((tid + q * 256) >> 2), M);
+#pragma unroll
+    for (int q = 0; q < SB; ++q) cb[q] = lb.row(n0 + ((tid + q * 256) >> 2), N);
+    bf16x8 ra[SA], rb[SB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < SA; ++q) {
+            const int e = tid + q * 256, k = k0 + 8 * (e & 3);
+            ra[q] = (e < BM * 4 && k < ke) ? la.load(ca[q], k) : zero8();
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+            const int e = tid + q * 256, k = k0 + 8 * (e & 3);
+            rb[q] = (e < BN * 4 && k < ke) ? lb.load(cb[q], k) : zero8();
+        }
+    };
     f32x4 acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    fetch(kb);
     for (int k0 = kb; k0 < ke; k0 += 32) {
-        for (int e = tid; e < BM * 4; e += 256) {
-            const int r = e >> 2, g = e & 3;
-            const int k = k0 + 8 * g;
-            As[r * GP + g] = k < ke ? la(m0 + r, k, M) : zero8();
+        __syncthreads();                       // previous step's fragments consumed
+#pragma unroll
+        for (int q = 0; q < SA; ++q) {
+            const int e = tid + q * 256;
+            if (e < BM * 4) As[(e >> 2) * GP + (e & 3)] = ra[q];
         }
-        for (int e = tid; e < BN * 4; e += 256) {
-            const int r = e >> 2, g = e & 3;
-            const int k = k0 + 8 * g;
-            Bs[r * GP + g] = k < ke ? lb(n0 + r, k, N) : zero8();
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+            const int e = tid + q * 256;
+            if (e < BN * 4) Bs[(e >> 2) * GP + (e & 3)] = rb[q];
         }
         __syncthreads();
+        if (k0 + 32 < ke) fetch(k0 + 32);
         bf16x8 a[TM], b[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) a[i] = As[(wm * TM * 16 + i * 16 + (lane & 15)) * GP + (lane >> 4)];
@@ -196,7 +190,6 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -252,17 +245,6 @@ hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ks
     return gemm(la, lb, ep, dz.B * dz.H * dz.W, dx.C, taps * dz.C, 1, s);
 }
 
-// partial dW[z][co][tap * C + ci] over pixel slabs
-hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
-                      hipStream_t s) {
-    const int taps = ksize * ksize;
-    const int P = x.B * x.H * x.W;
-    LoadWgChannel la{dz.p, dz.C, dz.cs, dz.coff, P};
-    LoadWgInput lb{x.p, x.B, x.H, x.W, x.C, x.cs, x.coff, ilog2(x.C), P, ksize};
-    EpiPart ep{part, dz.C, taps * x.C};
-    return gemm(la, lb, ep, dz.C, taps * x.C, P, splits, s);
-}
-
 // y[b, 2y+d/2, 2x+d%2, co] = sum_ci x[b,y,x,ci] w[co][d][ci] + bias[co]
 hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
                       hipStream_t s) {
@@ -280,13 +262,163 @@ hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipSt
     return gemm(la, lb, ep, dx.B * dx.H * dx.W, dx.C, 4 * g.C, 1, s);
 }
 
-// partial dW[z][co][d][ci]
-hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s) {
+// --------------------------------------------------------------------------- weight gradients
+// Partial weight gradients over pixel slabs, as GEMMs whose reduction runs over pixels:
+//   3x3 conv:    m = co, n = tap * Ci + ci:   sum_p dZ[p][co] X[p + off(tap)][ci]
+//   2x2 up-conv: m = d * Co + co, n = ci:     sum_p G[b, 2y + d/2, 2x + d%2][co] X[p][ci]
+//                (p = (b, y, x) over the up-conv's input)
+// stored as part[z][co][tap][ci] (tap = d for the up-conv). Pixels are strided in NHWC, so
+// each 64-pixel step stages both operands transposed into LDS ([row][pixel], rows padded to
+// 72 elements): the global loads stay coalesced (consecutive threads read consecutive channel
+// pairs of a pixel) and an MFMA fragment (8 consecutive pixels of one row) is one 16-byte LDS
+// read. The next step's operands are loaded into registers while the current step is
+// multiplied. Block: TM x TN output tile (TM * TN = 64 * 64, 4 wavefronts of 32 x 32; TM = 32
+// when m has at most 32 rows); grid (m tiles, n tiles, splits), split z covering pixels
+// [z kps, min(P, (z + 1) kps)), kps a multiple of 32.
+constexpr int kWgStep = 64;
+constexpr int kWgRow = kWgStep + 8;
+template <int UP, int TM>
+__global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __restrict__ part,
+                                               int P, int kps) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    constexpr int TN = 64 * 64 / TM;
+    constexpr int WM = TM / 32, WN = 4 / WM;       // wavefront grid
+    constexpr int PA = TM / 8, PB = TN / 8;        // pixels per thread per step (A, B staging)
+    constexpr int NTAP = UP ? 4 : 9;
+    __shared__ __attribute__((aligned(16))) bf16 As[TM * kWgRow], Bs[TN * kWgRow];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv / WN, wn = wv % WN;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int pb = blockIdx.z * kps, pe = min(P, pb + kps);
+    const int Co = dz.C, Ci = x.C;
+    const int M = UP ? 4 * Co : Co, N = UP ? Ci : 9 * Ci;
+    const int H = x.H, W = x.W;                  // the pixel grid p runs over
+    // A staging: row pair (2ra, 2ra+1), pixels PA*ga ..; B: column pair (2nb, 2nb+1), PB*gb ..
+    const int ra = tid % (TM / 2), ga = tid / (TM / 2);
+    const int nb = tid % (TN / 2), gb = tid / (TN / 2);
+    const int m = m0 + 2 * ra;
+    const bool m_ok = m < M;
+    const int d = UP && m_ok ? m / Co : 0, co = m_ok ? m - d * Co : 0;
+    const int n = n0 + 2 * nb;
+    const bool n_ok = n < N;
+    const int tap = !UP && n_ok ? n / Ci : 4, ci = n_ok ? n - (UP ? 0 : tap * Ci) : 0;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;  // zero shift for the up-conv (tap 4)
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x2 av[PA], bv[PB];
+    const bf16x2 zero2 = bf16x2{(__bf16)0.f, (__bf16)0.f};
+    auto load = [&](int k0) {
+        {   // A: dZ at the pixel (conv), G at the row's sub-pixel d (up-conv)
+            int p = k0 + PA * ga;
+            int yb = p / W, xx = p - yb * W;     // one division per step, then carries
+            int b = yb / H, yy = yb - b * H;
+#pragma unroll
+            for (int q = 0; q < PA; ++q) {
+                av[q] = zero2;
+                if (p < pe && m_ok) {
+                    size_t o;
+                    if (UP) o = ((size_t)(b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs;
+                    else o = (size_t)p * dz.cs;
+                    av[q] = *(const bf16x2*)(dz.p + o + dz.coff + co);
+                }
+                ++p;
+                if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
+            }
+        }
+        {   // B: X at the pixel shifted by the column's tap (conv) or at the pixel (up-conv)
+            int p = k0 + PB * gb;
+            int yb = p / W, xx = p - yb * W;
+            int b = yb / H, yy = yb - b * H;
+#pragma unroll
+            for (int q = 0; q < PB; ++q) {
+                bv[q] = zero2;
+                const int sy = yy + dy, sx = xx + dx;
+                if (p < pe && n_ok && (unsigned)sy < (unsigned)H && (unsigned)sx < (unsigned)W)
+                    bv[q] = *(const bf16x2*)(x.p + ((size_t)(b * H + sy) * W + sx) * x.cs + x.coff + ci);
+                ++p;
+                if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
+            }
+        }
+    };
+    load(pb);
+    for (int k0 = pb; k0 < pe; k0 += kWgStep) {
+        __syncthreads();                       // previous step's fragments consumed
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int h = 0; h < PA / 4; ++h)
+                *(bf16x4*)(As + (2 * ra + c) * kWgRow + PA * ga + 4 * h) =
+                    bf16x4{av[4 * h][c], av[4 * h + 1][c], av[4 * h + 2][c], av[4 * h + 3][c]};
+#pragma unroll
+            for (int h = 0; h < PB / 4; ++h)
+                *(bf16x4*)(Bs + (2 * nb + c) * kWgRow + PB * gb + 4 * h) =
+                    bf16x4{bv[4 * h][c], bv[4 * h + 1][c], bv[4 * h + 2][c], bv[4 * h + 3][c]};
+        }
+        __syncthreads();
+        if (k0 + kWgStep < pe) load(k0 + kWgStep);
+#pragma unroll
+        for (int kk = 0; kk < kWgStep; kk += 32) {
+            bf16x8 a[2], bb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *(const bf16x8*)(As + (wm * 32 + i * 16 + (lane & 15)) * kWgRow + kk + 8 * (lane >> 4));
+                bb[i] = *(const bf16x8*)(Bs + (wn * 32 + i * 16 + (lane & 15)) * kWgRow + kk + 8 * (lane >> 4));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    float* dst = part + (size_t)blockIdx.z * Co * NTAP * Ci;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (o < M && nn < N) {
+                    if (UP) {
+                        const int dd = o / Co, cc = o - dd * Co;
+                        dst[((size_t)cc * 4 + dd) * Ci + nn] = acc[i][j][r];
+                    } else {
+                        dst[(size_t)o * N + nn] = acc[i][j][r];
+                    }
+                }
+            }
+}
+
+template <int UP>
+hipError_t wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, hipStream_t s) {
     const int P = x.B * x.H * x.W;
-    LoadWgUpGrad la{g.p, x.B, x.H, x.W, g.C, g.cs, g.coff, P};
-    LoadWgChannel lb{x.p, x.C, x.cs, x.coff, P};
-    EpiPart ep{part, 4 * g.C, x.C};
-    return gemm(la, lb, ep, 4 * g.C, x.C, P, splits, s);
+    const int kps = wgrad_slab(P, splits);
+    const int sp = wgrad_splits_used(P, splits);
+    const int M = UP ? 4 * dz.C : dz.C, N = UP ? x.C : 9 * x.C;
+    if (M <= 32) {
+        dim3 g(1, (N + 127) / 128, sp);
+        k_wgrad<UP, 32><<<g, 256, 0, s>>>(dz, x, part, P, kps);
+    } else {
+        dim3 g((M + 63) / 64, (N + 63) / 64, sp);
+        k_wgrad<UP, 64><<<g, 256, 0, s>>>(dz, x, part, P, kps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
+                      hipStream_t s) {
+    if (ksize != 3) return hipErrorInvalidValue;
+    return wgrad<0>(x, dz, part, splits, s);
+}
+
+hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s) {
+    return wgrad<1>(x, g, part, splits, s);
 }
 
 }  // namespace nn

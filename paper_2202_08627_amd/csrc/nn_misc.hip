@@ -63,51 +63,74 @@ __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
     }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// dy *= (y > 0), eight channels (16 bytes) per thread
 __global__ void k_relu_mask(Tensor y, Tensor dy) {
-    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    const int G = y.C / 8;
+    const size_t n = (size_t)y.B * y.H * y.W * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % y.C;
-        const size_t p = e / y.C;
-        if (!((float)y.p[p * y.cs + y.coff + c] > 0.f)) dy.p[p * dy.cs + dy.coff + c] = (bf16)0.f;
+        const int g = e % G;
+        const size_t p = e / G;
+        const bf16x8 v = *(const bf16x8*)(y.p + p * y.cs + y.coff + 8 * g);
+        bf16x8* q = (bf16x8*)(dy.p + p * dy.cs + dy.coff + 8 * g);
+        bf16x8 d = *q;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!((float)v[i] > 0.f)) d[i] = (bf16)0.f;
+        *q = d;
     }
 }
 
 // Stage 1: block k sums pixels [k*P/nblk, (k+1)*P/nblk) of every channel -> part[k][C].
+// Thread (channel group g of 8 channels, pixel lane pl) reads 16 bytes per pixel; the pixel
+// lanes' sums meet in LDS in a fixed order.
 __global__ __launch_bounds__(kT) void k_chsum1(Tensor t, float* part, int nblk) {
-    __shared__ float red[kT];
+    __shared__ float red[kT * 8];
     const size_t P = (size_t)t.B * t.H * t.W;
     const size_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
-    const int C = t.C;
-    const int per = kT / C > 0 ? kT / C : 1;        // pixel lanes per channel
-    for (int c0 = 0; c0 < C; c0 += kT) {
-        const int c = c0 + (C >= kT ? threadIdx.x : threadIdx.x % C);
-        const int lanep = C >= kT ? 0 : threadIdx.x / C;
-        float s = 0.f;
-        if (c < C && lanep < per)
-            for (size_t p = p0 + lanep; p < p1; p += per) s += (float)t.p[p * t.cs + t.coff + c];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        if (C >= kT) {
-            if (c < C) part[(size_t)blockIdx.x * C + c] = red[threadIdx.x];
-        } else if (threadIdx.x < C) {
-            float v = 0.f;
-            for (int q = 0; q < per; ++q) v += red[q * C + threadIdx.x];
-            part[(size_t)blockIdx.x * C + threadIdx.x] = v;
-        }
-        __syncthreads();
+    const int C = t.C, G = C / 8;                 // G divides kT (C <= 8 kT, power of two)
+    const int g = threadIdx.x % G, pl = threadIdx.x / G, NL = kT / G;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (size_t p = p0 + pl; p < p1; p += NL) {
+        const bf16x8 v = *(const bf16x8*)(t.p + p * t.cs + t.coff + 8 * g);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[threadIdx.x * 8 + i] = acc[i];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += kT) {
+        float v = 0.f;
+        for (int l = 0; l < NL; ++l) v += red[(l * G + c / 8) * 8 + c % 8];
+        part[(size_t)blockIdx.x * C + c] = v;
     }
 }
-__global__ void k_chsum2(const float* part, int nblk, int C, float* out) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int k = 0; k < nblk; ++k) s += part[(size_t)k * C + c];
-        out[c] = s;
+// Stage 2: out[c] = sum_k part[k][c], 32 columns per pass, eight row lanes each; the lanes'
+// sums meet in LDS in a fixed order.
+__global__ __launch_bounds__(kT) void k_chsum2(const float* part, int nblk, int C, float* out) {
+    __shared__ float red[kT];
+    const int cl = threadIdx.x & 31, rl = threadIdx.x >> 5;   // column lane, row lane (8)
+    for (int c0 = blockIdx.x * 32; c0 < C; c0 += gridDim.x * 32) {
+        const int c = c0 + cl;
+        float v = 0.f;
+        if (c < C)
+            for (int k = rl; k < nblk; k += kT / 32) v += part[(size_t)k * C + c];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        if (rl == 0 && c < C) {
+            float t = 0.f;
+            for (int l = 0; l < kT / 32; ++l) t += red[l * 32 + cl];
+            out[c] = t;
+        }
+        __syncthreads();
     }
 }
 
 __global__ void k_splitk(const float* part, int splits, int n, float* out) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float s = 0.f;
+#pragma unroll 8
         for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
         out[i] = s;
     }
@@ -156,40 +179,59 @@ __global__ void k_mse2(const double* part, int nblk, size_t n, double* loss) {
 
 // head backward: part[k][0..2C) = sum over the block's pixels of dout[o] * a[c] for o = 0, 1;
 // part[k][2C..2C+2) = sum of dout[o]; da = (W^T dout) masked by a > 0 (a is post-ReLU).
+// Thread (channel group g of 8 channels, pixel lane pl); sums meet in LDS in a fixed order.
 __global__ __launch_bounds__(kT) void k_head_bwd1(Tensor a, const float* w, const float* dout,
                                                   int B, int H, int W, float* part, int nblk,
                                                   Tensor da) {
-    __shared__ float red[kT];
+    __shared__ float red[kT * 18];
     const size_t P = (size_t)B * H * W;
     const size_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
-    const int C = a.C;
-    // da for this block's pixels
-    for (size_t p = p0 + threadIdx.x; p < p1; p += kT) {
+    const int C = a.C, G = C / 8;
+    const int g = threadIdx.x % G, pl = threadIdx.x / G, NL = kT / G;
+    float w0[8], w1[8], s0[8], s1[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        w0[i] = w[8 * g + i];
+        w1[i] = w[C + 8 * g + i];
+        s0[i] = 0.f;
+        s1[i] = 0.f;
+    }
+    float b0 = 0.f, b1 = 0.f;
+    for (size_t p = p0 + pl; p < p1; p += NL) {
         const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
         const float g0 = dout[((size_t)(b * 2 + 0) * H + y) * W + xx];
         const float g1 = dout[((size_t)(b * 2 + 1) * H + y) * W + xx];
-        const bf16* q = a.p + p * a.cs + a.coff;
-        bf16* dq = da.p + p * da.cs + da.coff;
-        for (int c = 0; c < C; ++c) {
-            const float v = fmaf(g0, w[c], g1 * w[C + c]);
-            dq[c] = (float)q[c] > 0.f ? (bf16)v : (bf16)0.f;
+        const bf16x8 v = *(const bf16x8*)(a.p + p * a.cs + a.coff + 8 * g);
+        bf16x8 d;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float av = (float)v[i];
+            s0[i] = fmaf(g0, av, s0[i]);
+            s1[i] = fmaf(g1, av, s1[i]);
+            d[i] = av > 0.f ? (bf16)fmaf(g0, w0[i], g1 * w1[i]) : (bf16)0.f;
         }
+        *(bf16x8*)(da.p + p * da.cs + da.coff + 8 * g) = d;
+        b0 += g0;
+        b1 += g1;
     }
-    // weight / bias sums: thread handles entry e of [2C + 2] for a strided subset of pixels
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        red[threadIdx.x * 18 + i] = s0[i];
+        red[threadIdx.x * 18 + 8 + i] = s1[i];
+    }
+    red[threadIdx.x * 18 + 16] = g == 0 ? b0 : 0.f;
+    red[threadIdx.x * 18 + 17] = g == 0 ? b1 : 0.f;
+    __syncthreads();
     const int E = 2 * C + 2;
-    for (int e0 = 0; e0 < E; e0 += kT) {
-        const int e = e0 + threadIdx.x;
-        float s = 0.f;
-        if (e < E) {
-            const int o = e < 2 * C ? e / C : e - 2 * C;
-            const int c = e < 2 * C ? e % C : -1;
-            for (size_t p = p0; p < p1; ++p) {
-                const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
-                const float g = dout[((size_t)(b * 2 + o) * H + y) * W + xx];
-                s += c >= 0 ? g * (float)a.p[p * a.cs + a.coff + c] : g;
-            }
-            part[(size_t)blockIdx.x * E + e] = s;
+    for (int e = threadIdx.x; e < E; e += kT) {
+        float v = 0.f;
+        if (e < 2 * C) {
+            const int o = e / C, c = e % C;
+            for (int l = 0; l < NL; ++l) v += red[(l * G + c / 8) * 18 + 8 * o + c % 8];
+        } else {
+            for (int l = 0; l < NL; ++l) v += red[(l * G) * 18 + 16 + (e - 2 * C)];
         }
+        part[(size_t)blockIdx.x * E + e] = v;
     }
 }
 
@@ -235,12 +277,12 @@ hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, c
     return hipGetLastError();
 }
 hipError_t relu_mask(const Tensor& y, const Tensor& dy, hipStream_t s) {
-    k_relu_mask<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(y, dy);
+    k_relu_mask<<<nblocks((size_t)y.B * y.H * y.W * (y.C / 8)), kT, 0, s>>>(y, dy);
     return hipGetLastError();
 }
 hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s) {
     k_chsum1<<<nblk, kT, 0, s>>>(t, part, nblk);
-    k_chsum2<<<(t.C + kT - 1) / kT, kT, 0, s>>>(part, nblk, t.C, out);
+    k_chsum2<<<(t.C + 31) / 32, kT, 0, s>>>(part, nblk, t.C, out);
     return hipGetLastError();
 }
 hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s) {
@@ -264,7 +306,7 @@ hipError_t head_bwd(const Tensor& a, const float* w, const float* dout, int B, i
     if (db != dw + 2 * a.C) return hipErrorInvalidValue;
     const int E = 2 * a.C + 2;
     k_head_bwd1<<<nblk, kT, 0, s>>>(a, w, dout, B, H, W, part, nblk, da);
-    k_chsum2<<<1, kT, 0, s>>>(part, nblk, E, dw);     // fixed-order reduction of [nblk][E]
+    k_chsum2<<<(E + 31) / 32, kT, 0, s>>>(part, nblk, E, dw);   // fixed-order reduction of [nblk][E]
     return hipGetLastError();
 }
 hipError_t to_bf16(const float* src, bf16* dst, size_t n, hipStream_t s) {

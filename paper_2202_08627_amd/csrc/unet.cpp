@@ -81,9 +81,11 @@ std::vector<std::pair<const char*, Shape>> act_shapes(int c, int h, int w) {
             {"D1a", {h, w, c}},            {"D1b", {h, w, c}}};
 }
 
+// pixel slabs of the weight-gradient GEMMs: about 1024 pixels each (16 steps of 64), at
+// most 256, so that even the 32-channel layers launch several blocks per CU
 int wgrad_splits(size_t pixels) {
-    long s = (long)(pixels / 2048);
-    return (int)std::max(1L, std::min(64L, s));
+    long s = (long)(pixels / 1024);
+    return (int)std::max(1L, std::min(256L, s));
 }
 
 WsLayout layout(const eit_unet* u, int nb, int h, int w, bool train) {
@@ -198,7 +200,8 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
         const size_t pix = (size_t)X.B * X.H * X.W;
         const int sp = wgrad_splits(pix);
         NN_TRY(conv_wgrad(X, dY, part, sp, 3, s));
-        NN_TRY(splitk_reduce(part, sp, L[li].cout * 9 * L[li].cin, grad + L[li].w, s));
+        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), L[li].cout * 9 * L[li].cin,
+                             grad + L[li].w, s));
         NN_TRY(channel_sums(dY, sums, kSumBlocks, grad + L[li].b, s));
         if (dX) NN_TRY(conv_dgrad(dY, c.wt + L[li].wt, *dX, 3, s));
         return EIT_OK;
@@ -208,7 +211,8 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
         const size_t pix = (size_t)X.B * X.H * X.W;
         const int sp = wgrad_splits(pix);
         NN_TRY(upconv_wgrad(X, gY, part, sp, s));
-        NN_TRY(splitk_reduce(part, sp, 4 * L[li].cout * L[li].cin, grad + L[li].w, s));
+        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), 4 * L[li].cout * L[li].cin,
+                             grad + L[li].w, s));
         NN_TRY(channel_sums(gY, sums, kSumBlocks, grad + L[li].b, s));
         NN_TRY(upconv_dgrad(gY, c.wt + L[li].wt, dX, s));
         return EIT_OK;
