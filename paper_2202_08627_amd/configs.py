@@ -37,6 +37,7 @@ class SliceConfig:
     n_mask: int                 # sample-mask positions per illumination curve
     phantom: str = "random"     # "random" ellipses or "shepp" (Shepp-Logan-style)
     n_ellipses: int = 6
+    axis_max: float = 0.4       # random ellipses: semi-axes U[0.08, axis_max] * n/2
     sigma: float = 0.6          # flat IC Gaussian width, mask periods
     sigma_jitter: float = 0.0   # per-pixel relative jitter of sigma (uniform +-)
     counts: float = 1e4         # flat-field peak counts (Poisson level)

@@ -66,11 +66,12 @@ def mask_positions(n_mask: int) -> np.ndarray:
     return (np.arange(n_mask, dtype=np.float64) + 0.5) / n_mask - 0.5
 
 
-def random_ellipses(n: int, n_ell: int, rng: np.random.Generator) -> np.ndarray:
-    """Random ellipses inside radius 0.9*n/2; raw values U(0,1) per map."""
+def random_ellipses(n: int, n_ell: int, rng: np.random.Generator, axis_max: float = 0.4) -> np.ndarray:
+    """Random ellipses inside radius 0.9*n/2 (semi-axes U[0.08, axis_max] * n/2, at most
+    0.8 * n/2); raw values U(0,1) per map."""
     half = n / 2.0
-    a = rng.uniform(0.08, 0.4, n_ell) * half
-    b = rng.uniform(0.08, 0.4, n_ell) * half
+    a = rng.uniform(0.08, axis_max, n_ell) * half
+    b = rng.uniform(0.08, axis_max, n_ell) * half
     phi = rng.uniform(0.0, np.pi, n_ell)
     rmax = 0.9 * half - np.maximum(a, b)
     rc = rmax * np.sqrt(rng.uniform(0.0, 1.0, n_ell))
@@ -147,7 +148,7 @@ def ellipse_line_integrals(ell: np.ndarray, col: int, theta: np.ndarray, t: np.n
 
 def make_phantom(cfg: SliceConfig, rng: np.random.Generator) -> Phantom:
     if cfg.phantom == "random":
-        ell = random_ellipses(cfg.n, cfg.n_ellipses, rng)
+        ell = random_ellipses(cfg.n, cfg.n_ellipses, rng, cfg.axis_max)
     elif cfg.phantom == "shepp":
         ell = shepp_style_ellipses(cfg.n, max(cfg.n_ellipses - 2, 1), rng)
     else:

@@ -26,10 +26,11 @@ from . import configs, ops, synth
 from .unet import UNet
 
 
-def slice_config(n: int, n_theta: int, n_mask: int = 8, seed: int = 0) -> configs.SliceConfig:
+def slice_config(n: int, n_theta: int, n_mask: int = 8, seed: int = 0,
+                 axis_max: float = 0.4) -> configs.SliceConfig:
     """Random-ellipse slice with per-pixel sigma jitter, the warm-start workload."""
     return configs.SliceConfig(n=n, n_theta=n_theta, n_det=n, n_mask=n_mask, phantom="random",
-                               n_ellipses=6, sigma=0.6, sigma_jitter=0.05,
+                               n_ellipses=6, axis_max=axis_max, sigma=0.6, sigma_jitter=0.05,
                                mu_scale=configs.mu_range_for(n), seed=seed)
 
 
@@ -303,6 +304,9 @@ def _main():
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--workers", type=int, default=16)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--axis-max", type=float, default=0.4,
+                   help="largest ellipse semi-axis as a fraction of n/2 (0.8 at 256^2 spans the "
+                        "pixel sizes of 0.4 at 512^2)")
     t.add_argument("--out", required=True, help="weights .npz (a .json log is written beside it)")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=None)
@@ -318,7 +322,7 @@ def _main():
         print(msg, flush=True)
 
     if a.cmd == "train":
-        cfg = slice_config(W.train_n, W.train_theta, W.n_mask)
+        cfg = slice_config(W.train_n, W.train_theta, W.n_mask, axis_max=a.axis_max)
         t0 = time.time()
         X, Y, st = build_training_set(cfg, range(a.n_train + a.n_val), a.target_iters,
                                       workers=a.workers, log=log)
@@ -332,6 +336,7 @@ def _main():
                      val=val)
         t_train = time.time() - t1
         meta = {"n_train": a.n_train, "n_val": a.n_val, "target_iters": a.target_iters,
+                "axis_max": a.axis_max,
                 "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "seed": a.seed,
                 "train_shape": [W.train_n, W.train_theta, W.n_mask], "data_stats": st,
                 "data_s": t_data, "train_s": t_train, "loss_hist": hist,
