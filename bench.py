@@ -37,7 +37,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "slice-iters/s (512², 720 angles) and time-to-1e-3 tol, plain vs warm start"
-PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (counts packed FP32)
+PEAK_FP32_UNPACKED = 78.6     # 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz, one FMA per lane
+PEAK_LDS_TBS = 78.6           # 256 CUs x 128 B/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 # algorithmic work per unit: projector fused sample (both maps: 2 x (2 mul + 2 add) for the
 # interpolation weights applied to two voxels, plus the strip accumulation) and adjoint
@@ -340,10 +342,14 @@ def main():
     traffic = None
     if tr and tr.get("src") == _src_hash() and tr.get("variant") == (info["proj_variant"] if dom == "project" else info["adj_variant"]):
         traffic = tr["bytes"]
+    units = float(n) * nt * nd if dom == "project" else float(n) * n * nt
+    lds_bytes = 16.0 * units                   # one 16-byte read of both neighbours per unit
     roof = {
         "bound": "alu", "kernel": kname,
         "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "peak_unpacked": PEAK_FP32_UNPACKED, "frac_unpacked": round(achieved / PEAK_FP32_UNPACKED, 4),
+        "lds_alg_bytes": lds_bytes, "lds_frac": round(lds_bytes / (ms * 1e-3) / 1e12 / PEAK_LDS_TBS, 4),
         "launch_us": round(ms * 1e3, 2),
         "hbm_alg_bytes": hbm_alg[dom],
         "hbm_frac": round(hbm_alg[dom] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5),
