@@ -126,9 +126,13 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             else
                 buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
         };
+        // (WIDE staging) a wavefront whose first staged column lies past the window skips its
+        // loads and LDS writes: entries at or past win_w are never read
+        const int c0w = __builtin_amdgcn_readfirstlane(sc);
         auto load_strip = [&](int s) {
             const int lo = cld(lo_tab + s);
             if constexpr (WIDE) {
+                if (c0w >= win_w) return;
                 const int col = lo + sc;
                 const bool ok = sc < win_w && (unsigned)col < (unsigned)n;
                 const bool ok1 = DUP != 0 && sc + 1 < win_w && (unsigned)(col + 1) < (unsigned)n;
@@ -158,8 +162,11 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             __syncthreads();                           // previous strip fully consumed
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
-                if constexpr (WIDE) win[(sr + q * RS) * PW + sc] = buf[q];
-                else win[(q / CS) * PW + tid + (q % CS) * NT] = buf[q];
+                if constexpr (WIDE) {
+                    if (c0w < win_w) win[(sr + q * RS) * PW + sc] = buf[q];
+                } else {
+                    win[(q / CS) * PW + tid + (q % CS) * NT] = buf[q];
+                }
             }
             __syncthreads();
             if (s + 1 < ns) load_strip(s + 1);         // in flight during this strip
@@ -465,7 +472,11 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     X(8, 1, 64, 16, 128, 0)    \
     X(9, 16, 64, 16, 256, 1)   \
     X(10, 16, 64, 8, 256, 1)   \
-    X(11, 8, 64, 8, 256, 1)
+    X(11, 8, 64, 8, 256, 1)    \
+    X(12, 8, 64, 8, 128, 1)    \
+    X(13, 8, 64, 16, 128, 1)   \
+    X(14, 4, 64, 16, 128, 1)   \
+    X(15, 4, 64, 8, 128, 1)
 
 // Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
