@@ -137,7 +137,7 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
                 const bool ok = sc < win_w && (unsigned)col < (unsigned)n;
                 const bool ok1 = DUP != 0 && sc + 1 < win_w && (unsigned)(col + 1) < (unsigned)n;
                 int vo = ok ? ((s * R + sr) * n + col) * 4 : kBufOOB;
-                int vo1 = ok1 ? vo + 4 : kBufOOB;
+                int vo1 = ok1 ? ((s * R + sr) * n + col + 1) * 4 : kBufOOB;   // col may be -1
 #pragma unroll
                 for (int q = 0; q < SLOTS; ++q) {
                     load_pair(q, vo, vo1);

@@ -223,13 +223,20 @@ def test_opts_validation(ops):
         assert e.value.code == L.EIT_ERR_INVALID_ARG
 
 
+def _bench_plan(ops, c):
+    """The plan the benchmark times: tiles from the autotuner's cache for this size class."""
+    from paper_2202_08627_amd import autotune
+    geo = ops.Geometry.from_case(c)
+    return ops.Plan(geo, *autotune.tiling_for(geo))
+
+
 def test_large_slice_sampled_projection(ops):
     """Full-size 512^2 / 720-angle workload: the projector in the benchmark's launch shape,
     checked against the oracle on 24 sampled angles (the oracle's rows are independent)."""
     cfg = configs.SLICE_512
     say("large projection")
     c = synth.make_case(cfg)
-    plan = ops.Plan.from_case(c)
+    plan = _bench_plan(ops, c)
     P = host(plan.project(dev(c.x_true)))
     sel = np.linspace(0, cfg.n_theta - 1, 24).astype(int)
     sel = np.unique(np.concatenate([sel, [0, 180, 360, 540]]))
@@ -242,7 +249,7 @@ def test_large_slice_sampled_projection(ops):
 def test_large_slice_sampled_backprojection(ops):
     cfg = configs.SLICE_512
     c = synth.make_case(cfg)
-    plan = ops.Plan.from_case(c)
+    plan = _bench_plan(ops, c)
     rng = np.random.default_rng(4)
     sel = np.unique(np.linspace(0, cfg.n_theta - 1, 20).astype(int))
     y = np.zeros((2, cfg.n_theta, cfg.n_det))
@@ -251,3 +258,74 @@ def test_large_slice_sampled_backprojection(ops):
     for q in range(2):
         ref = oradon.backproject(y[q, sel], c.theta[sel], cfg.n)
         assert rel_l2(B[q], ref) < 1e-5
+
+
+def test_large_slice_reconstruction_in_bench_configuration(ops):
+    """The benchmark's run (512^2 / 720 / M = 8, autotuned tiles, captured graphs), 20
+    iterations: the cost history never rises, and at the returned x_20 (non-zero up to the
+    map's border, unlike the phantom) the reported cost, the device cost and the device
+    gradient are the oracle's (1e-6, 1e-6, 1e-4 relative)."""
+    cfg = configs.SLICE_512
+    say("large reconstruction")
+    c = synth.make_case(cfg)
+    plan = _bench_plan(ops, c)
+    iters = 20
+    x, rep, hist = plan.reconstruct(dev(c.s_exp), iters=iters, lam=cfg.lam, mu_scale=cfg.mu_scale,
+                                    delta_scale=cfg.delta_scale, m=10, cost_hist=True)
+    assert rep["rc"] == 0 and rep["iters"] == iters
+    h = host(hist)
+    assert np.all(np.diff(h) <= 0)
+    X = host(x)
+    geo = geometry(c, omodel)
+    S, gm, gd = omodel.cost_and_grad(X[0], X[1], c.s_exp, geo, cfg.lam_mu, cfg.lam_delta)
+    cost, grad = plan.cost_and_grad(x, dev(c.s_exp), cfg.lam_mu, cfg.lam_delta)
+    G = host(grad)
+    e = (abs(rep["cost"] - S) / S, abs(float(cost.cpu()) - S) / S, rel_l2(G[0], gm), rel_l2(G[1], gd))
+    say("reported cost, cost, grad mu, grad delta rel:", e)
+    assert e[0] < 1e-6 and e[1] < 1e-6
+    assert e[2] < 1e-4 and e[3] < 1e-4
+
+
+def _variant_case():
+    cfg = tiny_cfg(n=130, n_theta=181, n_det=131, n_mask=8)
+    return cfg, synth.make_case(cfg)
+
+
+def test_every_projector_variant(ops):
+    """Each compiled projector tile variant (both LDS layouts) on a multi-tile ragged geometry,
+    for a dense random map and for a map that is non-zero only on its border rows and columns
+    (the window entries that straddle the map's edge: a duplicated entry at column -1 must
+    still carry column 0)."""
+    from paper_2202_08627_amd import _lib as L
+    cfg, c = _variant_case()
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, cfg.n, cfg.n)).astype(np.float32).astype(np.float64)
+    border = np.zeros_like(x)
+    for e in (0, -1):
+        border[:, e, :] = x[:, e, :]
+        border[:, :, e] = x[:, :, e]
+    refs = [(xx, np.stack([oradon.project(xx[q], c.theta, cfg.n_det) for q in range(2)]))
+            for xx in (x, border)]
+    tried = 0
+    for v in range(len(ops.variants(0))):
+        try:
+            plan = ops.Plan(ops.Geometry.from_case(c), proj_variant=v, adj_variant=0)
+        except L.EitError as e:
+            assert e.code == L.EIT_ERR_SHAPE      # window wider than this variant's pitch
+            continue
+        say("projector variant", v)
+        for xx, ref in refs:
+            assert rel_l2(host(plan.project(dev(xx))), ref) < 1e-5, v
+        tried += 1
+    assert tried >= len(ops.variants(0)) // 2
+
+
+def test_every_adjoint_variant(ops):
+    cfg, c = _variant_case()
+    rng = np.random.default_rng(8)
+    y = rng.standard_normal((2, cfg.n_theta, cfg.n_det)).astype(np.float32).astype(np.float64)
+    ref = np.stack([oradon.backproject(y[q], c.theta, cfg.n) for q in range(2)])
+    for v in range(len(ops.variants(1))):
+        say("adjoint variant", v)
+        plan = ops.Plan(ops.Geometry.from_case(c), adj_variant=v)
+        assert rel_l2(host(plan.backproject(dev(y))), ref) < 1e-5, v
