@@ -52,8 +52,8 @@ WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.np
 # each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
 # this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.
 TRAFFIC = {
-    "project": {"src": "6a53299a8c5f1781", "variant": 11, "bytes": 25.05e6},
-    "backproject": {"src": "6a53299a8c5f1781", "variant": 0, "bytes": 29.60e6},
+    "project": {"src": "bfa9936cf0878580", "variant": 11, "bytes": 25.07e6},
+    "backproject": {"src": "bfa9936cf0878580", "variant": 0, "bytes": 29.60e6},
 }
 
 
