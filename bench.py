@@ -52,8 +52,8 @@ WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.np
 # each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
 # this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.
 TRAFFIC = {
-    "project": {"src": "bfa9936cf0878580", "variant": 11, "bytes": 25.07e6},
-    "backproject": {"src": "bfa9936cf0878580", "variant": 0, "bytes": 29.60e6},
+    "project": {"src": "e072be72464dbeb8", "variant": 11, "bytes": 25.05e6},
+    "backproject": {"src": "e072be72464dbeb8", "variant": 6, "bytes": 20.27e6},
 }
 
 
@@ -356,7 +356,8 @@ def main():
         "other_kernel": {k: {"launch_us": round(v[1] * 1e3, 2),
                              "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3)} for k, v in kern.items() if k != dom},
         "phase_ms_per_iter": {k: round(v / max(prep["iters"], 1), 5) for k, v in prep["phase_ms"].items()},
-        "tiling": {"proj_variant": info["proj_variant"], "adj_variant": info["adj_variant"]},
+        "tiling": {"proj_variant": info["proj_variant"], "adj_variant": info["adj_variant"],
+                   "adj_splits": info["adj_splits"]},
     }
 
     ttt = None

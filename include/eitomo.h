@@ -93,10 +93,16 @@ typedef struct {
 
 /* Optional tile-shape selection (autotuner output); NULL or -1 fields = defaults.
  * proj_variant / adj_variant index the library's compiled projector / adjoint tile
- * variants (see eit_variant_info). */
+ * variants (see eit_variant_info). adj_splits divides the angles of every adjoint voxel
+ * tile among that many blocks (1 .. 64, clamped to the number of angle chunks; <= 0 =
+ * automatic: doubled, up to 8, while the launch has under 1024 blocks and each part keeps
+ * two chunks). With more than one part each block stores FP64 partial sums in the
+ * workspace and a following pass adds them in part order, so results do not depend on
+ * block scheduling. */
 typedef struct {
     int32_t proj_variant;
     int32_t adj_variant;
+    int32_t adj_splits;
 } eit_tiling;
 
 /* Optimiser options for eit_reconstruct (L-BFGS on the scaled unknowns
@@ -222,6 +228,7 @@ typedef struct {
     int32_t adj_tx, adj_ty, adj_ac;
     int32_t n_groups, n_dblk, n_strips, win_w, win_pitch;
     int32_t kwin, kwin_pitch_limit, n_tx, n_ty;
+    int32_t adj_splits;
     int64_t proj_lds_bytes;
 } eit_plan_info;
 int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,

@@ -43,7 +43,8 @@ class Setup(C.Structure):
 
 
 class Tiling(C.Structure):
-    _fields_ = [("proj_variant", C.c_int32), ("adj_variant", C.c_int32)]
+    _fields_ = [("proj_variant", C.c_int32), ("adj_variant", C.c_int32),
+                ("adj_splits", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -65,7 +66,7 @@ class PlanInfo(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "proj_variant", "adj_variant", "proj_a", "proj_w", "proj_r", "adj_tx", "adj_ty", "adj_ac",
         "n_groups", "n_dblk", "n_strips", "win_w", "win_pitch", "kwin", "kwin_pitch_limit",
-        "n_tx", "n_ty")] + [("proj_lds_bytes", C.c_int64)]
+        "n_tx", "n_ty", "adj_splits")] + [("proj_lds_bytes", C.c_int64)]
 
 
 class UNetLayer(C.Structure):

@@ -3,7 +3,11 @@
 For a slice geometry (grid size, angles, detector pixels) every compiled variant that fits
 the geometry is timed through the C ABI (eit_project / eit_backproject, HIP events around
 repeated launches on the current stream) and the fastest pair is stored in a JSON cache keyed
-by the size class. `tiling_for(geo)` returns the cached choice (or -1/-1 = library defaults).
+by the size class. The adjoint is timed for every variant and angle split (blocks per voxel
+tile); the fastest few are then timed inside the optimiser step, where a split adjoint's
+partial sums are added by the update pass instead of a separate one, and the choice is the
+fastest per evaluation there. `tiling_for(geo)` returns the cached (projector variant,
+adjoint variant, adjoint split), or (-1, -1, 0) = library defaults.
 
     python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json]
 """
@@ -19,6 +23,9 @@ from . import _lib as L
 from . import ops, synth
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
+SPLITS = (1, 2, 4, 8)
+SOLVER_CANDIDATES = 4
+SOLVER_ITERS = 20
 
 
 def size_key(geo) -> str:
@@ -35,8 +42,8 @@ def load_cache(path: str = DEFAULT_CACHE) -> dict:
 def tiling_for(geo, path: str = DEFAULT_CACHE):
     ent = load_cache(path).get(size_key(geo))
     if not ent:
-        return -1, -1
-    return int(ent["proj_variant"]), int(ent["adj_variant"])
+        return -1, -1, 0
+    return int(ent["proj_variant"]), int(ent["adj_variant"]), int(ent.get("adj_splits", 1))
 
 
 def _time(fn, reps: int):
@@ -74,22 +81,54 @@ def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
             print(f"  project variant {v} {shape}: {ms * 1e3:.1f} us", flush=True)
         plan.close()
     for v, shape in enumerate(ops.variants(1)):
-        try:
-            plan = ops.Plan(geo, adj_variant=v)
-        except L.EitError:
-            continue
-        out = torch.empty(plan.x_shape, device="cuda")
-        ws = plan.workspace(L.EIT_OP_BACKPROJECT)
-        ms = _time(lambda: plan.backproject(y, out=out, ws=ws), reps)
-        res["adj"][v] = ms
-        if verbose:
-            print(f"  backproject variant {v} {shape}: {ms * 1e3:.1f} us", flush=True)
-        plan.close()
+        nchunks = -(-geo.n_theta // shape[2])
+        for g in SPLITS:
+            if g > 1 and g > nchunks // 2:
+                continue
+            try:
+                plan = ops.Plan(geo, adj_variant=v, adj_splits=g)
+            except L.EitError:
+                break
+            out = torch.empty(plan.x_shape, device="cuda")
+            ws = plan.workspace(L.EIT_OP_BACKPROJECT)
+            ms = _time(lambda: plan.backproject(y, out=out, ws=ws), reps)
+            res["adj"][(v, g)] = ms
+            if verbose:
+                print(f"  backproject variant {v} {shape} split {g}: {ms * 1e3:.1f} us", flush=True)
+            plan.close()
     pv = min(res["proj"], key=res["proj"].get)
-    av = min(res["adj"], key=res["adj"].get)
-    return {"proj_variant": pv, "adj_variant": av,
+    # optimiser-step timing of the best adjoint candidates (synthetic data: the flat-field
+    # intensities with 1 % noise; the per-evaluation cost does not depend on the values)
+    mk = geo.mask_pos[:, None] - geo.flat_ctr[None, :]
+    flat = geo.flat_amp[None, :] * np.exp(-mk ** 2 / (2 * geo.flat_sigma[None, :] ** 2))
+    s = np.broadcast_to(flat, (geo.n_theta,) + flat.shape) * (1 + 0.01 * rng.standard_normal(
+        (geo.n_theta,) + flat.shape))
+    s_exp = torch.as_tensor(s.astype(np.float32), device="cuda")
+    step = {}
+    for key in sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]:
+        plan = ops.Plan(geo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1])
+        ws = plan.workspace(L.EIT_OP_RECONSTRUCT, 10)
+        plan.reconstruct(s_exp, iters=2, ws=ws)
+        best = float("inf")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, rep, _ = plan.reconstruct(s_exp, iters=SOLVER_ITERS, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / max(rep["evals"], 1))
+        step[key] = best
+        if verbose:
+            print(f"  optimiser step with adjoint {key[0]} split {key[1]}: {best * 1e3:.1f} us"
+                  " per evaluation", flush=True)
+        plan.close()
+    av, ag = min(step, key=step.get)
+    return {"proj_variant": pv, "adj_variant": av, "adj_splits": ag,
             "proj_us": {str(k): round(v * 1e3, 2) for k, v in res["proj"].items()},
-            "adj_us": {str(k): round(v * 1e3, 2) for k, v in res["adj"].items()}}
+            "adj_us": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in res["adj"].items()},
+            "step_us_per_eval": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in step.items()}}
 
 
 def tune_and_store(geo, path: str = DEFAULT_CACHE, reps: int = 20, verbose: bool = True) -> dict:

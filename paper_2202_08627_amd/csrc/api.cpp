@@ -60,6 +60,16 @@ int default_adj_variant(int n) { (void)n; return 0; }
 int grid_for(int n_items, int cap) { return std::max(1, std::min(n_items, cap)); }
 constexpr int kGridCap = 256 * 16;   // persistent-grid cap: CUs x resident blocks
 
+// Adjoint angle split: automatic choice doubles the split while the launch has fewer than
+// kSplitTarget blocks (4 per CU) and every part keeps at least 2 angle chunks.
+constexpr int kSplitTarget = 1024;
+constexpr int kMaxSplits = 64;
+int auto_splits(int tiles, int nchunks) {
+    int g = 1;
+    while (tiles * g < kSplitTarget && 2 * g <= std::min(8, nchunks / 2)) g *= 2;
+    return g;
+}
+
 }  // namespace
 
 // ============================================================================ plan
@@ -72,6 +82,7 @@ struct eit_plan {
     int n_groups, n_dblk, n_strips, win_w, win_shift;
     size_t proj_lds;
     int n_tx, n_ty, kwin;
+    int adj_splits;        // adjoint blocks per voxel tile (angle ranges)
     int n_trx;             // transpose tiles per side
     int64_t nv;            // 2 n^2
     int n_vblocks;
@@ -188,7 +199,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         const int* pref = n <= 128 ? kProjPrefSmall : kProjPrefLarge;
         const int np = n <= 128 ? 3 : 4;
         for (int q = 0; q < np; ++q) {
-            eit_tiling t{pref[q], av};
+            eit_tiling t{pref[q], av, tiling ? tiling->adj_splits : 0};
             eit_plan probe{};
             HostTables hh;
             const std::string keep = g_err;
@@ -284,6 +295,13 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     }
     p->n_tx = (n + p->at.TX - 1) / p->at.TX;
     p->n_ty = (n + p->at.TY - 1) / p->at.TY;
+    {
+        const int nchunks = (nt + p->at.AC - 1) / p->at.AC;
+        const int want = tiling ? tiling->adj_splits : 0;
+        if (want > kMaxSplits)
+            return fail(EIT_ERR_INVALID_ARG, "adj_splits=%d above %d", want, kMaxSplits);
+        p->adj_splits = want >= 1 ? std::min(want, nchunks) : auto_splits(p->n_tx * p->n_ty, nchunks);
+    }
 
     // ---- detector tables
     std::vector<float4>& flat = h.flat;
@@ -309,7 +327,8 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         for (int b = 0; b < p->n_dblk; ++b) it_pr.push_back(make_int4(0, g, b, 0));
     for (int a = 0; a < nt; ++a) it_ic.push_back(make_int4(0, a, 0, 0));
     for (int ty = 0; ty < p->n_ty; ++ty)
-        for (int tx = 0; tx < p->n_tx; ++tx) it_bp.push_back(make_int4(0, tx, ty, 0));
+        for (int tx = 0; tx < p->n_tx; ++tx)
+            for (int g = 0; g < p->adj_splits; ++g) it_bp.push_back(make_int4(0, tx, ty, g));
     for (int b = 0; b < p->n_vblocks; ++b) it_vec.push_back(make_int4(0, b, 0, 0));
     p->n_it_tr = (int)it_tr.size(); p->n_it_pr = (int)it_pr.size(); p->n_it_ic = nt;
     p->n_it_bp = (int)it_bp.size(); p->n_it_vec = (int)it_vec.size();
@@ -365,6 +384,7 @@ extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
     info->proj_lds_bytes = (int64_t)tmp.proj_lds;
     info->kwin = tmp.kwin; info->n_tx = tmp.n_tx; info->n_ty = tmp.n_ty;
     info->kwin_pitch_limit = adj_pitch_limit(tmp.adj_v);
+    info->adj_splits = tmp.adj_splits;
     if (proj_angles)
         for (size_t a = 0; a < h.pang.size(); ++a) {
             const ProjAngle& q = h.pang[a];
@@ -389,7 +409,7 @@ extern "C" void eit_plan_destroy(eit_plan* p) { free_plan(p); }
 namespace {
 
 struct EvalLayout {
-    size_t desc, xT, P, part_ic, part_reg, cost, end;
+    size_t desc, xT, P, part_ic, part_reg, cost, bp_part, end;
 };
 
 EvalLayout eval_layout(const eit_plan* p, bool need_P, size_t base = 0) {
@@ -402,6 +422,7 @@ EvalLayout eval_layout(const eit_plan* p, bool need_P, size_t base = 0) {
     e.part_ic = L.take(sizeof(double) * (size_t)p->n_theta);
     e.part_reg = L.take(sizeof(double) * 2 * (size_t)p->n_trx * p->n_trx);
     e.cost = L.take(sizeof(double));
+    e.bp_part = p->adj_splits > 1 ? L.take(sizeof(double) * p->adj_splits * (size_t)p->nv) : 0;
     e.end = L.off;
     return e;
 }
@@ -436,6 +457,7 @@ SliceDesc base_desc(const eit_plan* p) {
     d.n_groups = p->n_groups; d.n_dblk = p->n_dblk; d.n_strips = p->n_strips;
     d.win_w = p->win_w; d.win_shift = p->win_shift;
     d.n_tx = p->n_tx; d.n_ty = p->n_ty; d.kwin = p->kwin;
+    d.adj_splits = p->adj_splits;
     d.pang = p->pang; d.groups = p->groups; d.win_lo = p->win_lo; d.aang = p->aang;
     d.flat = p->flat; d.mask = p->mask;
     d.n_reg_blocks = p->n_trx * p->n_trx;
@@ -443,6 +465,21 @@ SliceDesc base_desc(const eit_plan* p) {
 }
 
 char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+// The adjoint's partial-sum planes of a descriptor whose evaluation buffers start at `base`.
+void set_split_buffers(SliceDesc& d, void* base, const EvalLayout& L) {
+    d.bp_part = d.adj_splits > 1 ? (double*)at(base, L.bp_part) : nullptr;
+}
+
+// Adjoint launch, then (split plans) the pass that adds the parts into d.g.
+int enqueue_backproject(const eit_plan* p, const SliceDesc* dd, int add_reg, hipStream_t st) {
+    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
+                               add_reg, st));
+    if (p->adj_splits > 1)
+        HIP_TRY(launch_bp_combine(dd, p->it_vec, p->n_it_vec, grid_for(p->n_it_vec, kGridCap),
+                                  add_reg, st));
+    return EIT_OK;
+}
 
 int check_ws(const void* ws, size_t have, size_t need) {
     if (!ws) return fail(EIT_ERR_INVALID_ARG, "workspace is NULL");
@@ -475,9 +512,7 @@ int enqueue_eval(const eit_plan* p, const SliceDesc* dd, bool seeds, bool grad, 
     HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
                            p->proj_lds, st));
     HIP_TRY(launch_ic(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap), seeds ? 1 : 0, st));
-    if (grad)
-        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp,
-                                   grid_for(p->n_it_bp, kGridCap), 1, st));
+    if (grad) return enqueue_backproject(p, dd, 1, st);
     return EIT_OK;
 }
 
@@ -513,11 +548,10 @@ extern "C" int eit_backproject(const eit_plan* p, const float* sino, float* x_ou
     SliceDesc d = base_desc(p);
     d.P = const_cast<float*>(sino);   // read only by the adjoint
     d.g = x_out;
+    set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     HIP_TRY(launch_store_desc(d, dd, st));
-    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
-                               0, st));
-    return EIT_OK;
+    return enqueue_backproject(p, dd, 0, st);
 }
 
 extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float* s_exp,
@@ -541,13 +575,12 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
     d.cost = cost_dev;
     d.lam_mu = lam_mu; d.lam_de = lam_delta;
     d.reg_mu = 2.0 * lam_mu; d.reg_de = 2.0 * lam_delta;
+    set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     HIP_TRY(launch_store_desc(d, dd, st));
     if (int rc = enqueue_eval(p, dd, grad != nullptr, false, st)) return rc;
     HIP_TRY(launch_cost_reduce(dd, 1, st));
-    if (grad)
-        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp,
-                                   grid_for(p->n_it_bp, kGridCap), 1, st));
+    if (grad) return enqueue_backproject(p, dd, 1, st);
     return EIT_OK;
 }
 
@@ -562,14 +595,13 @@ extern "C" int eit_single_shot(const eit_plan* p, const float* s_exp, float* x_o
     d.P = (float*)at(ws, L.P);
     d.s_exp = s_exp;
     d.g = x_out;
+    set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     HIP_TRY(launch_store_desc(d, dd, st));
     const int gi = grid_for(p->n_it_ic, kGridCap);
     HIP_TRY(launch_ss_retrieve(dd, p->it_ic, p->n_it_ic, gi, st));
     HIP_TRY(launch_ss_filter(dd, p->it_ic, p->n_it_ic, gi, st));
-    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
-                               0, st));
-    return EIT_OK;
+    return enqueue_backproject(p, dd, 0, st);
 }
 
 // ============================================================================ reconstruct
@@ -759,6 +791,17 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
 }
 
 
+// Adjoint split of one solver slice: the parts land in the partial planes and the update
+// forms the gradient from them (gt is then unused).
+void set_solver_split(SliceDesc& d, LbDesc& l, void* base, const SolveLayout& S, int splits) {
+    d.adj_splits = splits;
+    set_split_buffers(d, base, S.ev);
+    l.gpart = d.bp_part;
+    l.gsplits = splits;
+    l.reg_mu = d.reg_mu;
+    l.reg_de = d.reg_de;
+}
+
 // Descriptors of one slice's optimiser run whose buffers start at `base` with layout S.
 void solver_descs(const eit_plan* p, const eit_opts* o, void* base, const SolveLayout& S,
                   const float* s_exp, float* x, double* cost_hist, SliceDesc& d, LbDesc& l) {
@@ -787,6 +830,7 @@ void solver_descs(const eit_plan* p, const eit_opts* o, void* base, const SolveL
     l.st = state;
     l.x_user = x;
     l.cost_hist = cost_hist;
+    set_solver_split(d, l, base, S, p->adj_splits);
 }
 
 void fill_report(const SolverState& hs, int launches, eit_report* rep) {
@@ -896,6 +940,7 @@ struct BatchLayout {
     size_t descs = 0, lbdescs = 0, items = 0, end = 0;
     std::vector<size_t> slice;        // per-slice solve layout base
     std::vector<int> order;           // slices by decreasing work
+    std::vector<int> splits;          // adjoint split per slice
     std::vector<Item> items_h;        // all work items, grouped by launch
     // item ranges (offset, count) in items_h
     std::pair<int, int> r_dir, r_ic, r_vec;
@@ -942,13 +987,20 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
         }
         if ((int)H.size() > off) B.r_proj.emplace_back(v, off, (int)H.size() - off, lds);
     }
+    // the angle split only serves launches with few tiles: a batch that fills the chip
+    // without it runs every slice unsplit
+    long long tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += (long long)plans[i]->n_tx * plans[i]->n_ty;
+    B.splits.resize(n);
+    for (int i = 0; i < n; ++i) B.splits[i] = tiles >= kSplitTarget ? 1 : plans[i]->adj_splits;
     for (int v = 0; v < adj_variant_count(); ++v) {
         const int off = (int)H.size();
         for (int i : B.order) {
             const eit_plan* p = plans[i];
             if (p->adj_v != v) continue;
             for (int ty = 0; ty < p->n_ty; ++ty)
-                for (int tx = 0; tx < p->n_tx; ++tx) H.push_back(make_int4(i, tx, ty, 0));
+                for (int tx = 0; tx < p->n_tx; ++tx)
+                    for (int g = 0; g < B.splits[i]; ++g) H.push_back(make_int4(i, tx, ty, g));
         }
         if ((int)H.size() > off) B.r_adj.emplace_back(v, off, (int)H.size() - off, (size_t)0);
     }
@@ -995,6 +1047,7 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
         void* base = at(ws, B.slice[i]);
         const SolveLayout S = solve_layout(plans[i], o->lbfgs_m);
         solver_descs(plans[i], o, base, S, s_exp[i], x[i], nullptr, dh[i], lh[i]);
+        set_solver_split(dh[i], lh[i], base, S, B.splits[i]);
         states[i] = lh[i].st;
     }
     SliceDesc* dd = (SliceDesc*)at(ws, B.descs);

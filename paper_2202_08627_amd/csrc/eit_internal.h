@@ -70,6 +70,9 @@ struct SliceDesc {
     double* cost;                  // scalar cost
     const int32_t* skip;           // optional device flag: nonzero => kernels no-op
     const int32_t* skip_adj;       // optional: nonzero => adjoint no-ops
+    // adjoint angle split: G = adj_splits blocks per voxel tile (1 = no split)
+    int32_t adj_splits, pad1;
+    double* bp_part;               // [G][2][n][n] FP64 partial sums of the adjoint (G > 1)
 };
 
 // Work items: (slice, a, b, c) -- meaning depends on the kernel.
@@ -111,6 +114,11 @@ struct LbDesc {
     SolverState* st;
     float* x_user;               // raw-unit iterate (in/out)
     double* cost_hist;           // optional [max_iter + 1]
+    // split adjoint (gsplits > 1): the gradient at zt is sum_g gpart[g] + reg * zt, formed
+    // here instead of in gt
+    const double* gpart;         // [gsplits][nv]
+    int32_t gsplits, pad;
+    double reg_mu, reg_de;
 };
 
 hipError_t launch_lb_init(const LbDesc* L, int n_slices, int m, int max_iter, int max_ls, double c1,
@@ -136,6 +144,8 @@ hipError_t launch_ic(const SliceDesc* d_descs, const Item* items, int n_items, i
 hipError_t launch_cost_reduce(const SliceDesc* d_descs, int n_slices, hipStream_t s);
 hipError_t launch_backproject(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
                               int grid, int add_reg, hipStream_t s);
+hipError_t launch_bp_combine(const SliceDesc* d_descs, const Item* vec_items, int n_items, int grid,
+                             int add_reg, hipStream_t s);
 
 // single-shot reconstruction (single_shot.hip)
 hipError_t launch_ss_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,

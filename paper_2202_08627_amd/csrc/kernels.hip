@@ -298,8 +298,14 @@ __global__ __launch_bounds__(256) void k_cost_reduce(const SliceDesc* __restrict
 // (1/w) max(0, 1 - d/w) is one FMA whose result the hardware clamps to [0, 1]:
 //   bin floor(u):     max(0, 1 - f/w),   bin floor(u)+1:   max(0, (1 - 1/w) + f/w)
 // (f = frac(u); neither exceeds 1 since f in [0, 1) and 1/w >= 1).
-// No atomics: each voxel's sum is accumulated in a fixed angle order by one thread, chunk
-// sums in FP64. The next chunk's bins are loaded into registers during the current chunk.
+// Each voxel's sum is accumulated in a fixed angle order by one thread, chunk sums in FP64.
+// The next chunk's bins are loaded into registers during the current chunk.
+// Angle split (item .w = part g of d.adj_splits = G): with G > 1 the chunks of a tile are
+// divided into G contiguous ranges, one block each, so that small maps still launch enough
+// blocks. Each block then stores its FP64 partial sums as plane g of d.bp_part, and a later
+// pass (k_bp_combine, or the optimiser's update) adds the G planes in the order g = 0 .. G-1
+// before the regulariser term and the FP32 rounding -- the same arithmetic as the unsplit
+// epilogue, with no inter-block synchronisation inside the launch.
 constexpr int isqrt_ceil(int v) {
     int s = 0;
     while (s * s < v) ++s;
@@ -356,6 +362,8 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
         const __amdgpu_buffer_rsrc_t bGd = make_rsrc(d.P + (size_t)nth * nd, sz4);
         const AdjAngle* aang = d.aang;
         const int nchunks = (nth + AC - 1) / AC;
+        const int G = d.adj_splits, gs = w.w;
+        const int ch0 = gs * nchunks / G, ch1 = (gs + 1) * nchunks / G;
 
         // per-angle constants and window origin of chunk ch into buffer slot ch & 1
         auto angle_setup = [&](int ch) {
@@ -390,14 +398,14 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
             }
         };
         __syncthreads();                  // LDS of the previous work item fully consumed
-        angle_setup(0);
+        angle_setup(ch0);
         __syncthreads();
-        load_chunk(0);
+        load_chunk(ch0);
         double acc_m[VPT], acc_d[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q) { acc_m[q] = 0.0; acc_d[q] = 0.0; }
         const float fil = (float)il, fjl = (float)jl;
-        for (int ch = 0; ch < nchunks; ++ch) {
+        for (int ch = ch0; ch < ch1; ++ch) {
             __syncthreads();                           // previous chunk fully consumed
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
@@ -408,9 +416,9 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
                 gw[(sa + q * AS) * PK + sb] = make_float4(gm, gd, nm, nd1);
             }
-            if (ch + 1 < nchunks) angle_setup(ch + 1);
+            if (ch + 1 < ch1) angle_setup(ch + 1);
             __syncthreads();
-            if (ch + 1 < nchunks) load_chunk(ch + 1);  // in flight during this chunk
+            if (ch + 1 < ch1) load_chunk(ch + 1);      // in flight during this chunk
             const int cb = ch & 1;
             float am[VPT], ad[VPT];
 #pragma unroll
@@ -439,6 +447,19 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
             }
         }
         const int i = i0 + il;
+        if (G > 1) {
+            const size_t nn = (size_t)n * n;
+            double* part = d.bp_part + (size_t)gs * 2 * nn;
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {
+                const int j = j0 + jl + q * JS;
+                if (i < n && j < n) {
+                    part[(size_t)j * n + i] = acc_m[q];
+                    part[nn + (size_t)j * n + i] = acc_d[q];
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
             const int j = j0 + jl + q * JS;
@@ -570,6 +591,35 @@ hipError_t launch_backproject(int variant, const SliceDesc* D, const Item* items
     EIT_ADJ_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+// Split adjoint epilogue. Item (slice, chunk): kVecChunk consecutive elements e of the
+// [2][n][n] output; g[e] = FP32(sum over parts of bp_part[part][e] (+ reg * x[e])).
+__global__ __launch_bounds__(kVecThreads) void k_bp_combine(const SliceDesc* __restrict__ D,
+                                                           const Item* __restrict__ items,
+                                                           int n_items, int add_reg) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped_adj(d) || d.adj_splits <= 1) continue;
+        const int G = d.adj_splits;
+        const size_t nn = (size_t)d.n * d.n, nv = 2 * nn;
+        const size_t e0 = (size_t)w.y * kVecChunk;
+        const size_t e1 = min(e0 + kVecChunk, nv);
+        for (size_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            double v = 0.0;
+            for (int g = 0; g < G; ++g) v += d.bp_part[g * nv + e];
+            if (add_reg) v = fma(e < nn ? d.reg_mu : d.reg_de, (double)d.x[e], v);
+            d.g[e] = (float)v;
+        }
+    }
+}
+
+hipError_t launch_bp_combine(const SliceDesc* D, const Item* items, int n_items, int grid,
+                             int add_reg, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_bp_combine<<<grid, kVecThreads, 0, s>>>(D, items, n_items, add_reg);
+    return hipGetLastError();
 }
 
 }  // namespace eit

@@ -227,6 +227,35 @@ __device__ __forceinline__ void st8(float* __restrict__ p, int64_t e, int64_t nv
     }
 }
 
+// Gradient at the trial point from the split adjoint's partial planes: the parts are added in
+// plane order, then the regulariser reg * zt, then rounded -- the adjoint's own epilogue.
+__device__ __forceinline__ void split_gradient(const LbDesc& l, int64_t e, int64_t nv, bool vec,
+                                               const float* zn, float* gv) {
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int g = 0; g < l.gsplits; ++g) {
+        const double* p = l.gpart + (int64_t)g * nv + e;
+        if (vec) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const double2 v = *(const double2*)(p + 2 * h);
+                acc[2 * h] += v.x;
+                acc[2 * h + 1] += v.y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < nv) acc[u] += p[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double reg = e + u < nv / 2 ? l.reg_mu : l.reg_de;
+        gv[u] = (float)fma(reg, (double)zn[u], acc[u]);
+    }
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restrict__ L,
                                                          const Item* __restrict__ items,
                                                          int n_items) {
@@ -250,13 +279,19 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_update(const LbDesc* __restr
 #pragma unroll
         for (int q = 0; q < kDotsFixed; ++q) acc[q] = 0.0;
         if (e < nv) {
-            ld8(l.gt, e, nv, vec, gv);
+            float zn[8];
+            if (l.gsplits > 1) {
+                ld8(l.zt, e, nv, vec, zn);
+                split_gradient(l, e, nv, vec, zn, gv);
+            } else {
+                ld8(l.gt, e, nv, vec, gv);
+                if (!init) ld8(l.zt, e, nv, vec, zn);
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc[0] = fma((double)gv[u], (double)gv[u], acc[0]);
             if (!init) {
-                float zo[8], zn[8], go[8], sv[8];
+                float zo[8], go[8], sv[8];
                 ld8(l.z, e, nv, vec, zo);
-                ld8(l.zt, e, nv, vec, zn);
                 ld8(l.g, e, nv, vec, go);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {

@@ -68,10 +68,11 @@ class Geometry:
         return dims, setup, arrs
 
 
-def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, tables: bool = False):
+def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, adj_splits: int = 0,
+            tables: bool = False):
     """Host-only plan diagnostics (no GPU needed): sizes and, optionally, the FP64 tables."""
     dims, setup, keep = geo.c_args()
-    til = L.Tiling(proj_variant, adj_variant)
+    til = L.Tiling(proj_variant, adj_variant, adj_splits)
     info = L.PlanInfo()
     L.check(L.lib().eit_plan_inspect(C.byref(dims), C.byref(setup), C.byref(til), C.byref(info),
                                      None, None, None, None))
@@ -113,12 +114,14 @@ def variants(kind: int):
 class Plan:
     """Owns one eit_plan (device angle/detector tables) for a slice geometry."""
 
-    def __init__(self, geo: Geometry, proj_variant: int = -1, adj_variant: int = -1):
+    def __init__(self, geo: Geometry, proj_variant: int = -1, adj_variant: int = -1,
+                 adj_splits: int = 0):
+        """adj_splits: blocks per adjoint voxel tile (0 = the library's automatic choice)."""
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
         self.geo = geo
         dims, setup, keep = geo.c_args()
-        til = L.Tiling(proj_variant, adj_variant)
+        til = L.Tiling(proj_variant, adj_variant, adj_splits)
         h = C.c_void_p()
         torch.cuda.current_device()
         L.check(L.lib().eit_plan_create(C.byref(dims), C.byref(setup), C.byref(til), C.byref(h)))

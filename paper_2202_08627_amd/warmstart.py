@@ -61,7 +61,7 @@ def scales(cfg) -> torch.Tensor:
 
 
 def build_training_set(cfg: configs.SliceConfig, seeds, target_iters: int = 300, chunk: int = 256,
-                       m: int = 10, workers: int = 8, tiling=(-1, -1), log=print):
+                       m: int = 10, workers: int = 8, tiling=(-1, -1, 0), log=print):
     """(inputs, targets) as device tensors [N][2][n][n] in scaled units, and statistics."""
     seeds = list(seeds)
     dev = torch.device("cuda")

@@ -209,3 +209,27 @@ def test_row_flags_match_oracle_rule():
     info = ops.inspect(g, tables=True)
     src = info["proj_angles"][:, 5]
     assert np.array_equal(src == 0, radon.row_flags(g.theta))
+
+
+def test_adjoint_split_choice():
+    """Adjoint angle split as the plan reports it: automatic (doubled while the launch has
+    under 1024 blocks and each part keeps two angle chunks), explicit (clamped to the chunk
+    count), rejected above 64; and the kernel's part ranges [g C / G, (g+1) C / G) cover the
+    C chunks once each with no empty part."""
+    big = geo_for(configs.SLICE_512)
+    assert ops.inspect(big)["adj_splits"] == 1                     # 16x16 tiles: 1024 blocks
+    info = ops.inspect(big, adj_variant=3)                         # 32x32 tiles: 256 blocks
+    assert (info["n_tx"] * info["n_ty"], info["adj_splits"]) == (256, 4)
+    small = geo_for(configs.SMALL_64)                              # 90 angles: 3 chunks of 32
+    assert ops.inspect(small)["adj_splits"] == 1
+    assert ops.inspect(small, adj_splits=2)["adj_splits"] == 2
+    assert ops.inspect(small, adj_splits=64)["adj_splits"] == 3
+    with pytest.raises(L.EitError) as e:
+        ops.inspect(small, adj_splits=65)
+    assert e.value.code == L.EIT_ERR_INVALID_ARG
+    for C_ in range(1, 40):
+        for G in range(1, C_ + 1):
+            parts = [(g * C_ // G, (g + 1) * C_ // G) for g in range(G)]
+            assert parts[0][0] == 0 and parts[-1][1] == C_
+            assert all(a < b for a, b in parts)
+            assert all(parts[i][1] == parts[i + 1][0] for i in range(G - 1))

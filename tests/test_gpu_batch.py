@@ -38,13 +38,16 @@ def _cases():
     return [synth.make_case(c, seed=i + 3) for i, c in enumerate(cfgs)]
 
 
-VARIANTS = [(-1, -1), (1, 1), (7, 5), (8, 0), (0, 2)]
+# (projector variant, adjoint variant, adjoint angle split); slices 1 and 3 split their
+# adjoint over 2 and 3 blocks per voxel tile
+VARIANTS = [(-1, -1, 0), (1, 1, 2), (7, 5, 1), (8, 0, 3), (0, 2, 1)]
 
 
 def test_batch_equals_single_slice_runs(ops):
     print("batch vs single", flush=True)
     cases = _cases()
-    plans = [ops.Plan.from_case(c, proj_variant=pv, adj_variant=av) for c, (pv, av) in zip(cases, VARIANTS)]
+    plans = [ops.Plan.from_case(c, proj_variant=pv, adj_variant=av, adj_splits=g)
+             for c, (pv, av, g) in zip(cases, VARIANTS)]
     s = [dev(c.s_exp) for c in cases]
     kw = dict(iters=20, lam=1e-2, mu_scale=0.05, delta_scale=1e-3)
     xs, reps = ops.reconstruct_batch(plans, s, **kw)
