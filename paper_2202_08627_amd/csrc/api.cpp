@@ -92,7 +92,7 @@ struct eit_plan {
     int32_t* win_lo = nullptr;
     AdjAngle* aang = nullptr;
     float4* flat = nullptr;
-    float* mask = nullptr;
+    double* mask = nullptr;
     // single-slice item lists (slice 0)
     Item* it_tr = nullptr;
     Item* it_pr = nullptr;
@@ -156,7 +156,7 @@ struct HostTables {
     std::vector<int32_t> groups, win_lo;
     std::vector<AdjAngle> aang;
     std::vector<float4> flat;
-    std::vector<float> maskf;
+    std::vector<double> maskd;
     std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
 };
 
@@ -264,10 +264,10 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     p->win_w = win_w;
     p->win_shift = 0;
     while ((1 << p->win_shift) < p->pt.PW) ++p->win_shift;
-    p->proj_lds = (size_t)R * (size_t)p->pt.PW * (p->pt.DUP ? sizeof(float4) : sizeof(float2));
-    if (win_w > p->pt.PW) {
+    p->proj_lds = (size_t)R * (size_t)p->pt.LP * (p->pt.DUP ? sizeof(float4) : sizeof(float2));
+    if (win_w > p->pt.LP) {
         return fail(EIT_ERR_SHAPE, "projector window %d wider than variant %d's pitch %d", win_w,
-                    pv, p->pt.PW);
+                    pv, p->pt.LP);
     }
 
     // ---- adjoint tables
@@ -311,9 +311,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         flat[k] = make_float4((float)setup->flat_amp[k], (float)setup->flat_ctr[k],
                               (float)(1.0 / (2.0 * sg * sg)), (float)(1.0 / (sg * sg)));
     }
-    std::vector<float>& maskf = h.maskf;
-    maskf.assign(nm, 0.f);
-    for (int j = 0; j < nm; ++j) maskf[j] = (float)mpos[j];
+    h.maskd = mpos;
 
     // ---- single-slice work items
     p->n_trx = (n + kTrTile - 1) / kTrTile;
@@ -356,7 +354,7 @@ extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
     }
     if ((rc = upload(&p->pang, h.pang)) || (rc = upload(&p->groups, h.groups)) ||
         (rc = upload(&p->win_lo, h.win_lo)) || (rc = upload(&p->aang, h.aang)) ||
-        (rc = upload(&p->flat, h.flat)) || (rc = upload(&p->mask, h.maskf)) ||
+        (rc = upload(&p->flat, h.flat)) || (rc = upload(&p->mask, h.maskd)) ||
         (rc = upload(&p->it_tr, h.it_tr)) || (rc = upload(&p->it_pr, h.it_pr)) ||
         (rc = upload(&p->it_ic, h.it_ic)) || (rc = upload(&p->it_bp, h.it_bp)) ||
         (rc = upload(&p->it_vec, h.it_vec))) {
@@ -380,7 +378,7 @@ extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
     info->proj_a = tmp.pt.A; info->proj_w = tmp.pt.W; info->proj_r = tmp.pt.R;
     info->adj_tx = tmp.at.TX; info->adj_ty = tmp.at.TY; info->adj_ac = tmp.at.AC;
     info->n_groups = tmp.n_groups; info->n_dblk = tmp.n_dblk; info->n_strips = tmp.n_strips;
-    info->win_w = tmp.win_w; info->win_pitch = 1 << tmp.win_shift;
+    info->win_w = tmp.win_w; info->win_pitch = tmp.pt.LP;
     info->proj_lds_bytes = (int64_t)tmp.proj_lds;
     info->kwin = tmp.kwin; info->n_tx = tmp.n_tx; info->n_ty = tmp.n_ty;
     info->kwin_pitch_limit = adj_pitch_limit(tmp.adj_v);
@@ -916,7 +914,10 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
     }
     if (kind == 2) {                       // projector LDS layout
         const int n = proj_variant_count();
-        if (v >= 0 && v < n && a) *a = proj_variant(v).DUP;
+        if (v >= 0 && v < n) {
+            if (a) *a = proj_variant(v).DUP;
+            if (b) *b = proj_variant(v).LP;
+        }
         return n;
     }
     if (kind == 1) {

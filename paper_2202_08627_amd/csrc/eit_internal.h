@@ -32,7 +32,8 @@ struct AdjAngle {
 };
 
 // Tile shapes (compile-time variants, chosen per grid-size class).
-struct ProjTile { int A, W, R, PW, DUP; };     // angles per group, detectors per block, rows per strip, pitch
+struct ProjTile { int A, W, R, PW, DUP, LP; };   // angles per group, detectors per block, rows per strip,
+                                                // staged width, 16-byte entries, LDS row pitch
 struct AdjTile  { int TX, TY, AC, VPT; }; // voxel tile, angles per staged chunk, voxels per thread
 
 // ---------------------------------------------------------------- per-slice descriptor
@@ -56,7 +57,7 @@ struct SliceDesc {
     const int32_t* win_lo;         // [n_groups][n_dblk][n_strips]
     const AdjAngle* aang;          // [n_theta]
     const float4* flat;            // [n_det] (A, c, 1/(2 s^2), 1/s^2)
-    const float* mask;             // [n_mask]
+    const double* mask;            // [n_mask] mask positions
     // per-call buffers (device)
     const float* x;                // [2][n][n] point of evaluation
     float* xT;                     // [2][n][n] transposed copy (projector source)
@@ -160,7 +161,7 @@ int adj_variant_count();
 AdjTile adj_variant(int v);
 int adj_pitch_limit(int v);   // compile-time LDS pitch capacity of adjoint variant v
 
-constexpr int kIcThreads = 256;
+constexpr int kIcThreads = 512;
 constexpr int kTrThreads = 256;      // transpose tile 32x32, 256 threads
 constexpr int kTrTile = 32;
 

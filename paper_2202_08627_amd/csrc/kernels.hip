@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // for all rays of the block; the host builds lo and win_w from FP64 extremes with a 1e-3
 // margin, and the host tests replay this exact FP32/FP64 arithmetic for every work item of
 // the benchmark and test geometries.
-template <int A, int W, int R, int PW, int DUP>
+template <int A, int W, int R, int PW, int DUP, int LP>
 __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
     constexpr int NT = A * W;
@@ -87,9 +87,11 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
     constexpr int RS = WIDE ? NT / PW : 1;   // rows staged per slot step
     constexpr int CS = WIDE ? 1 : PW / NT;   // columns per thread and row
     static_assert(R % RS == 0, "strip must tile the block");
+    static_assert(LP <= PW, "LDS rows hold at most the staged width");
     constexpr int SLOTS = R / RS * CS;
     typedef typename std::conditional<DUP != 0, float4, float2>::type Entry;
-    __shared__ Entry win[R * PW];
+    // LDS rows of LP entries (LP <= PW; window columns past LP are never staged or read)
+    __shared__ Entry win[R * LP];
     const int tid = threadIdx.x;
     const int al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
     const int kl = tid % W;
@@ -163,9 +165,10 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
                 if constexpr (WIDE) {
-                    if (c0w < win_w) win[(sr + q * RS) * PW + sc] = buf[q];
+                    if (c0w < win_w && (LP == PW || sc < LP)) win[(sr + q * RS) * LP + sc] = buf[q];
                 } else {
-                    win[(q / CS) * PW + tid + (q % CS) * NT] = buf[q];
+                    const int c = tid + (q % CS) * NT;
+                    if (LP == PW || c < LP) win[(q / CS) * LP + c] = buf[q];
                 }
             }
             __syncthreads();
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             for (int r = 0; r < R; ++r) {
                 const float u = fmaf((float)r, slope_f, uf);
                 const float ph = __builtin_amdgcn_fractf(u);
-                const Entry* q = rowp + r * PW + (int)u;
+                const Entry* q = rowp + r * LP + (int)u;
                 float4 v;
                 if constexpr (DUP != 0) {
                     v = *(const float4*)q;
@@ -241,14 +244,15 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
             const double T = exp(-pm);
             const double dl = (double)kap * 0.5 * (pp - pn);
             const float4 fl = d.flat[k];       // A, c, 1/(2 s^2), 1/s^2
+            const double z = (double)fl.z, fw = (double)fl.w;
             double sf = 0.0, sfp = 0.0;
             for (int j = 0; j < M; ++j) {
-                const double uu = (double)d.mask[j] - dl - (double)fl.y;
-                const double f = (double)fl.x * exp(-uu * uu * (double)fl.z);
+                const double uu = d.mask[j] - dl - (double)fl.y;
+                const double f = (double)fl.x * exp(-uu * uu * z);
                 const double r = fma(T, f, -(double)se[(size_t)j * nd + k]);
                 r2 = fma(r, r, r2);
                 sf = fma(r, f, sf);
-                sfp = fma(r, -uu * (double)fl.w * f, sfp);
+                sfp = fma(r, -uu * fw * f, sfp);
             }
             if (want_seeds) {
                 Pm[k] = (float)(sm * (-2.0 * T * sf));   // G_Pmu, scaled
@@ -481,23 +485,25 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 // ------------------------------------------------------------------------ registry
 // Projector variants (A angles x W detectors threads, R rows per strip, PW staged entries per
 // row, DUP = duplicated 16-byte entries).
-#define EIT_PROJ_VARIANTS(X)   \
-    X(0, 8, 64, 16, 256, 0)    \
-    X(1, 4, 64, 16, 128, 0)    \
-    X(2, 16, 64, 8, 256, 0)    \
-    X(3, 8, 64, 8, 256, 0)     \
-    X(4, 4, 128, 16, 256, 0)   \
-    X(5, 8, 64, 32, 256, 0)    \
-    X(6, 16, 64, 16, 256, 0)   \
-    X(7, 2, 64, 16, 128, 0)    \
-    X(8, 1, 64, 16, 128, 0)    \
-    X(9, 16, 64, 16, 256, 1)   \
-    X(10, 16, 64, 8, 256, 1)   \
-    X(11, 8, 64, 8, 256, 1)    \
-    X(12, 8, 64, 8, 128, 1)    \
-    X(13, 8, 64, 16, 128, 1)   \
-    X(14, 4, 64, 16, 128, 1)   \
-    X(15, 4, 64, 8, 128, 1)
+#define EIT_PROJ_VARIANTS(X)        \
+    X(0, 8, 64, 16, 256, 0, 256)    \
+    X(1, 4, 64, 16, 128, 0, 128)    \
+    X(2, 16, 64, 8, 256, 0, 256)    \
+    X(3, 8, 64, 8, 256, 0, 256)     \
+    X(4, 4, 128, 16, 256, 0, 256)   \
+    X(5, 8, 64, 32, 256, 0, 256)    \
+    X(6, 16, 64, 16, 256, 0, 256)   \
+    X(7, 2, 64, 16, 128, 0, 128)    \
+    X(8, 1, 64, 16, 128, 0, 128)    \
+    X(9, 16, 64, 16, 256, 1, 256)   \
+    X(10, 16, 64, 8, 256, 1, 256)   \
+    X(11, 8, 64, 8, 256, 1, 256)    \
+    X(12, 8, 64, 8, 128, 1, 128)    \
+    X(13, 8, 64, 16, 128, 1, 128)   \
+    X(14, 4, 64, 16, 128, 1, 128)   \
+    X(15, 4, 64, 8, 128, 1, 128)    \
+    X(16, 8, 64, 16, 256, 1, 136)   \
+    X(17, 8, 64, 8, 256, 1, 128)
 
 // Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
@@ -512,17 +518,17 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 
 int proj_variant_count() {
     int c = 0;
-#define X(id, A, W, R, PW, DUP) ++c;
+#define X(id, A, W, R, PW, DUP, LP) ++c;
     EIT_PROJ_VARIANTS(X)
 #undef X
     return c;
 }
 ProjTile proj_variant(int v) {
-#define X(id, A, W, R, PW, DUP) \
-    if (v == id) return ProjTile{A, W, R, PW, DUP};
+#define X(id, A, W, R, PW, DUP, LP) \
+    if (v == id) return ProjTile{A, W, R, PW, DUP, LP};
     EIT_PROJ_VARIANTS(X)
 #undef X
-    return ProjTile{0, 0, 0, 0, 0};
+    return ProjTile{0, 0, 0, 0, 0, 0};
 }
 int adj_pitch_limit(int v) {
 #define X(id, TX, TY, AC, VPT) \
@@ -556,11 +562,11 @@ hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, 
 hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, int n_items,
                           int grid, size_t lds, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, A, W, R, PW, DUP)                                                  \
-    if (variant == id) {                                                         \
-        (void)lds;                                                               \
-        k_project<A, W, R, PW, DUP><<<grid, A * W, 0, s>>>(D, items, n_items);   \
-        return hipGetLastError();                                                \
+#define X(id, A, W, R, PW, DUP, LP)                                                  \
+    if (variant == id) {                                                             \
+        (void)lds;                                                                   \
+        k_project<A, W, R, PW, DUP, LP><<<grid, A * W, 0, s>>>(D, items, n_items);   \
+        return hipGetLastError();                                                    \
     }
     EIT_PROJ_VARIANTS(X)
 #undef X

@@ -123,6 +123,30 @@ def test_cost_and_grad_parity(ops, cfg):
     assert rel_l2(G[1], gd) < 1e-4
 
 
+@pytest.mark.parametrize("layout", ["jittered", "narrow"])
+def test_cost_and_grad_mask_layouts(ops, layout):
+    """The IC stage with mask positions off the equal spacing ('jittered') and with every
+    other detector pixel given a flat-field width of 0.02 mask periods ('narrow': Gaussian
+    factors down to exp(-600) and below, next to ordinary pixels in one wavefront)."""
+    cfg = CASES[4]
+    c = synth.make_case(cfg)
+    if layout == "jittered":
+        rng = np.random.default_rng(11)
+        c = dataclasses.replace(c, mask_pos=c.mask_pos + 0.02 * rng.standard_normal(cfg.n_mask))
+    else:
+        sig = c.flat_sigma.copy()
+        sig[::2] = 0.02
+        c = dataclasses.replace(c, flat_sigma=sig)
+    plan = ops.Plan.from_case(c)
+    geo = geometry(c, omodel)
+    x = (0.9 * c.x_true).astype(np.float32).astype(np.float64)
+    cost, grad = plan.cost_and_grad(dev(x), dev(c.s_exp), cfg.lam_mu, cfg.lam_delta)
+    S, gm, gd = omodel.cost_and_grad(x[0], x[1], c.s_exp, geo, cfg.lam_mu, cfg.lam_delta)
+    assert float(cost) == pytest.approx(S, rel=1e-6)
+    G = host(grad)
+    assert rel_l2(G[0], gm) < 1e-4 and rel_l2(G[1], gd) < 1e-4
+
+
 def test_autograd_function_matches_oracle(ops):
     cfg = configs.SMALL_64
     c = synth.make_case(cfg)
