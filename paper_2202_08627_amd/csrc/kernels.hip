@@ -64,11 +64,13 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // Item (slice, group, detector block, -). Thread (angle slot al, detector kl) follows one
 // ray. The block walks the stepped axis in strips of R rows; for each strip it stages the
 // window [lo, lo + win_w) of the interpolation axis (host-computed lo, conservative in FP64)
-// in LDS, PW entries per row, and a sample applies the two interpolation weights to the
-// neighbouring columns with four FMAs. Two LDS layouts (a tile-shape option):
-//   DUP = 0: interleaved (mu, delta) pairs; a sample is two 8-byte LDS reads;
-//   DUP = 1: 16-byte entries (mu, delta of column c, mu, delta of column c + 1), each column
-//            stored twice; a sample is one aligned 16-byte read, staging loads twice as much.
+// in LDS, LP entries per row, and a sample interpolates between the neighbouring columns.
+// Two LDS layouts (a tile-shape option):
+//   DUP = 0: interleaved (mu, delta) pairs; a sample is two 8-byte LDS reads and applies the
+//            weights 1 - ph and ph with four FMAs;
+//   DUP = 1: 16-byte entries (mu, delta of column c, then the differences to column c + 1),
+//            each column loaded twice; a sample is one aligned 16-byte read, an add and an
+//            FMA per map (x_c + ph (x_{c+1} - x_c)), staging loads twice as much.
 // The next strip's window is loaded into registers (buffer loads: rows past the map read as
 // zero) while the current one is consumed.
 //
@@ -164,11 +166,16 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             __syncthreads();                           // previous strip fully consumed
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
+                Entry e = buf[q];
+                if constexpr (DUP != 0) {      // stored as (x_c, x_{c+1} - x_c) per map
+                    e.z -= e.x;
+                    e.w -= e.y;
+                }
                 if constexpr (WIDE) {
-                    if (c0w < win_w && (LP == PW || sc < LP)) win[(sr + q * RS) * LP + sc] = buf[q];
+                    if (c0w < win_w && (LP == PW || sc < LP)) win[(sr + q * RS) * LP + sc] = e;
                 } else {
                     const int c = tid + (q % CS) * NT;
-                    if (LP == PW || c < LP) win[(q / CS) * LP + c] = buf[q];
+                    if (LP == PW || c < LP) win[(q / CS) * LP + c] = e;
                 }
             }
             __syncthreads();
@@ -181,27 +188,26 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
             const double fl0 = floor(up0 + fmin(0.0, (double)(R - 1) * slope)) - 1.0;
             const float uf = (float)(up0 - fl0);
             const Entry* rowp = win + ((int)fl0 - lo);
-            float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+            float c0 = 0.f, c1 = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float u = fmaf((float)r, slope_f, uf);
+                const float u = r == 0 ? uf : fmaf((float)r, slope_f, uf);
                 const float ph = __builtin_amdgcn_fractf(u);
                 const Entry* q = rowp + r * LP + (int)u;
-                float4 v;
                 if constexpr (DUP != 0) {
-                    v = *(const float4*)q;
+                    // x_c + ph (x_{c+1} - x_c): the interpolation without a 1 - ph weight
+                    const float4 v = *(const float4*)q;
+                    c0 = fmaf(ph, v.z, c0 + v.x);
+                    c1 = fmaf(ph, v.w, c1 + v.y);
                 } else {
                     const float2 v0 = ((const float2*)q)[0], v1 = ((const float2*)q)[1];
-                    v = make_float4(v0.x, v0.y, v1.x, v1.y);
+                    const float om = 1.f - ph;
+                    c0 = fmaf(ph, v1.x, fmaf(om, v0.x, c0));
+                    c1 = fmaf(ph, v1.y, fmaf(om, v0.y, c1));
                 }
-                const float om = 1.f - ph;
-                c0 = fmaf(om, v.x, c0);
-                c1 = fmaf(om, v.y, c1);
-                c2 = fmaf(ph, v.z, c2);
-                c3 = fmaf(ph, v.w, c3);
             }
-            acc_m += (double)c0 + (double)c2;     // strip sums combined in FP64
-            acc_d += (double)c1 + (double)c3;
+            acc_m += (double)c0;                  // strip sums combined in FP64
+            acc_d += (double)c1;
         }
         if (a >= 0 && k < d.n_det) {
             d.P[(size_t)a * d.n_det + k] = (float)(wstep * acc_m);

@@ -36,10 +36,11 @@ __device__ inline void compact_direction(SolverState& s, const double* a, const 
     const double gamma = SY[(mc - 1) * W + (mc - 1)] / YY[(mc - 1) * W + (mc - 1)];
     const bool on = lane < mc;
     const double Rrr = on ? SY[lane * W + lane] : 1.0;
+    const double rinv = 1.0 / Rrr;                    // one division per lane, off the chain
     const double ar = on ? a[lane] : 0.0, br = on ? b[lane] : 0.0;
     double acc = ar, c = 0.0;
     for (int q = mc - 1; q >= 0; --q) {               // c_q known once rows > q are folded in
-        const double cq = __shfl(acc / Rrr, q);
+        const double cq = __shfl(acc * rinv, q);
         if (lane == q) c = cq;
         if (lane < q) acc -= SY[lane * W + q] * cq;
     }
@@ -50,7 +51,7 @@ __device__ inline void compact_direction(SolverState& s, const double* a, const 
     }
     double acc2 = v, e = 0.0;
     for (int q = 0; q < mc; ++q) {
-        const double eq = __shfl(acc2 / Rrr, q);
+        const double eq = __shfl(acc2 * rinv, q);
         if (lane == q) e = eq;
         if (on && lane > q) acc2 -= SY[q * W + lane] * eq;
     }
