@@ -297,9 +297,9 @@ def _main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--n-train", type=int, default=configs.WARMSTART.n_train)
-    t.add_argument("--n-val", type=int, default=128)
+    t.add_argument("--n-val", type=int, default=configs.WARMSTART.n_val)
     t.add_argument("--target-iters", type=int, default=configs.WARMSTART.target_iters)
-    t.add_argument("--epochs", type=int, default=30)
+    t.add_argument("--epochs", type=int, default=configs.WARMSTART.epochs)
     t.add_argument("--batch", type=int, default=16)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--workers", type=int, default=16)
@@ -307,6 +307,10 @@ def _main():
     t.add_argument("--axis-max", type=float, default=0.4,
                    help="largest ellipse semi-axis as a fraction of n/2 (0.8 at 256^2 spans the "
                         "pixel sizes of 0.4 at 512^2)")
+    t.add_argument("--train-n", type=int, default=configs.WARMSTART.train_n,
+                   help="grid size of the training slices")
+    t.add_argument("--train-theta", type=int, default=configs.WARMSTART.train_theta,
+                   help="angles of the training slices")
     t.add_argument("--out", required=True, help="weights .npz (a .json log is written beside it)")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=None)
@@ -322,7 +326,7 @@ def _main():
         print(msg, flush=True)
 
     if a.cmd == "train":
-        cfg = slice_config(W.train_n, W.train_theta, W.n_mask, axis_max=a.axis_max)
+        cfg = slice_config(a.train_n, a.train_theta, W.n_mask, axis_max=a.axis_max)
         t0 = time.time()
         X, Y, st = build_training_set(cfg, range(a.n_train + a.n_val), a.target_iters,
                                       workers=a.workers, log=log)
@@ -338,7 +342,7 @@ def _main():
         meta = {"n_train": a.n_train, "n_val": a.n_val, "target_iters": a.target_iters,
                 "axis_max": a.axis_max,
                 "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "seed": a.seed,
-                "train_shape": [W.train_n, W.train_theta, W.n_mask], "data_stats": st,
+                "train_shape": [a.train_n, a.train_theta, W.n_mask], "data_stats": st,
                 "data_s": t_data, "train_s": t_train, "loss_hist": hist,
                 "val_loss": evaluate_loss(net, *val),
                 "val_identity_loss": float(((val[0] - val[1]) ** 2).mean().cpu())}
