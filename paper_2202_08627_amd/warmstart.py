@@ -311,6 +311,8 @@ def _main():
                    help="grid size of the training slices")
     t.add_argument("--train-theta", type=int, default=configs.WARMSTART.train_theta,
                    help="angles of the training slices")
+    t.add_argument("--seed0", type=int, default=0, help="first phantom seed of the training set")
+    t.add_argument("--init", default=None, help="start from these weights instead of He init")
     t.add_argument("--out", required=True, help="weights .npz (a .json log is written beside it)")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=None)
@@ -328,11 +330,14 @@ def _main():
     if a.cmd == "train":
         cfg = slice_config(a.train_n, a.train_theta, W.n_mask, axis_max=a.axis_max)
         t0 = time.time()
-        X, Y, st = build_training_set(cfg, range(a.n_train + a.n_val), a.target_iters,
-                                      workers=a.workers, log=log)
+        X, Y, st = build_training_set(cfg, range(a.seed0, a.seed0 + a.n_train + a.n_val),
+                                      a.target_iters, workers=a.workers, log=log)
         t_data = time.time() - t0
-        net = UNet(W.base_channels)
-        net.init_he(a.seed)
+        if a.init:
+            net = load_net(a.init)
+        else:
+            net = UNet(W.base_channels)
+            net.init_he(a.seed)
         val = (X[a.n_train:], Y[a.n_train:])
         log(f"[train] identity-map val loss {float(((val[0] - val[1]) ** 2).mean().cpu()):.4e}")
         t1 = time.time()
@@ -340,6 +345,7 @@ def _main():
                      val=val)
         t_train = time.time() - t1
         meta = {"n_train": a.n_train, "n_val": a.n_val, "target_iters": a.target_iters,
+                "seed0": a.seed0, "init": os.path.basename(a.init) if a.init else None,
                 "axis_max": a.axis_max,
                 "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "seed": a.seed,
                 "train_shape": [a.train_n, a.train_theta, W.n_mask], "data_stats": st,
