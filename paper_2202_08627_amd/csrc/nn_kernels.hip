@@ -269,12 +269,15 @@ hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipSt
 //                (p = (b, y, x) over the up-conv's input)
 // stored as part[z][co][tap][ci] (tap = d for the up-conv). Pixels are strided in NHWC, so
 // each 64-pixel step stages both operands transposed into LDS ([row][pixel], rows padded to
-// 72 elements): the global loads stay coalesced (consecutive threads read consecutive channel
-// pairs of a pixel) and an MFMA fragment (8 consecutive pixels of one row) is one 16-byte LDS
-// read. The next step's operands are loaded into registers while the current step is
-// multiplied. Block: TM x TN output tile (TM * TN = 64 * 64, 4 wavefronts of 32 x 32; TM = 32
-// when m has at most 32 rows); grid (m tiles, n tiles, splits), split z covering pixels
-// [z kps, min(P, (z + 1) kps)), kps a multiple of 32.
+// 72 elements): a thread loads 16 bytes (8 consecutive channels = 8 rows of one tap) for each
+// of a few consecutive pixels and writes them as 8 short row segments, and an MFMA fragment
+// (8 consecutive pixels of one row) is one 16-byte LDS read. Rows of a thread group and
+// pixel groups interleave so that each LDS write instruction covers every bank once. The
+// next step's operands are loaded into registers while the current step is multiplied.
+// Block: TM x TN output tile (TM * TN = 64 * 64, 4 wavefronts of 32 x 32; TM = 32 when m
+// has at most 32 rows); grid (m tiles, n tiles, splits), split z covering pixels
+// [z kps, min(P, (z + 1) kps)), kps a multiple of 32. Channel counts are multiples of 8, so
+// an 8-row group never straddles a tap or a sub-pixel.
 constexpr int kWgStep = 64;
 constexpr int kWgRow = kWgStep + 8;
 template <int UP, int TM>
@@ -284,8 +287,12 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     constexpr int TN = 64 * 64 / TM;
     constexpr int WM = TM / 32, WN = 4 / WM;       // wavefront grid
-    constexpr int PA = TM / 8, PB = TN / 8;        // pixels per thread per step (A, B staging)
     constexpr int NTAP = UP ? 4 : 9;
+    // A staging: OA row groups x 16 pixel groups of AP = 4 pixels (threads past OA * 16 idle);
+    // B staging: OB row groups x GB pixel groups of BP pixels (all 256 threads)
+    constexpr int OA = TM / 8, GA = 16, AP = kWgStep / GA;
+    constexpr int OB = TN / 8, GB = 256 / OB, BP = kWgStep / GB;
+    static_assert(AP == 4 && (BP == 4 || BP == 2), "staging shapes");
     __shared__ __attribute__((aligned(16))) bf16 As[TM * kWgRow], Bs[TN * kWgRow];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
@@ -294,13 +301,13 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     const int Co = dz.C, Ci = x.C;
     const int M = UP ? 4 * Co : Co, N = UP ? Ci : 9 * Ci;
     const int H = x.H, W = x.W;                  // the pixel grid p runs over
-    // A staging: row pair (2ra, 2ra+1), pixels PA*ga ..; B: column pair (2nb, 2nb+1), PB*gb ..
-    const int ra = tid % (TM / 2), ga = tid / (TM / 2);
-    const int nb = tid % (TN / 2), gb = tid / (TN / 2);
-    const int m = m0 + 2 * ra;
-    const bool m_ok = m < M;
+    const int ga = tid % GA, oa = tid / GA;
+    const bool a_act = oa < OA;
+    const int gb = tid % GB, ob = tid / GB;
+    const int m = m0 + 8 * oa;
+    const bool m_ok = a_act && m < M;
     const int d = UP && m_ok ? m / Co : 0, co = m_ok ? m - d * Co : 0;
-    const int n = n0 + 2 * nb;
+    const int n = n0 + 8 * ob;
     const bool n_ok = n < N;
     const int tap = !UP && n_ok ? n / Ci : 4, ci = n_ok ? n - (UP ? 0 : tap * Ci) : 0;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;  // zero shift for the up-conv (tap 4)
@@ -309,36 +316,35 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x2 av[PA], bv[PB];
-    const bf16x2 zero2 = bf16x2{(__bf16)0.f, (__bf16)0.f};
+    bf16x8 av[AP], bv[BP];
     auto load = [&](int k0) {
-        {   // A: dZ at the pixel (conv), G at the row's sub-pixel d (up-conv)
-            int p = k0 + PA * ga;
+        if (a_act) {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv)
+            int p = k0 + AP * ga;
             int yb = p / W, xx = p - yb * W;     // one division per step, then carries
             int b = yb / H, yy = yb - b * H;
 #pragma unroll
-            for (int q = 0; q < PA; ++q) {
-                av[q] = zero2;
+            for (int q = 0; q < AP; ++q) {
+                av[q] = zero8();
                 if (p < pe && m_ok) {
                     size_t o;
                     if (UP) o = ((size_t)(b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs;
                     else o = (size_t)p * dz.cs;
-                    av[q] = *(const bf16x2*)(dz.p + o + dz.coff + co);
+                    av[q] = ld8(dz.p + o + dz.coff + co);
                 }
                 ++p;
                 if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
             }
         }
-        {   // B: X at the pixel shifted by the column's tap (conv) or at the pixel (up-conv)
-            int p = k0 + PB * gb;
+        {   // B: X at the pixel shifted by the row group's tap (conv) or at the pixel (up-conv)
+            int p = k0 + BP * gb;
             int yb = p / W, xx = p - yb * W;
             int b = yb / H, yy = yb - b * H;
 #pragma unroll
-            for (int q = 0; q < PB; ++q) {
-                bv[q] = zero2;
+            for (int q = 0; q < BP; ++q) {
+                bv[q] = zero8();
                 const int sy = yy + dy, sx = xx + dx;
                 if (p < pe && n_ok && (unsigned)sy < (unsigned)H && (unsigned)sx < (unsigned)W)
-                    bv[q] = *(const bf16x2*)(x.p + ((size_t)(b * H + sy) * W + sx) * x.cs + x.coff + ci);
+                    bv[q] = ld8(x.p + ((size_t)(b * H + sy) * W + sx) * x.cs + x.coff + ci);
                 ++p;
                 if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
             }
@@ -347,16 +353,19 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     load(pb);
     for (int k0 = pb; k0 < pe; k0 += kWgStep) {
         __syncthreads();                       // previous step's fragments consumed
+        if (a_act) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+            for (int c = 0; c < 8; ++c)
+                *(bf16x4*)(As + (8 * oa + c) * kWgRow + AP * ga) =
+                    bf16x4{av[0][c], av[1][c], av[2][c], av[3][c]};
+        }
 #pragma unroll
-            for (int h = 0; h < PA / 4; ++h)
-                *(bf16x4*)(As + (2 * ra + c) * kWgRow + PA * ga + 4 * h) =
-                    bf16x4{av[4 * h][c], av[4 * h + 1][c], av[4 * h + 2][c], av[4 * h + 3][c]};
-#pragma unroll
-            for (int h = 0; h < PB / 4; ++h)
-                *(bf16x4*)(Bs + (2 * nb + c) * kWgRow + PB * gb + 4 * h) =
-                    bf16x4{bv[4 * h][c], bv[4 * h + 1][c], bv[4 * h + 2][c], bv[4 * h + 3][c]};
+        for (int c = 0; c < 8; ++c) {
+            if constexpr (BP == 4)
+                *(bf16x4*)(Bs + (8 * ob + c) * kWgRow + BP * gb) =
+                    bf16x4{bv[0][c], bv[1][c], bv[2][c], bv[3][c]};
+            else
+                *(bf16x2*)(Bs + (8 * ob + c) * kWgRow + BP * gb) = bf16x2{bv[0][c], bv[1][c]};
         }
         __syncthreads();
         if (k0 + kWgStep < pe) load(k0 + kWgStep);

@@ -158,8 +158,10 @@ def warm_start(plan: ops.Plan, s_exp: torch.Tensor, net: UNet | None, cfg, lam: 
     if net is not None:
         z = (x_ss / sc).unsqueeze(0).contiguous()
         cands["unet"] = (net(z)[0] * sc).contiguous()
-    costs = {k: float(plan.cost_and_grad(v, s_exp, lam_mu, lam_de, want_grad=False)[0].cpu())
-             for k, v in cands.items()}
+    # the candidates' costs stay on the device until one transfer reads them all
+    dev_costs = [plan.cost_and_grad(v, s_exp, lam_mu, lam_de, want_grad=False)[0].reshape(1)
+                 for v in cands.values()]
+    costs = dict(zip(cands.keys(), torch.cat(dev_costs).cpu().tolist()))
     choice = guard_choice(costs)
     return cands[choice], choice, costs
 
