@@ -243,7 +243,8 @@ const char* eit_last_error(void);
  * c = angles per chunk, d = voxels per thread), kind 2 = projector LDS layout (a = 1 if a
  * sample reads one 16-byte entry holding both neighbouring columns, 0 if it reads two 8-byte
  * (mu, delta) pairs; b = entries per LDS row, the widest window the variant accepts, at most
- * the staged width d of kind 0). Returns the number of variants of that kind; fills a/b/c/d (each may
+ * the staged width d of kind 0; c = 1 if a wavefront follows 8 detectors of 8 angles instead
+ * of 64 detectors of one angle). Returns the number of variants of that kind; fills a/b/c/d (each may
  * be NULL) for index v if in range. */
 int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c, int32_t* d);
 

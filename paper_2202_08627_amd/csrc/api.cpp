@@ -917,6 +917,7 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
         if (v >= 0 && v < n) {
             if (a) *a = proj_variant(v).DUP;
             if (b) *b = proj_variant(v).LP;
+            if (c) *c = proj_variant(v).IL;
         }
         return n;
     }

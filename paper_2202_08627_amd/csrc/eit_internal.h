@@ -32,8 +32,9 @@ struct AdjAngle {
 };
 
 // Tile shapes (compile-time variants, chosen per grid-size class).
-struct ProjTile { int A, W, R, PW, DUP, LP; };   // angles per group, detectors per block, rows per strip,
-                                                // staged width, 16-byte entries, LDS row pitch
+struct ProjTile { int A, W, R, PW, DUP, LP, IL; };  // angles per group, detectors per block, rows per
+                                                   // strip, staged width, 16-byte entries, LDS row
+                                                   // pitch, interleaved rays (8 angles per wavefront)
 struct AdjTile  { int TX, TY, AC, VPT; }; // voxel tile, angles per staged chunk, voxels per thread
 
 // ---------------------------------------------------------------- per-slice descriptor

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // for all rays of the block; the host builds lo and win_w from FP64 extremes with a 1e-3
 // margin, and the host tests replay this exact FP32/FP64 arithmetic for every work item of
 // the benchmark and test geometries.
-template <int A, int W, int R, int PW, int DUP, int LP>
+template <int A, int W, int R, int PW, int DUP, int LP, int IL>
 __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
     constexpr int NT = A * W;
@@ -95,19 +95,44 @@ __global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ 
     // LDS rows of LP entries (LP <= PW; window columns past LP are never staged or read)
     __shared__ Entry win[R * LP];
     const int tid = threadIdx.x;
-    const int al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
-    const int kl = tid % W;
+    // ray of this thread: angle slot al, detector kl of the block
+    //   IL = 0: a wavefront follows 64 consecutive detectors of one angle;
+    //   IL = 1: a wavefront follows 8 consecutive detectors of 8 angles, each 16-lane group
+    //           two angles x 8 detectors. LDS serves a 16-byte read 16 lanes at a time; 16
+    //           rays of one angle reach over 16 / |cos| > 16 entries, so their entries meet
+    //           in a bank, while two neighbouring angles over 8 detectors stay within ~15.
+    static_assert(!IL || (A % 8 == 0 && W % 8 == 0), "interleaved rays need 8-angle groups");
+    int al, kl;
+    if constexpr (IL != 0) {
+        constexpr int DO = W / 8;                // detector octets per angle
+        const int wv = tid >> 6, lane = tid & 63;
+        al = 8 * (wv / DO) + (lane >> 3);
+        kl = 8 * (wv % DO) + (lane & 7);
+    } else {
+        al = __builtin_amdgcn_readfirstlane(tid / W);   // uniform per wavefront
+        kl = tid % W;
+    }
     const int sc = tid % PW, sr = tid / PW;  // staging column and first row of this thread
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
         if (skipped(d)) continue;
         const int n = d.n, grp = w.y, dblk = w.z;
-        const int a = cld(d.groups + grp * A + al);
         const int a0 = cld(d.groups + grp * A);
-        const ProjAngle* pp = d.pang + (a >= 0 ? a : a0);
-        const double inv = cld(&pp->inv), base = cld(&pp->base), slope = cld(&pp->slope);
-        const float slope_f = cld(&pp->slope_f), wstep = cld(&pp->w);
+        int a;
+        double inv, base, slope;
+        float slope_f, wstep;
+        if constexpr (IL != 0) {                 // angle differs across the wavefront
+            a = d.groups[grp * A + al];
+            const ProjAngle* pp = d.pang + (a >= 0 ? a : a0);
+            inv = pp->inv; base = pp->base; slope = pp->slope;
+            slope_f = pp->slope_f; wstep = pp->w;
+        } else {
+            a = cld(d.groups + grp * A + al);
+            const ProjAngle* pp = d.pang + (a >= 0 ? a : a0);
+            inv = cld(&pp->inv); base = cld(&pp->base); slope = cld(&pp->slope);
+            slope_f = cld(&pp->slope_f); wstep = cld(&pp->w);
+        }
         const int src = cld(&d.pang[a0].src);
         const int k = dblk * W + kl;
         const int k_eff = k < d.n_det ? k : d.n_det - 1;
@@ -492,24 +517,28 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 // Projector variants (A angles x W detectors threads, R rows per strip, PW staged entries per
 // row, DUP = duplicated 16-byte entries).
 #define EIT_PROJ_VARIANTS(X)        \
-    X(0, 8, 64, 16, 256, 0, 256)    \
-    X(1, 4, 64, 16, 128, 0, 128)    \
-    X(2, 16, 64, 8, 256, 0, 256)    \
-    X(3, 8, 64, 8, 256, 0, 256)     \
-    X(4, 4, 128, 16, 256, 0, 256)   \
-    X(5, 8, 64, 32, 256, 0, 256)    \
-    X(6, 16, 64, 16, 256, 0, 256)   \
-    X(7, 2, 64, 16, 128, 0, 128)    \
-    X(8, 1, 64, 16, 128, 0, 128)    \
-    X(9, 16, 64, 16, 256, 1, 256)   \
-    X(10, 16, 64, 8, 256, 1, 256)   \
-    X(11, 8, 64, 8, 256, 1, 256)    \
-    X(12, 8, 64, 8, 128, 1, 128)    \
-    X(13, 8, 64, 16, 128, 1, 128)   \
-    X(14, 4, 64, 16, 128, 1, 128)   \
-    X(15, 4, 64, 8, 128, 1, 128)    \
-    X(16, 8, 64, 16, 256, 1, 136)   \
-    X(17, 8, 64, 8, 256, 1, 128)
+    X(0, 8, 64, 16, 256, 0, 256, 0)    \
+    X(1, 4, 64, 16, 128, 0, 128, 0)    \
+    X(2, 16, 64, 8, 256, 0, 256, 0)    \
+    X(3, 8, 64, 8, 256, 0, 256, 0)     \
+    X(4, 4, 128, 16, 256, 0, 256, 0)   \
+    X(5, 8, 64, 32, 256, 0, 256, 0)    \
+    X(6, 16, 64, 16, 256, 0, 256, 0)   \
+    X(7, 2, 64, 16, 128, 0, 128, 0)    \
+    X(8, 1, 64, 16, 128, 0, 128, 0)    \
+    X(9, 16, 64, 16, 256, 1, 256, 0)   \
+    X(10, 16, 64, 8, 256, 1, 256, 0)   \
+    X(11, 8, 64, 8, 256, 1, 256, 0)    \
+    X(12, 8, 64, 8, 128, 1, 128, 0)    \
+    X(13, 8, 64, 16, 128, 1, 128, 0)   \
+    X(14, 4, 64, 16, 128, 1, 128, 0)   \
+    X(15, 4, 64, 8, 128, 1, 128, 0)    \
+    X(16, 8, 64, 16, 256, 1, 136, 0)   \
+    X(17, 8, 64, 8, 256, 1, 128, 0)     \
+    X(18, 8, 64, 8, 256, 1, 128, 1)     \
+    X(19, 8, 64, 16, 256, 1, 136, 1)    \
+    X(20, 16, 64, 8, 256, 1, 256, 1)    \
+    X(21, 8, 64, 8, 256, 1, 256, 1)
 
 // Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
@@ -524,17 +553,17 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 
 int proj_variant_count() {
     int c = 0;
-#define X(id, A, W, R, PW, DUP, LP) ++c;
+#define X(id, A, W, R, PW, DUP, LP, IL) ++c;
     EIT_PROJ_VARIANTS(X)
 #undef X
     return c;
 }
 ProjTile proj_variant(int v) {
-#define X(id, A, W, R, PW, DUP, LP) \
-    if (v == id) return ProjTile{A, W, R, PW, DUP, LP};
+#define X(id, A, W, R, PW, DUP, LP, IL) \
+    if (v == id) return ProjTile{A, W, R, PW, DUP, LP, IL};
     EIT_PROJ_VARIANTS(X)
 #undef X
-    return ProjTile{0, 0, 0, 0, 0, 0};
+    return ProjTile{0, 0, 0, 0, 0, 0, 0};
 }
 int adj_pitch_limit(int v) {
 #define X(id, TX, TY, AC, VPT) \
@@ -568,11 +597,11 @@ hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, 
 hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, int n_items,
                           int grid, size_t lds, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, A, W, R, PW, DUP, LP)                                                  \
-    if (variant == id) {                                                             \
-        (void)lds;                                                                   \
-        k_project<A, W, R, PW, DUP, LP><<<grid, A * W, 0, s>>>(D, items, n_items);   \
-        return hipGetLastError();                                                    \
+#define X(id, A, W, R, PW, DUP, LP, IL)                                                  \
+    if (variant == id) {                                                                 \
+        (void)lds;                                                                       \
+        k_project<A, W, R, PW, DUP, LP, IL><<<grid, A * W, 0, s>>>(D, items, n_items);   \
+        return hipGetLastError();                                                        \
     }
     EIT_PROJ_VARIANTS(X)
 #undef X
