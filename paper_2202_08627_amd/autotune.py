@@ -14,6 +14,7 @@ adjoint variant, adjoint split), or (-1, -1, 0) = library defaults.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 
@@ -25,7 +26,8 @@ from . import ops, synth
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
 SPLITS = (1, 2, 4, 8)
 SOLVER_CANDIDATES = 4
-SOLVER_ITERS = 20
+SOLVER_ITERS = 40
+SOLVER_REPS = 3
 
 
 def size_key(geo) -> str:
@@ -97,25 +99,27 @@ def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
                 print(f"  backproject variant {v} {shape} split {g}: {ms * 1e3:.1f} us", flush=True)
             plan.close()
     pv = min(res["proj"], key=res["proj"].get)
-    # optimiser-step timing of the best adjoint candidates (synthetic data: the flat-field
-    # intensities with 1 % noise; the per-evaluation cost does not depend on the values)
-    mk = geo.mask_pos[:, None] - geo.flat_ctr[None, :]
-    flat = geo.flat_amp[None, :] * np.exp(-mk ** 2 / (2 * geo.flat_sigma[None, :] ** 2))
-    s = np.broadcast_to(flat, (geo.n_theta,) + flat.shape) * (1 + 0.01 * rng.standard_normal(
-        (geo.n_theta,) + flat.shape))
-    s_exp = torch.as_tensor(s.astype(np.float32), device="cuda")
+    # optimiser-step timing of the best adjoint candidates on a simulated random-ellipse slice
+    # of this size (a run that keeps iterating; flat data would stop within a few steps)
+    from . import warmstart
+    cfg = warmstart.slice_config(geo.n, geo.n_theta, geo.n_mask)
+    cfg = dataclasses.replace(cfg, n_det=geo.n_det)
+    case = synth.make_case(cfg, seed=12345)
+    sgeo = ops.Geometry.from_case(case)
+    s_exp = torch.as_tensor(case.s_exp, device="cuda")
+    kw = dict(lam=cfg.lam, mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale)
     step = {}
     for key in sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]:
-        plan = ops.Plan(geo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1])
+        plan = ops.Plan(sgeo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1])
         ws = plan.workspace(L.EIT_OP_RECONSTRUCT, 10)
-        plan.reconstruct(s_exp, iters=2, ws=ws)
+        plan.reconstruct(s_exp, iters=2, ws=ws, **kw)
         best = float("inf")
-        for _ in range(2):
+        for _ in range(SOLVER_REPS):
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            _, rep, _ = plan.reconstruct(s_exp, iters=SOLVER_ITERS, ws=ws)
+            _, rep, _ = plan.reconstruct(s_exp, iters=SOLVER_ITERS, ws=ws, **kw)
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1) / max(rep["evals"], 1))

@@ -464,15 +464,21 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 const float omw = rec2[cb][aa];
                 const float u0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
                 const float4* row = gw + aa * PK;
+                // all of the thread's bin reads for this angle are issued before any is used
+                float4 g[VPT];
+                float f[VPT];
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
                     const float u = q == 0 ? u0 : fmaf((float)(q * JS), r1.y, u0);
-                    const float f = __builtin_amdgcn_fractf(u);
-                    const float w0 = __builtin_amdgcn_fmed3f(fmaf(-f, r1.w, 1.f), 0.f, 1.f);
-                    const float w1 = __builtin_amdgcn_fmed3f(fmaf(f, r1.w, omw), 0.f, 1.f);
-                    const float4 g = row[(int)u];
-                    am[q] = fmaf(w0, g.x, fmaf(w1, g.z, am[q]));
-                    ad[q] = fmaf(w0, g.y, fmaf(w1, g.w, ad[q]));
+                    f[q] = __builtin_amdgcn_fractf(u);
+                    g[q] = row[(int)u];
+                }
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const float w0 = __builtin_amdgcn_fmed3f(fmaf(-f[q], r1.w, 1.f), 0.f, 1.f);
+                    const float w1 = __builtin_amdgcn_fmed3f(fmaf(f[q], r1.w, omw), 0.f, 1.f);
+                    am[q] = fmaf(w0, g[q].x, fmaf(w1, g[q].z, am[q]));
+                    ad[q] = fmaf(w0, g[q].y, fmaf(w1, g[q].w, ad[q]));
                 }
             }
 #pragma unroll
