@@ -1,5 +1,6 @@
-// Device-side L-BFGS control logic (compact representation, Armijo backtracking), shared by
-// the kernels whose last finishing block runs a slice's decision and memory update.
+// Device-side L-BFGS control logic (compact representation, Armijo backtracking): the
+// line-search decision and the memory update with the next direction's coefficients, each
+// run by one block per slice (k_lb_decide, k_lb_finalize in lbfgs.hip).
 #pragma once
 #include "device_common.h"
 #include "reduce.h"
@@ -81,7 +82,7 @@ __device__ inline void finish(SolverState& s, int status) {
 
 // ------------------------------------------------------------------------ decision
 // Block-wide: reduce the cost at the trial point (FP64, fixed order) and run the Armijo test
-// F(zt) <= F(z) + c1 alpha g.d. Run by the block that completes a slice's IC work items.
+// F(zt) <= F(z) + c1 alpha g.d. One block per slice, after the IC launch.
 __device__ inline void decide_body(const SliceDesc& d, SolverState& s) {
     __shared__ double red[kIcThreads / 64];
     double a = 0.0, r0 = 0.0, r1 = 0.0;
