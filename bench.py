@@ -47,7 +47,7 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_PER_SAMPLE = 12.0
 FLOPS_PER_VOXEL_ANGLE = 18.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2202_08627_amd", "csrc", "kernels.hip")
-WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_512.npz")
+WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.npz")
 # HBM bytes per launch at this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
 # this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.

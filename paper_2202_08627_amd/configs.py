@@ -112,14 +112,14 @@ BATCH_256 = BatchConfig()
 
 @dataclass(frozen=True)
 class WarmStartConfig:
-    """Learned warm start: 4-level U-Net, 32 base channels, trained at 512^2/720 (the
-    evaluation shape)."""
-    train_n: int = 512
-    train_theta: int = 720
+    """Learned warm start: 4-level U-Net, 32 base channels, trained at 256^2/360 on 4000
+    random-ellipse slices, evaluated at 512^2/720."""
+    train_n: int = 256
+    train_theta: int = 360
     n_mask: int = 8
-    n_train: int = 2000
-    n_val: int = 64
-    epochs: int = 40
+    n_train: int = 4000
+    n_val: int = 128
+    epochs: int = 80
     target_iters: int = 300
     eval_n: int = 512
     eval_theta: int = 720

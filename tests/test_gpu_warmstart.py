@@ -12,7 +12,7 @@ import torch
 pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2202_08627_amd", "weights", "unet_b32_512.npz")
+                       "paper_2202_08627_amd", "weights", "unet_b32_256.npz")
 
 
 def _case(seed):
