@@ -78,8 +78,11 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // for all rays of the block; the host builds lo and win_w from FP64 extremes with a 1e-3
 // margin, and the host tests replay this exact FP32/FP64 arithmetic for every work item of
 // the benchmark and test geometries.
+// Interleaved 16-row variants are held to 80 VGPRs (six wavefronts per SIMD, three 512-thread
+// blocks per CU); unconstrained they take 84 and only two blocks fit.
 template <int A, int W, int R, int PW, int DUP, int LP, int IL>
-__global__ __launch_bounds__(A* W) void k_project(const SliceDesc* __restrict__ D,
+__global__ __launch_bounds__(A* W) __attribute__((amdgpu_waves_per_eu(IL && R >= 16 ? 6 : 1)))
+void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
     constexpr int NT = A * W;
     static_assert(W % 64 == 0, "one angle per whole wavefront");
