@@ -23,6 +23,15 @@ __device__ inline void reset_memory(SolverState& s) {
     s.spare = 0;
 }
 
+// Value of lane q (the same q in every lane) in every lane: two scalar lane reads instead of
+// an LDS permute, which keeps the substitution chains below short.
+__device__ __forceinline__ double lane_bcast(double v, int q) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), q);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), q);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Direction coefficients from a_r = s_r.g, b_r = y_r.g (ring order, oldest first). SY and YY
 // are the ring-ordered m_cur x m_cur matrices (row stride kMaxM) in LDS. Runs in the first
 // wavefront of the block: lane r owns row r, and each substitution step broadcasts the newly
@@ -41,18 +50,18 @@ __device__ inline void compact_direction(SolverState& s, const double* a, const 
     const double ar = on ? a[lane] : 0.0, br = on ? b[lane] : 0.0;
     double acc = ar, c = 0.0;
     for (int q = mc - 1; q >= 0; --q) {               // c_q known once rows > q are folded in
-        const double cq = __shfl(acc * rinv, q);
+        const double cq = lane_bcast(acc * rinv, q);
         if (lane == q) c = cq;
         if (lane < q) acc -= SY[lane * W + q] * cq;
     }
     double v = on ? Rrr * c - gamma * br : 0.0;
     for (int q = 0; q < mc; ++q) {
-        const double cq = __shfl(c, q);
+        const double cq = lane_bcast(c, q);
         if (on) v += gamma * YY[lane * W + q] * cq;
     }
     double acc2 = v, e = 0.0;
     for (int q = 0; q < mc; ++q) {
-        const double eq = __shfl(acc2 * rinv, q);
+        const double eq = lane_bcast(acc2 * rinv, q);
         if (lane == q) e = eq;
         if (on && lane > q) acc2 -= SY[q * W + lane] * eq;
     }
