@@ -549,7 +549,9 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     X(20, 16, 64, 8, 256, 1, 256, 1)    \
     X(21, 8, 64, 8, 256, 1, 256, 1)     \
     X(22, 8, 64, 12, 256, 1, 128, 1)    \
-    X(23, 8, 64, 12, 256, 1, 136, 1)
+    X(23, 8, 64, 12, 256, 1, 136, 1)    \
+    X(24, 8, 64, 12, 128, 1, 128, 1)    \
+    X(25, 8, 64, 16, 128, 1, 128, 1)
 
 // Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
 #define EIT_ADJ_VARIANTS(X) \
