@@ -220,8 +220,13 @@ int eit_reconstruct_batch(int32_t n_slices, const eit_plan* const* plans,
  * and LDS bounds can be checked on the host. Output arrays may be NULL; if given they need
  * 6*n_theta doubles (per angle: inv, base, slope, slope as float, step weight, source 0/1),
  * n_groups*proj_a int32 (angle ids, -1 = empty), n_groups*n_dblk*n_strips int32 (window
- * origins) and 8*n_theta doubles (per angle: cos, sin, offset, cos as float, sin as float,
- * 1/w, 1/w^2, 1/w - 1/w^2). Call once with NULL arrays to learn the sizes. */
+ * origins) and 10*n_theta doubles (per angle: cos, sin, offset, cos as float, sin as float,
+ * 1/w, 1/w^2, 1/w - 1/w^2, mirror-frame offset, mirror partner). The mirror-frame offset
+ * cd_s places voxel (i, j) at detector coordinate -i cos + j sin + cd_s (the angle pi - theta).
+ * The mirror partner is filled for mirror-pair adjoint variants (adj_mirror = 1): the later
+ * angle b with cos b = -cos a and sin b = sin a that angle a is paired with, -1 if a has none,
+ * -2 if a is itself the partner of an earlier angle; n_pairs counts the angles that are not -2.
+ * Otherwise it is -1 for every angle. Call once with NULL arrays to learn the sizes. */
 typedef struct {
     int32_t proj_variant, adj_variant;
     int32_t proj_a, proj_w, proj_r;
@@ -229,6 +234,7 @@ typedef struct {
     int32_t n_groups, n_dblk, n_strips, win_w, win_pitch;
     int32_t kwin, kwin_pitch_limit, n_tx, n_ty;
     int32_t adj_splits;
+    int32_t adj_mirror, n_pairs;
     int64_t proj_lds_bytes;
 } eit_plan_info;
 int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
@@ -244,8 +250,10 @@ const char* eit_last_error(void);
  * sample reads one 16-byte entry holding both neighbouring columns, 0 if it reads two 8-byte
  * (mu, delta) pairs; b = entries per LDS row, the widest window the variant accepts, at most
  * the staged width d of kind 0; c = 1 if a wavefront follows 8 detectors of 8 angles instead
- * of 64 detectors of one angle). Returns the number of variants of that kind; fills a/b/c/d (each may
- * be NULL) for index v if in range. */
+ * of 64 detectors of one angle), kind 3 = adjoint kernel form (a = 1 for the mirror-pair
+ * kernel: each voxel with its row mirror and each angle with its mirror angle pi - theta; its
+ * c of kind 1 counts angle pairs). Returns the number of variants of that kind; fills a/b/c/d
+ * (each may be NULL) for index v if in range. */
 int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b, int32_t* c, int32_t* d);
 
 /* ---------------------------------------------------------------------------------------

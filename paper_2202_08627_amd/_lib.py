@@ -66,7 +66,7 @@ class PlanInfo(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "proj_variant", "adj_variant", "proj_a", "proj_w", "proj_r", "adj_tx", "adj_ty", "adj_ac",
         "n_groups", "n_dblk", "n_strips", "win_w", "win_pitch", "kwin", "kwin_pitch_limit",
-        "n_tx", "n_ty", "adj_splits")] + [("proj_lds_bytes", C.c_int64)]
+        "n_tx", "n_ty", "adj_splits", "adj_mirror", "n_pairs")] + [("proj_lds_bytes", C.c_int64)]
 
 
 class UNetLayer(C.Structure):

@@ -93,7 +93,8 @@ def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
             print(f"  project variant {v} {shape}: {ms * 1e3:.1f} us", flush=True)
         plan.close()
     for v, shape in enumerate(ops.variants(1)):
-        nchunks = -(-geo.n_theta // shape[2])
+        units = geo.n_theta // 2 + 1 if shape[4] else geo.n_theta   # angle pairs if mirrored
+        nchunks = -(-units // shape[2])
         for g in SPLITS:
             if g > 1 and g > nchunks // 2:
                 continue

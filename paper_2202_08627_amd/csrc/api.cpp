@@ -83,6 +83,7 @@ struct eit_plan {
     size_t proj_lds;
     int n_tx, n_ty, kwin;
     int adj_splits;        // adjoint blocks per voxel tile (angle ranges)
+    int n_pairs;           // mirror-pair adjoint: angle pair slots (0 otherwise)
     int n_trx;             // transpose tiles per side
     int64_t nv;            // 2 n^2
     int n_vblocks;
@@ -91,6 +92,7 @@ struct eit_plan {
     int32_t* groups = nullptr;
     int32_t* win_lo = nullptr;
     AdjAngle* aang = nullptr;
+    int2* apairs = nullptr;
     float4* flat = nullptr;
     double* mask = nullptr;
     // single-slice item lists (slice 0)
@@ -116,7 +118,7 @@ int upload(T** dst, const std::vector<T>& v) {
 
 void free_plan(eit_plan* p) {
     if (!p) return;
-    void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->flat, p->mask,
+    void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->apairs, p->flat, p->mask,
                     p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -147,6 +149,43 @@ ProjAngle make_pangle(double th, int n, bool row) {
     return a;
 }
 
+// Mirror pairs for the mirror-pair adjoint: angle b is the mirror of a when cos b = -cos a and
+// sin b = sin a (to 1e-12), i.e. b = pi - a as a set of lines. Angles are taken in order; an
+// angle not yet used is paired with the first unused later angle that mirrors it. mate[a] is
+// that partner (a first of a pair), -1 (no partner in the set), or -2 (second of a pair).
+void mirror_pairs(const std::vector<double>& theta, std::vector<int32_t>& mate) {
+    const int nt = (int)theta.size();
+    std::vector<int> order(nt);
+    std::vector<double> cs(nt), sn(nt);
+    for (int a = 0; a < nt; ++a) {
+        order[a] = a;
+        cs[a] = std::cos(theta[a]);
+        sn[a] = std::sin(theta[a]);
+    }
+    // candidates sorted by sin, then index: a mirror has the same sin
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        return sn[x] < sn[y] || (sn[x] == sn[y] && x < y);
+    });
+    std::vector<double> key(nt);
+    for (int q = 0; q < nt; ++q) key[q] = sn[order[q]];
+    const double tol = 1e-12;
+    mate.assign(nt, -1);
+    for (int a = 0; a < nt; ++a) {
+        if (mate[a] != -1) continue;
+        const int lo = (int)(std::lower_bound(key.begin(), key.end(), sn[a] - tol) - key.begin());
+        int best = -1;
+        for (int q = lo; q < nt && key[q] <= sn[a] + tol; ++q) {
+            const int b = order[q];
+            if (b > a && mate[b] == -1 && std::fabs(cs[b] + cs[a]) <= tol && (best < 0 || b < best))
+                best = b;
+        }
+        if (best >= 0) {
+            mate[a] = best;
+            mate[best] = -2;
+        }
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -155,6 +194,8 @@ struct HostTables {
     std::vector<ProjAngle> pang;
     std::vector<int32_t> groups, win_lo;
     std::vector<AdjAngle> aang;
+    std::vector<int2> apairs;
+    std::vector<int32_t> mate;     // per angle: mirror partner (first of a pair), -1, or -2
     std::vector<float4> flat;
     std::vector<double> maskd;
     std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
@@ -281,6 +322,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         const double wv = row ? std::fabs(cs) : std::fabs(sn);
         AdjAngle q{};
         q.cs = cs; q.sn = sn; q.cd = cdet - c * (cs + sn);
+        q.cd_s = cdet - c * (-cs + sn);
         q.cs_f = (float)cs; q.sn_f = (float)sn;
         q.iw = (float)(1.0 / wv);
         q.iw2 = (float)(1.0 / (wv * wv));
@@ -294,9 +336,19 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         return fail(EIT_ERR_SHAPE, "adjoint window %d exceeds variant capacity", p->kwin);
     }
     p->n_tx = (n + p->at.TX - 1) / p->at.TX;
-    p->n_ty = (n + p->at.TY - 1) / p->at.TY;
+    // the mirror-pair adjoint runs tiles of the top half only (rows j with 2j <= n-1)
+    p->n_ty = p->at.MIR ? ((n + 1) / 2 + p->at.TY - 1) / p->at.TY : (n + p->at.TY - 1) / p->at.TY;
+    h.apairs.clear();
+    h.mate.assign(nt, -1);
+    if (p->at.MIR) {
+        mirror_pairs(theta, h.mate);
+        for (int a = 0; a < nt; ++a)
+            if (h.mate[a] != -2) h.apairs.push_back(make_int2(a, h.mate[a]));
+    }
+    p->n_pairs = (int)h.apairs.size();
     {
-        const int nchunks = (nt + p->at.AC - 1) / p->at.AC;
+        const int units = p->at.MIR ? p->n_pairs : nt;
+        const int nchunks = (units + p->at.AC - 1) / p->at.AC;
         const int want = tiling ? tiling->adj_splits : 0;
         if (want > kMaxSplits)
             return fail(EIT_ERR_INVALID_ARG, "adj_splits=%d above %d", want, kMaxSplits);
@@ -354,6 +406,7 @@ extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
     }
     if ((rc = upload(&p->pang, h.pang)) || (rc = upload(&p->groups, h.groups)) ||
         (rc = upload(&p->win_lo, h.win_lo)) || (rc = upload(&p->aang, h.aang)) ||
+        (rc = upload(&p->apairs, h.apairs)) ||
         (rc = upload(&p->flat, h.flat)) || (rc = upload(&p->mask, h.maskd)) ||
         (rc = upload(&p->it_tr, h.it_tr)) || (rc = upload(&p->it_pr, h.it_pr)) ||
         (rc = upload(&p->it_ic, h.it_ic)) || (rc = upload(&p->it_bp, h.it_bp)) ||
@@ -383,6 +436,8 @@ extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
     info->kwin = tmp.kwin; info->n_tx = tmp.n_tx; info->n_ty = tmp.n_ty;
     info->kwin_pitch_limit = adj_pitch_limit(tmp.adj_v);
     info->adj_splits = tmp.adj_splits;
+    info->adj_mirror = tmp.at.MIR;
+    info->n_pairs = tmp.n_pairs;
     if (proj_angles)
         for (size_t a = 0; a < h.pang.size(); ++a) {
             const ProjAngle& q = h.pang[a];
@@ -394,9 +449,9 @@ extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
     if (adj_angles)
         for (size_t a = 0; a < h.aang.size(); ++a) {
             const AdjAngle& q = h.aang[a];
-            double* o = adj_angles + 8 * a;
+            double* o = adj_angles + 10 * a;
             o[0] = q.cs; o[1] = q.sn; o[2] = q.cd; o[3] = q.cs_f; o[4] = q.sn_f;
-            o[5] = q.iw; o[6] = q.iw2; o[7] = q.iwm;
+            o[5] = q.iw; o[6] = q.iw2; o[7] = q.iwm; o[8] = q.cd_s; o[9] = h.mate[a];
         }
     return EIT_OK;
 }
@@ -456,6 +511,7 @@ SliceDesc base_desc(const eit_plan* p) {
     d.win_w = p->win_w; d.win_shift = p->win_shift;
     d.n_tx = p->n_tx; d.n_ty = p->n_ty; d.kwin = p->kwin;
     d.adj_splits = p->adj_splits;
+    d.n_pairs = p->n_pairs; d.apairs = p->apairs;
     d.pang = p->pang; d.groups = p->groups; d.win_lo = p->win_lo; d.aang = p->aang;
     d.flat = p->flat; d.mask = p->mask;
     d.n_reg_blocks = p->n_trx * p->n_trx;
@@ -919,6 +975,11 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
             if (b) *b = proj_variant(v).LP;
             if (c) *c = proj_variant(v).IL;
         }
+        return n;
+    }
+    if (kind == 3) {                       // adjoint kernel form
+        const int n = adj_variant_count();
+        if (v >= 0 && v < n && a) *a = adj_variant(v).MIR;
         return n;
     }
     if (kind == 1) {

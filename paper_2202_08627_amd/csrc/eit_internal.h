@@ -24,8 +24,11 @@ struct ProjAngle {
 // Gather form of R^T: voxel (i, j) projects to detector coordinate
 // u = i*cs + j*sn + cd (bins, fractional); it receives from bins floor(u) and floor(u)+1
 // with triangle weights (1/w) max(0, 1 - |k - u|/w).
+// Mirror frame of the same angle (cos -> -cos): u_s = -i*cs + j*sn + cd_s. Voxel (i, j) at
+// the mirror angle pi - theta and voxel (i, n-1-j) at theta project to u_s and n_det-1-u_s.
 struct AdjAngle {
     double cs, sn, cd;         // FP64 for the per-tile window origin
+    double cd_s;               // mirror-frame offset
     float cs_f, sn_f;          // FP32 for the inner loop
     float iw, iw2, iwm;        // 1/w, 1/w^2, 1/w - 1/w^2
     float omw;                 // 1 - 1/w
@@ -35,7 +38,8 @@ struct AdjAngle {
 struct ProjTile { int A, W, R, PW, DUP, LP, IL; };  // angles per group, detectors per block, rows per
                                                    // strip, staged width, 16-byte entries, LDS row
                                                    // pitch, interleaved rays (8 angles per wavefront)
-struct AdjTile  { int TX, TY, AC, VPT; }; // voxel tile, angles per staged chunk, voxels per thread
+struct AdjTile  { int TX, TY, AC, VPT, MIR; }; // voxel tile, angles (or angle pairs) per staged
+                                              // chunk, voxels per thread, mirror pairs 0/1
 
 // ---------------------------------------------------------------- per-slice descriptor
 // Everything a kernel needs for one slice. Lives in device memory; kernels index it by the
@@ -73,7 +77,8 @@ struct SliceDesc {
     const int32_t* skip;           // optional device flag: nonzero => kernels no-op
     const int32_t* skip_adj;       // optional: nonzero => adjoint no-ops
     // adjoint angle split: G = adj_splits blocks per voxel tile (1 = no split)
-    int32_t adj_splits, pad1;
+    int32_t adj_splits, n_pairs;   // n_pairs: entries of apairs (mirror-pair adjoint only)
+    const int2* apairs;            // [n_pairs] (angle, mirror angle or -1)
     double* bp_part;               // [G][2][n][n] FP64 partial sums of the adjoint (G > 1)
 };
 

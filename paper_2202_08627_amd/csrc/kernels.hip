@@ -357,13 +357,32 @@ constexpr int adj_pitch_max() {
     return pow2_at_least(isqrt_ceil((TX - 1) * (TX - 1) + (TY - 1) * (TY - 1)) + 4);
 }
 
+// Voxel (il, jl) of thread tid in a TX-wide tile. With TX = 32 a wavefront covers a 16 x 4
+// patch (two wavefronts side by side) rather than two 32-voxel rows: the tile keeps its
+// staging cost per voxel, and the bin reads of a wavefront stay as spread out as those of a
+// 16-wide tile, which causes no LDS bank conflicts (the 32-wide rows did).
+template <int TX>
+__device__ __forceinline__ void adj_voxel(int tid, int& il, int& jl) {
+    if constexpr (TX == 32) {   // the block has an even number of wavefronts (TY / VPT % 4 == 0)
+        const int w = tid >> 6, l = tid & 63;
+        il = (l & 15) + 16 * (w & 1);
+        jl = (l >> 4) + 4 * (w >> 1);
+    } else {
+        il = tid % TX;
+        jl = tid / TX;
+    }
+}
+
 struct TileWin { int lo; float off; };
-__device__ __forceinline__ TileWin tile_window(const AdjAngle* q, int i0, int j0, int TX, int TY) {
-    const double cs = cld(&q->cs), sn = cld(&q->sn), cd = cld(&q->cd);
+__device__ __forceinline__ TileWin tile_window_cs(double cs, double sn, double cd, int i0, int j0,
+                                                  int TX, int TY) {
     const double uc = fma((double)j0, sn, fma((double)i0, cs, cd));
     const double umin = uc + fmin(0.0, (TX - 1) * cs) + fmin(0.0, (TY - 1) * sn);
     const int lo = (int)floor(umin) - 1;
     return TileWin{lo, (float)(uc - (double)lo)};
+}
+__device__ __forceinline__ TileWin tile_window(const AdjAngle* q, int i0, int j0, int TX, int TY) {
+    return tile_window_cs(cld(&q->cs), cld(&q->sn), cld(&q->cd), i0, j0, TX, TY);
 }
 
 // Index safety: a voxel's coordinate relative to the window is u >= 1 - 1e-5 (lo is one bin
@@ -381,12 +400,14 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     static_assert(AC % AS == 0, "chunk must tile the block");
     constexpr int SLOTS = AC / AS;
     constexpr int JS = TY / VPT;
+    static_assert(TX != 32 || JS % 4 == 0, "16 x 4 wavefront patches");
     __shared__ float4 gw[AC * PK];
     __shared__ float4 rec[2][AC];            // cs, sn, offset, 1/w   (double-buffered by chunk)
     __shared__ float rec2[2][AC];            // 1 - 1/w
     __shared__ int los[2][AC];
     const int tid = threadIdx.x;
-    const int il = tid % TX, jl = tid / TX;
+    int il, jl;
+    adj_voxel<TX>(tid, il, jl);
     const int sb = tid % PK, sa = tid / PK;  // staging bin and first angle of this thread
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
@@ -522,6 +543,202 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     }
 }
 
+// ------------------------------------------------------------------------ mirror-pair adjoint
+// Same operator as k_backproject, with each voxel paired with its row mirror and each angle
+// with its mirror angle. With u = i cs + j sn + cd the detector coordinate of voxel v = (i, j)
+// at angle theta, and u_s = -i cs + j sn + cd_s that of v at pi - theta (cos -> -cos), the
+// voxel v' = (i, n-1-j) projects to n_det-1-u at pi - theta and to n_det-1-u_s at theta: four
+// voxel-angle pairs from two coordinates. A reflected coordinate n_det-1-u has its two bins at
+// fractional distances f and 1 - f from bins n_det-1-floor(u) and n_det-2-floor(u), so staging
+// those bins in descending order gives the same entry index and weights as the direct read.
+// Per pair slot (angle a, mirror b or -1) the block stages four windows, each kwin bins:
+//   W0: bins of a around u (ascending)    -> v at a      W1: bins of b, reflected at u -> v' at b
+//   W2: bins of b around u_s (ascending)  -> v at b      W3: bins of a, reflected at u_s -> v' at a
+// An angle without a mirror in the set (b = -1) stages zeros in W1 and W2: it still reaches v
+// and v' through W0 and W3. Item (slice, tile_x, tile_y, part): the tile's rows j lie in the
+// top half; a thread writes v when 2j <= n-1 and v' = (i, n-1-j) when 2j < n-1, so every voxel
+// (the middle row of an odd map included) is written once. Summation order: per voxel, the
+// pairs in order, a before b, FP32 within a chunk of AC pairs, chunk sums in FP64.
+template <int TX, int TY, int AC, int VPT>
+__global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDesc* __restrict__ D,
+                                                                   const Item* __restrict__ items,
+                                                                   int n_items, int add_reg) {
+    constexpr int NT = TX * TY / VPT;
+    constexpr int PK = adj_pitch_max<TX, TY>();
+    static_assert(NT % PK == 0, "staging must tile the block");
+    static_assert(64 % PK == 0, "a staged window row must not straddle wavefronts");
+    constexpr int NR = 4 * AC;               // window rows per chunk
+    constexpr int AS = NT / PK;              // window rows staged per slot step
+    static_assert(NR % AS == 0, "chunk must tile the block");
+    constexpr int SLOTS = NR / AS;
+    constexpr int JS = TY / VPT;
+    static_assert(TX != 32 || JS % 4 == 0, "16 x 4 wavefront patches");
+    __shared__ float4 gw[NR * PK];
+    __shared__ float4 rec[2][AC];            // cs, sn, offset of u, 1/w   (double-buffered)
+    __shared__ float2 rec2[2][AC];           // offset of u_s, 1 - 1/w
+    __shared__ int4 wins[2][AC];             // a, b, window origin for u, for u_s
+    const int tid = threadIdx.x;
+    int il, jl;
+    adj_voxel<TX>(tid, il, jl);
+    const int sb = tid % PK, sr = tid / PK;  // staging bin and first window row of this thread
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped_adj(d)) continue;
+        const int n = d.n, nd = d.n_det, nth = d.n_theta, npair = d.n_pairs;
+        const int kwin = d.kwin;
+        const int i0 = w.y * TX, j0 = w.z * TY;
+        const int sz4 = nth * nd * 4;
+        const __amdgpu_buffer_rsrc_t bGm = make_rsrc(d.P, sz4);
+        const __amdgpu_buffer_rsrc_t bGd = make_rsrc(d.P + (size_t)nth * nd, sz4);
+        const int nchunks = (npair + AC - 1) / AC;
+        const int G = d.adj_splits, gs = w.w;
+        const int ch0 = gs * nchunks / G, ch1 = (gs + 1) * nchunks / G;
+
+        auto pair_setup = [&](int ch) {
+            if (tid < AC) {
+                const int pi = ch * AC + tid;
+                // padding slot: no angle, every window stages zeros
+                float4 r1 = make_float4(0.f, 0.f, 1.f, 0.f);
+                float2 r2 = make_float2(1.f, 0.f);
+                int4 wv = make_int4(-1, -1, 0, 0);
+                if (pi < npair) {
+                    const int2 pr = d.apairs[pi];
+                    const AdjAngle* q = d.aang + pr.x;
+                    const double cs = cld(&q->cs), sn = cld(&q->sn);
+                    const TileWin tu = tile_window_cs(cs, sn, cld(&q->cd), i0, j0, TX, TY);
+                    const TileWin ts = tile_window_cs(-cs, sn, cld(&q->cd_s), i0, j0, TX, TY);
+                    r1 = make_float4(cld(&q->cs_f), cld(&q->sn_f), tu.off, cld(&q->iw));
+                    r2 = make_float2(ts.off, cld(&q->omw));
+                    wv = make_int4(pr.x, pr.y, tu.lo, ts.lo);
+                }
+                rec[ch & 1][tid] = r1;
+                rec2[ch & 1][tid] = r2;
+                wins[ch & 1][tid] = wv;
+            }
+        };
+        float2 buf[SLOTS];
+        auto load_chunk = [&](int ch) {
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) {
+                const int rr = sr + q * AS, wk = rr & 3;
+                const int4 wv = wins[ch & 1][rr >> 2];
+                const int ang = (wk == 0 || wk == 3) ? wv.x : wv.y;
+                const int lo = wk < 2 ? wv.z : wv.w;
+                const int k = (wk == 1 || wk == 3) ? nd - 1 - lo - sb : lo + sb;
+                const bool ok = ang >= 0 && sb < kwin && (unsigned)k < (unsigned)nd;
+                const int vo = ok ? (ang * nd + k) * 4 : kBufOOB;
+                buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+            }
+        };
+        __syncthreads();                  // LDS of the previous work item fully consumed
+        pair_setup(ch0);
+        __syncthreads();
+        load_chunk(ch0);
+        double acc_m[VPT], acc_d[VPT], mir_m[VPT], mir_d[VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { acc_m[q] = 0.0; acc_d[q] = 0.0; mir_m[q] = 0.0; mir_d[q] = 0.0; }
+        const float fil = (float)il, fjl = (float)jl;
+        for (int ch = ch0; ch < ch1; ++ch) {
+            __syncthreads();                           // previous chunk fully consumed
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) {
+                // the next bin of the same window row is held by the next lane (PK divides 64)
+                const int rr = sr + q * AS;
+                const float iw = rec[ch & 1][rr >> 2].w;
+                const float gm = iw * buf[q].x, gd = iw * buf[q].y;
+                float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
+                if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
+                gw[rr * PK + sb] = make_float4(gm, gd, nm, nd1);
+            }
+            if (ch + 1 < ch1) pair_setup(ch + 1);
+            __syncthreads();
+            if (ch + 1 < ch1) load_chunk(ch + 1);      // in flight during this chunk
+            const int cb = ch & 1;
+            float am[VPT], ad[VPT], bm[VPT], bd[VPT];
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { am[q] = 0.f; ad[q] = 0.f; bm[q] = 0.f; bd[q] = 0.f; }
+#pragma unroll 2
+            for (int pp = 0; pp < AC; ++pp) {
+                const float4 r1 = rec[cb][pp];
+                const float2 r2 = rec2[cb][pp];
+                const float uu0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
+                const float us0 = fmaf(fil, -r1.x, fmaf(fjl, r1.y, r2.x));
+                const float4* row = gw + pp * 4 * PK;
+                float4 g0[VPT], g1[VPT], g2[VPT], g3[VPT];
+                float fu[VPT], fs[VPT];
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const float uu = q == 0 ? uu0 : fmaf((float)(q * JS), r1.y, uu0);
+                    const float us = q == 0 ? us0 : fmaf((float)(q * JS), r1.y, us0);
+                    fu[q] = __builtin_amdgcn_fractf(uu);
+                    fs[q] = __builtin_amdgcn_fractf(us);
+                    const int ku = (int)uu, ks = (int)us;
+                    g0[q] = row[ku];
+                    g1[q] = row[PK + ku];
+                    g2[q] = row[2 * PK + ks];
+                    g3[q] = row[3 * PK + ks];
+                }
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const float u0 = __builtin_amdgcn_fmed3f(fmaf(-fu[q], r1.w, 1.f), 0.f, 1.f);
+                    const float u1 = __builtin_amdgcn_fmed3f(fmaf(fu[q], r1.w, r2.y), 0.f, 1.f);
+                    const float s0 = __builtin_amdgcn_fmed3f(fmaf(-fs[q], r1.w, 1.f), 0.f, 1.f);
+                    const float s1 = __builtin_amdgcn_fmed3f(fmaf(fs[q], r1.w, r2.y), 0.f, 1.f);
+                    am[q] = fmaf(u0, g0[q].x, fmaf(u1, g0[q].z, am[q]));
+                    ad[q] = fmaf(u0, g0[q].y, fmaf(u1, g0[q].w, ad[q]));
+                    bm[q] = fmaf(u0, g1[q].x, fmaf(u1, g1[q].z, bm[q]));
+                    bd[q] = fmaf(u0, g1[q].y, fmaf(u1, g1[q].w, bd[q]));
+                    am[q] = fmaf(s0, g2[q].x, fmaf(s1, g2[q].z, am[q]));
+                    ad[q] = fmaf(s0, g2[q].y, fmaf(s1, g2[q].w, ad[q]));
+                    bm[q] = fmaf(s0, g3[q].x, fmaf(s1, g3[q].z, bm[q]));
+                    bd[q] = fmaf(s0, g3[q].y, fmaf(s1, g3[q].w, bd[q]));
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {        // chunk sums combined in FP64
+                acc_m[q] += (double)am[q];
+                acc_d[q] += (double)ad[q];
+                mir_m[q] += (double)bm[q];
+                mir_d[q] += (double)bd[q];
+            }
+        }
+        const int i = i0 + il;
+        const size_t nn = (size_t)n * n;
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int j = j0 + jl + q * JS, jm = n - 1 - j;
+            const bool wr = i < n && 2 * j <= n - 1;
+            const bool wrm = i < n && 2 * j < n - 1;
+            const size_t o = (size_t)j * n + i, om = (size_t)jm * n + i;
+            if (G > 1) {
+                double* part = d.bp_part + (size_t)gs * 2 * nn;
+                if (wr) { part[o] = acc_m[q]; part[nn + o] = acc_d[q]; }
+                if (wrm) { part[om] = mir_m[q]; part[nn + om] = mir_d[q]; }
+                continue;
+            }
+            if (wr) {
+                double vm = acc_m[q], vd = acc_d[q];
+                if (add_reg) {
+                    vm = fma(d.reg_mu, (double)d.x[o], vm);
+                    vd = fma(d.reg_de, (double)d.x[nn + o], vd);
+                }
+                d.g[o] = (float)vm;
+                d.g[nn + o] = (float)vd;
+            }
+            if (wrm) {
+                double vm = mir_m[q], vd = mir_d[q];
+                if (add_reg) {
+                    vm = fma(d.reg_mu, (double)d.x[om], vm);
+                    vd = fma(d.reg_de, (double)d.x[nn + om], vd);
+                }
+                d.g[om] = (float)vm;
+                d.g[nn + om] = (float)vd;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------ registry
 // Projector variants (A angles x W detectors threads, R rows per strip, PW staged entries per
 // row, DUP = duplicated 16-byte entries).
@@ -553,16 +770,22 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     X(24, 8, 64, 12, 128, 1, 128, 1)    \
     X(25, 8, 64, 16, 128, 1, 128, 1)
 
-// Adjoint variants (TX x TY voxel tile, AC angles per chunk, VPT voxels per thread).
-#define EIT_ADJ_VARIANTS(X) \
-    X(0, 16, 16, 32, 1)     \
-    X(1, 16, 16, 32, 2)     \
-    X(2, 32, 16, 32, 2)     \
-    X(3, 32, 32, 32, 4)     \
-    X(4, 16, 32, 32, 2)     \
-    X(5, 16, 16, 64, 1)     \
-    X(6, 32, 32, 16, 4)     \
-    X(7, 32, 16, 32, 4)
+// Adjoint variants (TX x TY voxel tile, AC angles per chunk -- angle pairs with MIR = 1 --,
+// VPT voxels per thread, MIR = 1: mirror-pair kernel).
+#define EIT_ADJ_VARIANTS(X)    \
+    X(0, 16, 16, 32, 1, 0)     \
+    X(1, 16, 16, 32, 2, 0)     \
+    X(2, 32, 16, 32, 2, 0)     \
+    X(3, 32, 32, 32, 4, 0)     \
+    X(4, 16, 32, 32, 2, 0)     \
+    X(5, 16, 16, 64, 1, 0)     \
+    X(6, 32, 32, 16, 4, 0)     \
+    X(7, 32, 16, 32, 4, 0)     \
+    X(8, 32, 32, 8, 2, 1)      \
+    X(9, 16, 16, 8, 1, 1)      \
+    X(10, 32, 16, 8, 2, 1)     \
+    X(11, 16, 32, 8, 2, 1)     \
+    X(12, 32, 32, 16, 2, 1)
 
 int proj_variant_count() {
     int c = 0;
@@ -579,7 +802,7 @@ ProjTile proj_variant(int v) {
     return ProjTile{0, 0, 0, 0, 0, 0, 0};
 }
 int adj_pitch_limit(int v) {
-#define X(id, TX, TY, AC, VPT) \
+#define X(id, TX, TY, AC, VPT, MIR) \
     if (v == id) return adj_pitch_max<TX, TY>();
     EIT_ADJ_VARIANTS(X)
 #undef X
@@ -587,17 +810,17 @@ int adj_pitch_limit(int v) {
 }
 int adj_variant_count() {
     int c = 0;
-#define X(id, TX, TY, AC, VPT) ++c;
+#define X(id, TX, TY, AC, VPT, MIR) ++c;
     EIT_ADJ_VARIANTS(X)
 #undef X
     return c;
 }
 AdjTile adj_variant(int v) {
-#define X(id, TX, TY, AC, VPT) \
-    if (v == id) return AdjTile{TX, TY, AC, VPT};
+#define X(id, TX, TY, AC, VPT, MIR) \
+    if (v == id) return AdjTile{TX, TY, AC, VPT, MIR};
     EIT_ADJ_VARIANTS(X)
 #undef X
-    return AdjTile{0, 0, 0};
+    return AdjTile{0, 0, 0, 0, 0};
 }
 
 hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, int grid,
@@ -636,10 +859,14 @@ hipError_t launch_cost_reduce(const SliceDesc* D, int n_slices, hipStream_t s) {
 hipError_t launch_backproject(int variant, const SliceDesc* D, const Item* items, int n_items,
                               int grid, int add_reg, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, TX, TY, AC, VPT)                                                            \
+#define X(id, TX, TY, AC, VPT, MIR)                                                       \
     if (variant == id) {                                                                  \
-        k_backproject<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(D, items, n_items,  \
-                                                                     add_reg);            \
+        if constexpr (MIR != 0)                                                           \
+            k_backproject_pair<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(           \
+                D, items, n_items, add_reg);                                              \
+        else                                                                              \
+            k_backproject<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(D, items,       \
+                                                                         n_items, add_reg); \
         return hipGetLastError();                                                         \
     }
     EIT_ADJ_VARIANTS(X)

@@ -81,14 +81,14 @@ def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, adj_sp
         pa = np.zeros(6 * geo.n_theta)
         gr = np.zeros(info.n_groups * info.proj_a, dtype=np.int32)
         wl = np.zeros(info.n_groups * info.n_dblk * info.n_strips, dtype=np.int32)
-        aa = np.zeros(8 * geo.n_theta)
+        aa = np.zeros(10 * geo.n_theta)
         L.check(L.lib().eit_plan_inspect(C.byref(dims), C.byref(setup), C.byref(til), C.byref(info),
                                          L.dptr(pa), gr.ctypes.data_as(L.IP), wl.ctypes.data_as(L.IP),
                                          L.dptr(aa)))
         out["proj_angles"] = pa.reshape(-1, 6)
         out["groups"] = gr.reshape(info.n_groups, info.proj_a)
         out["win_lo"] = wl.reshape(info.n_groups, info.n_dblk, info.n_strips)
-        out["adj_angles"] = aa.reshape(-1, 8)
+        out["adj_angles"] = aa.reshape(-1, 10)
     del keep
     return out
 
@@ -96,7 +96,8 @@ def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, adj_sp
 def variants(kind: int):
     """Tile shapes of the compiled variants: projector (kind 0) as (angles per group,
     detectors per block, rows per strip, duplicated 16-byte LDS entries 0/1); adjoint
-    (kind 1) as (tile x, tile y, angles per chunk, voxels per thread)."""
+    (kind 1) as (tile x, tile y, angles -- or angle pairs -- per chunk, voxels per thread,
+    mirror-pair kernel 0/1)."""
     n = L.lib().eit_variant_info(kind, -1, None, None, None, None)
     out = []
     for v in range(n):
@@ -107,7 +108,9 @@ def variants(kind: int):
             L.lib().eit_variant_info(2, v, C.byref(dup), None, None, None)
             out.append((a.value, b.value, c.value, dup.value))
         else:
-            out.append((a.value, b.value, c.value, e.value))
+            mir = C.c_int32()
+            L.lib().eit_variant_info(3, v, C.byref(mir), None, None, None)
+            out.append((a.value, b.value, c.value, e.value, mir.value))
     return out
 
 

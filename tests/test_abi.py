@@ -94,8 +94,9 @@ def test_variant_registry():
     assert len(pv) >= 3 and len(av) >= 3
     for a, w, r, dup in pv:
         assert a * w <= 1024 and w % 64 == 0 and dup in (0, 1)
-    for tx, ty, ac, vpt in av:
-        assert tx * ty // vpt <= 1024 and (tx * ty // vpt) % 64 == 0
+    for tx, ty, ac, vpt, mir in av:
+        assert tx * ty // vpt <= 1024 and (tx * ty // vpt) % 64 == 0 and mir in (0, 1)
+    assert {v[4] for v in av} == {0, 1}
 
 
 def f32(v):
@@ -150,13 +151,25 @@ def check_projector_bounds(g, pv):
 
 def check_adjoint_bounds(g, av, vpt):
     """Emulates the adjoint's tile origin (FP64) and per-voxel FP32 FMAs (including the
-    row offsets of a thread's extra voxels) and checks bins stay in [0, kwin - 2]."""
+    row offsets of a thread's extra voxels) and checks bins stay in [0, kwin - 2]. The
+    mirror-pair kernel evaluates a second coordinate per voxel, in the mirror frame (cos
+    negated, offset cd_s), for the tiles of the top half; both are replayed."""
     info = ops.inspect(g, adj_variant=av, tables=True)
     TX, TY, kwin = info["adj_tx"], info["adj_ty"], info["kwin"]
     assert kwin <= info["kwin_pitch_limit"]
-    JS = TY // vpt
+    if info["adj_mirror"]:
+        assert info["n_ty"] * TY >= (g.n + 1) // 2
+        aa = info["adj_angles"]
+        _adjoint_frame_bounds(info, vpt, aa[:, 0], aa[:, 1], aa[:, 2], aa[:, 3], aa[:, 4])
+        _adjoint_frame_bounds(info, vpt, -aa[:, 0], aa[:, 1], aa[:, 8], -aa[:, 3], aa[:, 4])
+        return
     aa = info["adj_angles"]
-    cs, sn, cd, csf, snf = (aa[:, q] for q in range(5))
+    _adjoint_frame_bounds(info, vpt, *(aa[:, q] for q in range(5)))
+
+
+def _adjoint_frame_bounds(info, vpt, cs, sn, cd, csf, snf):
+    TX, TY, kwin = info["adj_tx"], info["adj_ty"], info["kwin"]
+    JS = TY // vpt
     i0 = (np.arange(info["n_tx"]) * TX).astype(np.float64)
     j0 = (np.arange(info["n_ty"]) * TY).astype(np.float64)
     I0, J0 = np.meshgrid(i0, j0, indexing="xy")
@@ -186,7 +199,7 @@ SHAPES = [configs.SMALL_64, configs.SLICE_512, configs.SLICE_1024,
 def _all_variants(g):
     ok = [check_projector_bounds(g, pv) for pv in range(len(ops.variants(0)))]
     assert ok[ops.inspect(g)["proj_variant"]]        # the default variant must apply
-    for av, (tx, ty, ac, vpt) in enumerate(ops.variants(1)):
+    for av, (tx, ty, ac, vpt, mir) in enumerate(ops.variants(1)):
         check_adjoint_bounds(g, av, vpt)
 
 
@@ -209,6 +222,46 @@ def test_row_flags_match_oracle_rule():
     info = ops.inspect(g, tables=True)
     src = info["proj_angles"][:, 5]
     assert np.array_equal(src == 0, radon.row_flags(g.theta))
+
+
+def _mirror_variant():
+    return next(v for v, t in enumerate(ops.variants(1)) if t[4])
+
+
+def test_mirror_pairs():
+    """Angle pairing of the mirror-pair adjoint: for a*pi/N_theta every a in 1 .. N/2 - 1 pairs
+    with N - a, while 0 and pi/2 (its own mirror) stay unpaired; for any angle list every pair
+    satisfies cos b = -cos a, sin b = sin a, every angle sits in exactly one pair slot, and
+    the pair count and chunk split follow."""
+    mv = _mirror_variant()
+    g = geo_for(configs.SLICE_512)
+    info = ops.inspect(g, adj_variant=mv, tables=True)
+    mate = info["adj_angles"][:, 9].astype(int)
+    nt = g.n_theta
+    assert info["adj_mirror"] == 1 and info["n_pairs"] == nt // 2 + 1
+    assert mate[0] == -1 and mate[nt // 2] == -1
+    assert all(mate[a] == nt - a for a in range(1, nt // 2))
+    assert all(mate[a] == -2 for a in range(nt // 2 + 1, nt))
+    # the unpaired kernel reports no pairs
+    assert ops.inspect(g, adj_variant=3, tables=True)["n_pairs"] == 0
+    rng = np.random.default_rng(3)
+    base = rng.uniform(0, np.pi, 40)
+    for theta in (np.sort(rng.uniform(-np.pi, 2 * np.pi, 50)),       # no mirrors
+                  np.concatenate([base, np.pi - base[:25], [0.0, np.pi / 2, np.pi]])):
+        gg = geo_for(configs.SliceConfig(n=66, n_theta=len(theta), n_det=70, n_mask=4))
+        gg.theta = theta
+        inf = ops.inspect(gg, adj_variant=mv, tables=True)
+        m = inf["adj_angles"][:, 9].astype(int)
+        firsts = [a for a in range(len(theta)) if m[a] != -2]
+        assert inf["n_pairs"] == len(firsts)
+        seconds = [m[a] for a in firsts if m[a] >= 0]
+        assert sorted(firsts + seconds) == list(range(len(theta)))
+        for a in firsts:
+            if m[a] >= 0:
+                assert m[a] > a
+                assert abs(np.cos(theta[m[a]]) + np.cos(theta[a])) < 1e-12
+                assert abs(np.sin(theta[m[a]]) - np.sin(theta[a])) < 1e-12
+    assert inf["n_pairs"] == 40 + 25 - 25 + 2            # 25 mirrored, 0 with pi, pi/2 alone
 
 
 def test_adjoint_split_choice():
