@@ -95,7 +95,7 @@ def time_to_tol(plan, s_exp, cfg, extra_seeds, log):
     """Warm-start comparison on this slice plus held-out random slices (medians)."""
     import numpy as np
     import torch
-    from paper_2202_08627_amd import ops, warmstart as WS
+    from paper_2202_08627_amd import autotune, ops, warmstart as WS
     net = WS.load_net(WEIGHTS)
     recs = []
     r = WS.evaluate_case(plan, s_exp, net, cfg, tol=1e-3)
@@ -104,7 +104,8 @@ def time_to_tol(plan, s_exp, cfg, extra_seeds, log):
     wcfg = WS.slice_config(cfg.n, cfg.n_theta, cfg.n_mask)
     for seed in extra_seeds:
         _, s, g = WS._make_case((wcfg, seed))
-        p = ops.Plan(WS._geometry(wcfg, g))
+        geo = WS._geometry(wcfg, g)
+        p = ops.Plan(geo, *autotune.tiling_for(geo))
         r = WS.evaluate_case(p, torch.tensor(s, device="cuda"), net, wcfg, tol=1e-3)
         r["slice"] = f"random ellipses, seed {seed}"
         recs.append(r)

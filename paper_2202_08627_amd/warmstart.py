@@ -22,7 +22,7 @@ from concurrent.futures import ProcessPoolExecutor
 import numpy as np
 import torch
 
-from . import configs, ops, synth
+from . import autotune, configs, ops, synth
 from .unet import UNet
 
 
@@ -369,7 +369,8 @@ def _main():
                           (c.theta, c.mask_pos, c.flat_amp, c.flat_ctr, c.flat_sigma)))
         recs = []
         for cf, seed, sx, g in cases:
-            plan = ops.Plan(_geometry(cf, g))
+            geo = _geometry(cf, g)
+            plan = ops.Plan(geo, *autotune.tiling_for(geo))
             r = evaluate_case(plan, torch.tensor(sx, device="cuda"), net, cf, tol=a.tol)
             r["seed"] = seed
             recs.append(r)
