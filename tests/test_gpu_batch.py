@@ -38,16 +38,19 @@ def _cases():
     return [synth.make_case(c, seed=i + 3) for i, c in enumerate(cfgs)]
 
 
-# (projector variant, adjoint variant, adjoint angle split); slices 1 and 3 split their
-# adjoint over 2 and 3 blocks per voxel tile
+# (projector variant, adjoint variant, adjoint angle split) per slice. First set: slices 1
+# and 3 split their adjoint over 2 and 3 blocks per voxel tile. Second set: interleaved-ray
+# projectors and mirror-pair adjoints (split and unsplit), the kinds the tuned size classes use.
 VARIANTS = [(-1, -1, 0), (1, 1, 2), (7, 5, 1), (8, 0, 3), (0, 2, 1)]
+VARIANTS_IL_MIRROR = [(22, 12, 2), (23, 8, 1), (24, 9, 3), (25, 11, 2), (18, 10, 1)]
 
 
-def test_batch_equals_single_slice_runs(ops):
-    print("batch vs single", flush=True)
+@pytest.mark.parametrize("variants", [VARIANTS, VARIANTS_IL_MIRROR], ids=["mixed", "il-mirror"])
+def test_batch_equals_single_slice_runs(ops, variants):
+    print("batch vs single", variants, flush=True)
     cases = _cases()
     plans = [ops.Plan.from_case(c, proj_variant=pv, adj_variant=av, adj_splits=g)
-             for c, (pv, av, g) in zip(cases, VARIANTS)]
+             for c, (pv, av, g) in zip(cases, variants)]
     s = [dev(c.s_exp) for c in cases]
     kw = dict(iters=20, lam=1e-2, mu_scale=0.05, delta_scale=1e-3)
     xs, reps = ops.reconstruct_batch(plans, s, **kw)
