@@ -21,6 +21,10 @@ Printed as one JSON line. Extra keys:
   time_to_tol   iterations and wall time to 1e-3 relative L2 (the larger over the two maps)
                 of the plain run's converged solution, per start, on this slice and three held-out
                 random-ellipse 512^2 slices (learned start: committed trained weights, guard on).
+
+Other workloads (`--workload`): batch256 (256 independent slices of mixed size),
+unet_train / unet_infer (the warm-start network), autograd1024 (cost and gradient through the
+autograd node at 1024^2, 1800 angles, M = 12).
 """
 from __future__ import annotations
 
@@ -252,12 +256,81 @@ def unet_main(args, log, train):
     return 0
 
 
+def autograd_main(args, log):
+    """Differentiation workload: S(x) and its gradient through the autograd node EITCost at
+    1024^2, 1800 angles, 1024 detector pixels, M = 12 (forward: projections and IC model;
+    backward: recomputed projections, IC seeds and the adjoint), plus the projector and
+    adjoint launches timed alone on the same plan."""
+    import torch
+    from paper_2202_08627_amd import _lib, autotune, configs, ops, synth
+    cfg = configs.SLICE_1024
+    log(f"# building inputs {cfg.n}^2 x {cfg.n_theta} x {cfg.n_det} x M={cfg.n_mask}")
+    case = synth.make_case(cfg)
+    torch.cuda.set_device(0)
+    geo = ops.Geometry.from_case(case)
+    tiling = autotune.tiling_for(geo)
+    plan = ops.Plan(geo, *tiling)
+    s_exp = torch.as_tensor(case.s_exp, device="cuda")
+    x = torch.as_tensor((0.9 * case.x_true).astype("float32"), device="cuda").requires_grad_()
+
+    def step():
+        x.grad = None
+        ops.eit_cost(x, s_exp, plan, cfg.lam_mu, cfg.lam_delta).backward()
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+
+    def kernel_ms(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+    xd = x.detach()
+    sino = torch.empty(plan.sino_shape, device="cuda")
+    out = torch.empty(plan.x_shape, device="cuda")
+    wsp = plan.workspace(_lib.EIT_OP_PROJECT)
+    wsb = plan.workspace(_lib.EIT_OP_BACKPROJECT)
+    ms_p = kernel_ms(lambda: plan.project(xd, out=sino, ws=wsp))
+    ms_b = kernel_ms(lambda: plan.backproject(sino, out=out, ws=wsb))
+    units = float(cfg.n) * cfg.n_theta * cfg.n_det
+    fp = FLOPS_PER_SAMPLE * units / (ms_p * 1e-3) / 1e12
+    fb = FLOPS_PER_VOXEL_ANGLE * float(cfg.n) ** 2 * cfg.n_theta / (ms_b * 1e-3) / 1e12
+    line = {
+        "metric": "autograd cost+gradient evaluations/s (1024^2, 1800 angles)",
+        "value": round(1.0 / t, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "autograd_1024: EITCost forward + backward, 1024x1024 slice, "
+                               "1800 angles over 180 deg, 1024 detector pixels, 12 mask positions",
+                   "tiling": {"proj_variant": tiling[0], "adj_variant": tiling[1],
+                              "adj_splits": tiling[2]}},
+        "roofline": {"bound": "alu", "kernel": "k_project (call incl. launch)",
+                     "achieved": round(fp, 3), "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": round(fp / 157.3, 4), "traffic": None,
+                     "project_call_ms": round(ms_p, 4), "backproject_call_ms": round(ms_b, 4),
+                     "backproject_tflops": round(fb, 3)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["slice512", "batch256", "unet_train", "unet_infer"],
+    ap.add_argument("--workload", choices=["slice512", "batch256", "unet_train", "unet_infer",
+                                           "autograd1024"],
                     default="slice512",
                     help="slice512 (default): the headline slice; batch256: 256 mixed slices; "
-                         "unet_train / unet_infer: the warm-start network")
+                         "unet_train / unet_infer: the warm-start network; autograd1024: "
+                         "cost and gradient through the autograd node at 1024^2")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
@@ -284,6 +357,8 @@ def main():
         return batch_main(args, log)
     if args.workload in ("unet_train", "unet_infer"):
         return unet_main(args, log, args.workload == "unet_train")
+    if args.workload == "autograd1024":
+        return autograd_main(args, log)
 
     child = None
     if not args.no_cpu_baseline:
