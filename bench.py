@@ -345,7 +345,7 @@ def main():
         cpu_baseline_child(args.cpu_evals)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs one slice problem per GPU and "
+        print("bench.py measures one GPU only: the library runs one slice problem per GPU and "
               "has no multi-GPU path (slices shard across GPUs without communication).",
               file=sys.stderr)
         return 2
