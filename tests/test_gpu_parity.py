@@ -482,3 +482,22 @@ def test_mirror_adjoint_in_gradient_and_reconstruction(ops):
     X = host(xr)
     assert rel_l2(X[0], xo[0]) < 1e-3 and rel_l2(X[1], xo[1]) < 1e-3
     assert np.allclose(host(hist)[1:], tr.cost, rtol=1e-4)
+
+
+def test_mirror_adjoint_degenerate_shapes(ops):
+    """The mirror-pair adjoint at the smallest sizes: maps of 2, 3 and 5 voxels (the middle
+    row of the odd ones is its own mirror) with one angle, with 0 and pi/2 (both their own
+    mirrors) and with one mirrored pair, against the oracle."""
+    rng = np.random.default_rng(14)
+    for n in (2, 3, 5):
+        for theta in (np.array([0.4]), np.array([0.0, np.pi / 2]), np.array([0.3, np.pi - 0.3])):
+            cfg = tiny_cfg(n=n, n_theta=len(theta), n_det=n + 1, n_mask=3)
+            c = synth.make_case(cfg)
+            geo = ops.Geometry.from_case(c)
+            geo.theta = theta
+            y = rng.standard_normal((2, len(theta), cfg.n_det)).astype(np.float32).astype(np.float64)
+            ref = np.stack([oradon.backproject(y[q], theta, n) for q in range(2)])
+            for v in _mirror_variants(ops):
+                say("mirror adjoint degenerate", n, len(theta), v)
+                plan = ops.Plan(geo, adj_variant=v)
+                assert rel_l2(host(plan.backproject(dev(y))), ref) < 1e-5, (n, theta, v)
