@@ -264,6 +264,19 @@ def test_mirror_pairs():
     assert inf["n_pairs"] == 40 + 25 - 25 + 2            # 25 mirrored, 0 with pi, pi/2 alone
 
 
+def test_mirror_pairs_duplicates_and_wrapped_angles():
+    """Repeated angles pair one to one in order of appearance; angles given outside
+    [0, pi) pair by their cosine and sine (pi + a and -a mirror each other); a lone copy stays
+    unpaired."""
+    mv = _mirror_variant()
+    th = np.array([0.5, 0.5, np.pi - 0.5, np.pi - 0.5, np.pi - 0.5, np.pi + 0.2, -0.2 + 0.0, 1.0])
+    g = geo_for(configs.SliceConfig(n=34, n_theta=len(th), n_det=36, n_mask=3))
+    g.theta = th
+    m = ops.inspect(g, adj_variant=mv, tables=True)["adj_angles"][:, 9].astype(int)
+    # pi + 0.2 has cos = -cos(0.2), sin = -sin(0.2) = sin(-0.2) with cos(-0.2) = cos(0.2)
+    assert list(m) == [2, 3, -2, -2, -1, 6, -2, -1]
+
+
 def test_adjoint_split_choice():
     """Adjoint angle split as the plan reports it: automatic (doubled while the launch has
     under 1024 blocks and each part keeps two angle chunks), explicit (clamped to the chunk
