@@ -284,6 +284,29 @@ def test_large_slice_sampled_backprojection(ops):
         assert rel_l2(B[q], ref) < 1e-5
 
 
+def test_768_slice_sampled_parity_in_tuned_configuration(ops):
+    """The batch's 768^2 / 1080-angle class in its tuned launch shape (autotuner cache):
+    projections of the phantom on 16 sampled angles and the backprojection of a sinogram that
+    is non-zero on 16 sampled angles, against the oracle."""
+    from paper_2202_08627_amd import autotune
+    cfg = configs.SliceConfig(n=768, n_theta=1080, n_det=768, n_mask=8, mu_scale=configs.mu_range_for(768))
+    c = synth.make_case(cfg)
+    say("768 sampled parity", autotune.tiling_for(ops.Geometry.from_case(c)))
+    plan = _bench_plan(ops, c)
+    sel = np.unique(np.concatenate([np.linspace(0, cfg.n_theta - 1, 12).astype(int),
+                                    [0, 270, 540, 810]]))
+    P = host(plan.project(dev(c.x_true)))
+    x32 = c.x_true.astype(np.float32).astype(np.float64)
+    for q in range(2):
+        assert rel_l2(P[q, sel], oradon.project(x32[q], c.theta[sel], cfg.n_det)) < 1e-5
+    rng = np.random.default_rng(9)
+    y = np.zeros((2, cfg.n_theta, cfg.n_det))
+    y[:, sel] = rng.standard_normal((2, sel.size, cfg.n_det)).astype(np.float32)
+    B = host(plan.backproject(dev(y)))
+    for q in range(2):
+        assert rel_l2(B[q], oradon.backproject(y[q, sel], c.theta[sel], cfg.n)) < 1e-5
+
+
 def test_large_slice_reconstruction_in_bench_configuration(ops):
     """The benchmark's run (512^2 / 720 / M = 8, autotuned tiles, captured graphs), 20
     iterations: the cost history never rises, and at the returned x_20 (non-zero up to the
