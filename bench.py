@@ -420,6 +420,26 @@ def main():
         traffic = tr["bytes"]
     units = float(n) * nt * nd if dom == "project" else float(n) * n * nt
     lds_bytes = 16.0 * units                   # one 16-byte read of both neighbours per unit
+    # kernels whose roofline is HBM: algorithmic bytes per launch and the achieved rate.
+    #   ic: projections in, IC data in, seeds out;
+    #   lb_update (accepted trials): trial point, gradient (FP64 partial planes when the adjoint
+    #     is split), iterate and gradient, the m history pairs in; new pair, iterate, gradient out;
+    #   lb_direction: new direction (gradient, iterate and the m pairs in; direction, trial
+    #     point and its transpose out) or backtrack (direction and iterate in; trial point and
+    #     its transpose out), weighted by how often each ran.
+    nv = 2.0 * n * n
+    mh = kw["m"]
+    G = info["adj_splits"]
+    b_ic = 4.0 * nt * nd * (4 + cfg.n_mask)
+    b_up = nv * (4 + (8 * G if G > 1 else 4) + 8 + 8 * mh + 16)
+    b_new, b_bt = nv * (4 + 4 + 8 * mh + 12), nv * (4 + 4 + 12)
+    b_dir = (accepted * b_new + max(evals - accepted, 0) * b_bt) / evals
+    hbm_kernels = {}
+    for k, b, launches in (("ic", b_ic, evals), ("update", b_up, accepted), ("direction", b_dir, evals)):
+        ms_k = prep["phase_ms"][k] / launches
+        gbs = b / (ms_k * 1e-3) / 1e9
+        hbm_kernels[k] = {"launch_us": round(ms_k * 1e3, 2), "alg_bytes": round(b),
+                          "GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
     roof = {
         "bound": "alu", "kernel": kname,
         "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -432,6 +452,7 @@ def main():
         "other_kernel": {k: {"launch_us": round(v[1] * 1e3, 2),
                              "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3)} for k, v in kern.items() if k != dom},
         "phase_ms_per_iter": {k: round(v / max(prep["iters"], 1), 5) for k, v in prep["phase_ms"].items()},
+        "hbm_kernels": hbm_kernels,
         "tiling": {"proj_variant": info["proj_variant"], "adj_variant": info["adj_variant"],
                    "adj_splits": info["adj_splits"]},
     }
@@ -471,7 +492,8 @@ def main():
                                "slice, 720 angles over 180 deg, 512 detector pixels, 8 mask positions, "
                                "Shepp-Logan-style phantom, Poisson 1e4 counts, from zero",
                    "n": n, "n_theta": nt, "n_det": nd, "n_mask": cfg.n_mask,
-                   "iterations": args.steps, "evals": rep["evals"], "final_cost": rep["cost"]},
+                   "iterations": args.steps, "evals": rep["evals"],
+                   "evals_per_s": round(rep["evals"] / t, 1), "final_cost": rep["cost"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
