@@ -29,8 +29,16 @@ class Opts:
     tol_rel_step: float = 0.0
 
 
+def clear_plans() -> None:
+    """Releases the cached plans (their device tables) of every geometry seen so far."""
+    for p in _plans.values():
+        p.close()
+    _plans.clear()
+
+
 def plan_for(case) -> ops.Plan:
-    """The case's plan with the autotuned tiles; one per geometry, kept for reuse."""
+    """The case's plan with the autotuned tiles; one per geometry, kept for reuse until
+    `clear_plans`."""
     c = case.cfg
     key = (c.n, c.n_theta, c.n_det, c.n_mask, float(c.kappa),
            np.asarray(case.theta, np.float64).tobytes(), np.asarray(case.mask_pos, np.float64).tobytes(),

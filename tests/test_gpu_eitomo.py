@@ -81,3 +81,5 @@ def test_warmstart_without_network(E):
     x0 = torch.zeros_like(x) if choice == "zero" else E.plan_for(c).single_shot(dev(c.s_exp))
     x1, _ = E.reconstruct(c, o, x0=x0)
     assert torch.equal(x, x1)
+    E.clear_plans()
+    assert not E._plans
