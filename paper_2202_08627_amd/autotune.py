@@ -42,11 +42,35 @@ def load_cache(path: str = DEFAULT_CACHE) -> dict:
     return {}
 
 
+def _fits(geo, pv: int, av: int, ag: int) -> bool:
+    """Whether the library accepts these tiles for this geometry (host-only check)."""
+    try:
+        ops.inspect(geo, pv, av, ag)
+        return True
+    except L.EitError:
+        return False
+
+
 def tiling_for(geo, path: str = DEFAULT_CACHE):
+    """Cached tiles of the geometry's size class, checked against this geometry's angle list.
+    The cache is keyed by size only; a variant tuned on angles over 180 degrees can be too
+    narrow for other angle lists (over 360 degrees, irregular), whose projector windows are
+    wider. Then the next fastest timed variant that fits is taken (the cache keeps every
+    variant's time), and the library's default if none does."""
     ent = load_cache(path).get(size_key(geo))
     if not ent:
         return -1, -1, 0
-    return int(ent["proj_variant"]), int(ent["adj_variant"]), int(ent.get("adj_splits", 1))
+    pv, av, ag = int(ent["proj_variant"]), int(ent["adj_variant"]), int(ent.get("adj_splits", 1))
+    if _fits(geo, pv, av, ag):
+        return pv, av, ag
+    projs = [pv] + [int(k) for k, _ in sorted(ent.get("proj_us", {}).items(), key=lambda kv: kv[1])]
+    adjs = [(av, ag)] + [tuple(int(v) for v in k.split("/"))
+                         for k, _ in sorted(ent.get("adj_us", {}).items(), key=lambda kv: kv[1])]
+    p_ok = next((p for p in projs if _fits(geo, p, -1, 0)), -1)
+    a_ok = next((a for a in adjs if _fits(geo, -1, *a)), (-1, 0))
+    if _fits(geo, p_ok, *a_ok):
+        return (p_ok, *a_ok)
+    return -1, -1, 0
 
 
 def _time(fn, reps: int):
