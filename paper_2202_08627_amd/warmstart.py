@@ -184,30 +184,57 @@ def rel_err(x: torch.Tensor, x_ref: torch.Tensor, cfg=None) -> float:
     return float(d.max().cpu())
 
 
+STABILITY_PROBES = (1, 5, 20, 50)
+
+
+def first_stable_crossing(err, e0: float, tol: float, k_max: int, probes=STABILITY_PROBES):
+    """Smallest K with err(K) <= tol after which err stays <= tol at the probe points
+    K + p (p in probes, up to k_max) and at k_max. L-BFGS gives no guarantee that the error
+    falls monotonically, so a bisection alone can land on a crossing that is undone later:
+    when a probe fails, the search restarts above the failing probe.
+    Returns (K or None if err(k_max) > tol, err(K), checks) where checks holds err(K - 1)
+    (> tol, or None for K = 0) and the probe errors."""
+    cache = {0: e0}
+
+    def E(k):
+        if k not in cache:
+            cache[k] = err(k)
+        return cache[k]
+
+    if E(k_max) > tol:
+        return None, cache[k_max], {"k_max": k_max, "err_k_max": cache[k_max]}
+    lo = 0
+    while True:
+        if E(lo) <= tol:
+            k = lo
+        else:
+            a, b = lo, k_max          # E(a) > tol, E(b) <= tol
+            while b - a > 1:
+                mid = (a + b) // 2
+                if E(mid) <= tol:
+                    b = mid
+                else:
+                    a = mid
+            k = b
+        later = sorted({min(k + p, k_max) for p in probes} | {k_max})
+        bad = [q for q in later if E(q) > tol]
+        if not bad:
+            checks = {"err_k_minus_1": E(k - 1) if k > 0 else None,
+                      "probes": {int(q): E(q) for q in later}}
+            return k, E(k), checks
+        lo = bad[-1]
+
+
 def iterations_to_tolerance(plan: ops.Plan, s_exp, x0, x_star, cfg, tol: float = 1e-3,
                             k_max: int = 2000, m: int = 10):
-    """Smallest K with rel_err(x_K, x_star) <= tol, by bisection over K. The device iteration
-    is deterministic, so a run of K iterations is the first K iterations of a longer run.
-    Returns (K or None if not reached by k_max, error at K)."""
+    """Iterations from x0 until rel_err(x_K, x_star) <= tol for good (first_stable_crossing).
+    The device iteration is deterministic, so a run of K iterations is the first K iterations
+    of a longer run. Returns (K or None if not reached by k_max, error at K, checks)."""
     def err(k):
         x, rep, _ = plan.reconstruct(s_exp, x0=x0, iters=k, lam=cfg.lam, mu_scale=cfg.mu_scale,
                                      delta_scale=cfg.delta_scale, m=m)
         return rel_err(x, x_star, cfg)
-    e0 = rel_err(x0, x_star, cfg)
-    if e0 <= tol:
-        return 0, e0
-    e_hi = err(k_max)
-    if e_hi > tol:
-        return None, e_hi
-    lo, hi = 0, k_max            # err(lo) > tol, err(hi) <= tol
-    while hi - lo > 1:
-        mid = (lo + hi) // 2
-        e = err(mid)
-        if e <= tol:
-            hi, e_hi = mid, e
-        else:
-            lo = mid
-    return hi, e_hi
+    return first_stable_crossing(err, rel_err(x0, x_star, cfg), tol, k_max)
 
 
 def time_iterations(plan: ops.Plan, s_exp, x0, k: int, cfg, m: int = 10, reps: int = 3) -> float:
@@ -253,7 +280,7 @@ def evaluate_case(plan: ops.Plan, s_exp, net, cfg, tol: float = 1e-3, k_ref: int
         starts["unet"] = (x0, None, choice)
         out["guard_costs"] = costs
     for name, (x0, t_start, choice) in starts.items():
-        k, e = iterations_to_tolerance(plan, s_exp, x0, x_star, cfg, tol=tol, k_max=k_max, m=m)
+        k, e, checks = iterations_to_tolerance(plan, s_exp, x0, x_star, cfg, tol=tol, k_max=k_max, m=m)
         if t_start is None:
             if name == "single_shot":
                 ts = []
@@ -268,6 +295,7 @@ def evaluate_case(plan: ops.Plan, s_exp, net, cfg, tol: float = 1e-3, k_ref: int
                 t_start = time_warm_start(plan, s_exp, net, cfg, reps)
         t_iter = time_iterations(plan, s_exp, x0, k, cfg, m, reps) if k else 0.0
         out[name] = {"iters": k, "err": e, "err0": rel_err(x0, x_star, cfg), "choice": choice,
+                     "checks": checks,
                      "t_start_s": t_start, "t_iter_s": t_iter,
                      "t_total_s": (t_start + t_iter) if k is not None else None}
     return out

@@ -29,3 +29,40 @@ def test_summary_medians_and_ratios():
     assert s["unet"]["reached"] == 2 and s["unet"]["median_iters"] == 125
     assert s["ratio_time_unet_vs_zero"] == 0.75
     assert s["ratio_iters_unet_vs_zero"] == 0.875
+
+
+def test_stable_crossing_on_a_monotone_error():
+    from paper_2202_08627_amd.warmstart import first_stable_crossing
+    err = lambda k: 1.0 / (1.0 + k)          # <= 1e-2 from k = 99 on
+    k, e, checks = first_stable_crossing(err, 1.0, 1e-2, 500)
+    assert k == 99 and e == err(99)
+    assert checks["err_k_minus_1"] > 1e-2
+    assert all(v <= 1e-2 for v in checks["probes"].values())
+
+
+def test_stable_crossing_skips_a_crossing_that_is_undone():
+    """The error dips below the tolerance at 95-105, rises above it again and stays below from
+    160 on. Bisection over [0, 200] alone evaluates 100 (in the dip), then 50, 75, 87, 93, 96,
+    94, 95 and stops at K = 95, inside the dip. The probes after it (96, 100, 115, 145, 200) see
+    the rise at 115 and 145, so the search restarts above 145 and returns 160."""
+    from paper_2202_08627_amd.warmstart import first_stable_crossing
+    tol = 1e-3
+
+    def err(k):
+        return 0.5 * tol if (95 <= k <= 105 or k >= 160) else 2.0 * tol
+    k, e, checks = first_stable_crossing(err, 1.0, tol, 200)
+    assert k == 160 and checks["err_k_minus_1"] > tol
+    k, e, checks = first_stable_crossing(err, 1.0, tol, 200, probes=())
+    assert k == 95                    # what a bisection without the probes would report
+
+
+def test_stable_crossing_not_reached():
+    from paper_2202_08627_amd.warmstart import first_stable_crossing
+    k, e, checks = first_stable_crossing(lambda k: 1.0, 1.0, 1e-3, 50)
+    assert k is None and e == 1.0
+
+
+def test_stable_crossing_at_zero():
+    from paper_2202_08627_amd.warmstart import first_stable_crossing
+    k, e, checks = first_stable_crossing(lambda k: 1e-4, 1e-4, 1e-3, 50)
+    assert k == 0 and checks["err_k_minus_1"] is None
