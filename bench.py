@@ -16,8 +16,13 @@ Printed as one JSON line. Extra keys:
                 bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
                 plain copy's counts (recorded with the kernel source's hash: null once the
                 source differs);
+  roofline.project_plus_adjoint
+                algorithmic HBM bytes of projector and adjoint (maps and sinograms in and out)
+                over their summed launch time, against 8 TB/s;
   cpu_baseline  the FP64 oracle on this host, single thread, two cost+gradient evaluations
-                of the same slice, scaled to slice-iterations/s;
+                of the same slice, scaled to slice-iterations/s; `host`: one oracle process per
+                host core (at most 16) at the same time, the host's aggregate rate;
+  paper_context the paper's own CPU timings and hardware (context, not a target);
   time_to_tol   iterations and wall time to 1e-3 relative L2 (the larger over the two maps)
                 of the plain run's converged solution, per start, on this slice and three held-out
                 random-ellipse 512^2 slices (learned start: committed trained weights, guard on).
@@ -45,11 +50,16 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (counts packed
 PEAK_FP32_UNPACKED = 78.6     # 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz, one FMA per lane
 PEAK_LDS_TBS = 78.6           # 256 CUs x 128 B/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
-# algorithmic work per unit: projector fused sample (both maps: 2 x (2 mul + 2 add) for the
-# interpolation weights applied to two voxels, plus the strip accumulation) and adjoint
-# voxel-angle pair (both maps, two detector bins each)
-FLOPS_PER_SAMPLE = 12.0
-FLOPS_PER_VOXEL_ANGLE = 18.0
+# Algorithmic work per unit (the useful arithmetic, not the instructions issued):
+#   projector fused sample (one ray, one row, both maps): per map the interpolation
+#     x_c + phi (x_(c+1) - x_c) is one multiply-add on the staged (value, difference) entry and
+#     the ray sum one add: 3 FLOP per map, 6 per sample (about 1.0-1.1 GFLOP per 512^2/720
+#     projection);
+#   adjoint voxel-angle pair (both maps): the two triangle weights of the voxel's two detector
+#     bins (one multiply-add each, 4 FLOP) and per map two multiply-adds of weight and seed
+#     (8 FLOP): 12 FLOP per pair (about 2.3 GFLOP per 512^2/720 backprojection).
+FLOPS_PER_SAMPLE = 6.0
+FLOPS_PER_VOXEL_ANGLE = 12.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2202_08627_amd", "csrc", "kernels.hip")
 WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.npz")
 # HBM bytes per launch at this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
@@ -66,9 +76,42 @@ def _src_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+# The paper's own timings (CPU only; its workload is a 220^2 slice, 400 angles over 360 deg,
+# one mask position, single-map h-mode), quoted beside the measured rates as context.
+PAPER_CONTEXT = {
+    "hardware": "Intel Core i5 at 2.10 GHz workstation, single thread (Radon transform in "
+                "Numba; SciPy L-BFGS-B)",
+    "final_method": "Numba, no ring term, 20 flat scans: 36 iterations in 6.62 % of 219 s = "
+                    "14.5 s for a 220^2 slice, 400 angles, M = 1 (Table 2), i.e. 2.5 slice-iters/s",
+    "per_voxel_angle": "about 20 ns per voxel-angle pair per iteration (14.5 s / 36 / (220^2 x 400))",
+    "extrapolated_to_this_workload": "about 0.26 slice-iters/s at 512^2 x 720 angles at the same "
+                                     "rate per voxel-angle pair (not measured by the paper)",
+    "simulated_total_iteration_time_s": {"N_t = N_theta = 360": 31, "720": 290, "1440": 2700},
+    "full_3d_stack": "220 x 220 x 75 voxels in 23 min, single thread",
+}
+
+
+def cpu_cores():
+    """CPU model and the cores this process may use (at most 16, the host share of one GPU)."""
+    import platform
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return cpu, max(1, min(n, 16))
+
+
 def cpu_baseline_child(n_evals: int):
     """Time the CPU oracle on n_evals cost+gradient evaluations of the benchmark slice."""
-    import platform
     import numpy as np
     from paper_2202_08627_amd import configs, synth
     from oracle import model
@@ -79,20 +122,36 @@ def cpu_baseline_child(n_evals: int):
     prob = model.ScaledProblem(c.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
     rng = np.random.default_rng(0)
     zs = [np.zeros((2, cfg.n, cfg.n))] + [rng.uniform(0, 1, (2, cfg.n, cfg.n)) for _ in range(n_evals - 1)]
+    w0 = time.time()
     t0 = time.perf_counter()
     for z in zs:
         prob(z)
     t = (time.perf_counter() - t0) / len(zs)
-    cpu = platform.processor() or ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    print(json.dumps({"eval_s": t, "n_evals": len(zs), "cores": 1, "cpu": cpu}), flush=True)
+    cpu, _ = cpu_cores()
+    print(json.dumps({"eval_s": t, "n_evals": len(zs), "cores": 1, "cpu": cpu,
+                      "t_start": w0, "t_end": time.time()}), flush=True)
+
+
+def cpu_host_baseline(log):
+    """The oracle on the whole host share: one single-threaded process per core, each running
+    one cost+gradient evaluation of the benchmark slice at the same time (slices are
+    independent, so this is the host's slice throughput). Returns (evaluations/s, cores, cpu,
+    wall seconds) or None."""
+    cpu, p = cpu_cores()
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                               "--cpu-evals", "1"], env=env, stdout=subprocess.PIPE,
+                              stderr=subprocess.PIPE, text=True) for _ in range(p)]
+    res = []
+    for q in procs:
+        out, err = q.communicate(timeout=900)
+        if q.returncode != 0 or not out.strip():
+            log(f"host baseline process failed: {err[-1000:]}")
+            return None
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    # the evaluations overlap; the aggregate rate is evaluations over the span they covered
+    span = max(r["t_end"] for r in res) - min(r["t_start"] for r in res)
+    return p / span, p, cpu, span
 
 
 def time_to_tol(plan, s_exp, cfg, extra_seeds, log):
@@ -336,6 +395,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--no-host-baseline", action="store_true",
+                    help="skip the oracle run on every host core")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain 256 MiB device copy (HBM counter scaling)")
     ap.add_argument("--cpu-evals", type=int, default=2)
@@ -420,6 +481,10 @@ def main():
         traffic = tr["bytes"]
     units = float(n) * nt * nd if dom == "project" else float(n) * n * nt
     lds_bytes = 16.0 * units                   # one 16-byte read of both neighbours per unit
+    # HBM roofline of projector + adjoint together: maps in and sinograms out, seeds in and
+    # gradient out (2.10 + 2.95 + 2.95 + 2.10 MB at 512^2 / 720), over their summed launch time
+    pa_bytes = 4.0 * (2 * n * n + 2 * nt * nd) * 2
+    pa_ms = kern["project"][1] + kern["backproject"][1]
     # kernels whose roofline is HBM: algorithmic bytes per launch and the achieved rate.
     #   ic: projections in, IC data in, seeds out;
     #   lb_update (accepted trials): trial point, gradient (FP64 partial planes when the adjoint
@@ -449,6 +514,11 @@ def main():
         "launch_us": round(ms * 1e3, 2),
         "hbm_alg_bytes": hbm_alg[dom],
         "hbm_frac": round(hbm_alg[dom] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5),
+        "flop_per_unit": FLOPS_PER_SAMPLE if dom == "project" else FLOPS_PER_VOXEL_ANGLE,
+        "units_per_launch": units,
+        "project_plus_adjoint": {"alg_bytes": pa_bytes, "launch_us": round(pa_ms * 1e3, 2),
+                                 "GB/s": round(pa_bytes / (pa_ms * 1e-3) / 1e9, 1),
+                                 "hbm_frac": round(pa_bytes / (pa_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)},
         "other_kernel": {k: {"launch_us": round(v[1] * 1e3, 2),
                              "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3)} for k, v in kern.items() if k != dom},
         "phase_ms_per_iter": {k: round(v / max(prep["iters"], 1), 5) for k, v in prep["phase_ms"].items()},
@@ -480,6 +550,19 @@ def main():
                               f"(zero and a random point) at {cb['eval_s']:.1f} s each on 1 thread "
                               f"({cb['cpu']}); scaled by the {evals_per_iter:.3f} evaluations per "
                               f"iteration of the timed run")}
+            if not args.no_host_baseline:
+                log("# oracle on every host core")
+                hb = cpu_host_baseline(log)
+                if hb:
+                    eps, p, cpu_model, span = hb
+                    cpu["host"] = {"value": round(eps / evals_per_iter, 6), "unit": "slice-iters/s",
+                                   "cores": p, "cpu": cpu_model,
+                                   "sample": (f"{p} single-threaded oracle processes, one FP64 "
+                                              f"cost+gradient evaluation of the slice each, "
+                                              f"overlapping in {span:.1f} s; scaled by the "
+                                              f"{evals_per_iter:.3f} evaluations per iteration"),
+                                   "gpu_over_host": round(value / (eps / evals_per_iter), 1)}
+            cpu["gpu_over_core"] = round(value / cpu["value"], 1)
         else:
             log(f"cpu baseline failed: {err[-2000:]}")
 
@@ -496,6 +579,7 @@ def main():
                    "evals_per_s": round(rep["evals"] / t, 1), "final_cost": rep["cost"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "time_to_tol": ttt,
     }
     print(json.dumps(line), flush=True)

@@ -170,7 +170,12 @@ int eit_project(const eit_plan* plan, const float* x, float* sino, void* ws, siz
                 void* stream);
 
 /* Exact transpose R^T of eit_project's operator (gather form, no atomics):
- * sino device float[2][n_theta][n_det] -> x_out device float[2][n][n]. */
+ * sino device float[2][n_theta][n_det] -> x_out device float[2][n][n].
+ * Theory section: the paper minimises eq. 5 with its analytic gradient; by the chain rule
+ * through eq. 1 and eq. 2 that gradient is R^T applied to the derivatives of the cost with
+ * respect to the projections (the IC residual seeds), which is this operator. It is also the
+ * backprojection of the single-shot route's filtered backprojection (Kak & Slaney, the
+ * paper's Radon reference). Asynchronous; errors as for eit_project. */
 int eit_backproject(const eit_plan* plan, const float* sino, float* x_out, void* ws,
                     size_t ws_bytes, void* stream);
 
@@ -196,12 +201,20 @@ int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, 
 int eit_single_shot(const eit_plan* plan, const float* s_exp, float* x_out, void* ws,
                     size_t ws_bytes, void* stream);
 
-/* Minimise the cost from x (device float[2][n][n], raw units): x holds the start on entry
- * and x_K on return. L-BFGS (memory opts->lbfgs_m, compact representation, FP64 dot
- * products) with Armijo backtracking, entirely device-resident; one accepted step per
- * iteration. Synchronises `stream` at the end and fills *rep (host, may be NULL).
- * cost_hist (device double[max_iter + 1], may be NULL) receives F after the start
- * evaluation and after every accepted iteration. */
+/* Minimise the cost of eq. 5 from x (device float[2][n][n], raw units): x holds the start on
+ * entry and x_K on return. Theory section: the paper minimises eq. 5 with L-BFGS (SciPy's
+ * implementation) using the analytic gradient, and states no settings; here L-BFGS with
+ * memory opts->lbfgs_m (compact representation, FP64 dot products, H_0 = (s.y / y.y) I),
+ * first trial step 1/||g|| from an empty memory and 1 otherwise, Armijo backtracking by
+ * halving (constant opts->c1, at most opts->max_ls_trials trials; when every trial fails the
+ * memory is cleared and the iteration redone along -g, or the run stops with
+ * EIT_ERR_LINESEARCH if the memory was empty), a pair kept only if s.y > 1e-10 |s||y|, entirely
+ * device-resident; one accepted step per iteration. Synchronises `stream` at the end and fills
+ * *rep (host, may be NULL). cost_hist (device double[max_iter + 1], may be NULL) receives F
+ * after the start evaluation and after every accepted iteration. The captured graphs of the
+ * evaluation steps are kept per (plan, workspace address, lbfgs_m) and replayed by later calls
+ * with the same three (at most 16 kept; eit_plan_destroy drops a plan's). Returns
+ * EIT_ERR_NONFINITE if the cost at the start is not finite. */
 int eit_reconstruct(const eit_plan* plan, const float* s_exp, const eit_opts* opts, float* x,
                     double* cost_hist, eit_report* rep, void* ws, size_t ws_bytes, void* stream);
 

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -456,7 +457,15 @@ extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
     return EIT_OK;
 }
 
-extern "C" void eit_plan_destroy(eit_plan* p) { free_plan(p); }
+namespace {
+void purge_graphs(const eit_plan* p);
+}  // namespace
+
+extern "C" void eit_plan_destroy(eit_plan* p) {
+    if (!p) return;
+    purge_graphs(p);
+    free_plan(p);
+}
 
 // ============================================================================ workspace
 namespace {
@@ -690,7 +699,7 @@ struct StepPlan {
 };
 
 // ev: optional array of EIT_N_PHASES + 1 events recorded around the phases.
-int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev = nullptr) {
+int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
     auto mark = [&](int i) -> int {
         if (ev) HIP_TRY(hipEventRecord(ev[i], st));
         return EIT_OK;
@@ -746,60 +755,156 @@ struct PhaseTimer {
     }
 };
 
+// ---------------------------------------------------------------------------- step graphs
+// A captured graph holds kStepsPerGraph consecutive evaluation steps; the launch gap between
+// graphs is larger than between kernels of one graph. Its kernels read every per-call value
+// (data pointers, options, optimiser state) from descriptors at fixed workspace offsets, so
+// a graph depends only on the plans (item tables, tiles), the workspace address and the
+// L-BFGS memory (which fixes the workspace layout). Graphs are therefore kept, keyed by
+// those, and replayed by later calls instead of being captured and instantiated each time.
+// At most kGraphCacheMax are kept (least recently used dropped); destroying a plan drops its
+// graphs. Captures run on a library-owned stream per device, so the caller's stream, the
+// null stream included, only ever replays.
+constexpr int kStepsPerGraph = 4;
+constexpr size_t kGraphCacheMax = 16;
+
+struct GraphKey {
+    std::vector<const eit_plan*> plans;
+    const void* ws = nullptr;
+    int m = 0;
+    int device = 0;
+    bool operator==(const GraphKey& o) const {
+        return plans == o.plans && ws == o.ws && m == o.m && device == o.device;
+    }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+std::vector<hipStream_t> g_capture_streams;    // per device, created on first use
+
+void destroy_entry(GraphEntry& e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+}
+
+void purge_graphs(const eit_plan* p) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    bool any = false;
+    for (const auto& e : g_graphs)
+        any = any || std::find(e.key.plans.begin(), e.key.plans.end(), p) != e.key.plans.end();
+    if (!any) return;
+    (void)hipDeviceSynchronize();           // no replay of a dropped graph may still be queued
+    for (auto& e : g_graphs)
+        if (std::find(e.key.plans.begin(), e.key.plans.end(), p) != e.key.plans.end()) destroy_entry(e);
+    g_graphs.erase(std::remove_if(g_graphs.begin(), g_graphs.end(),
+                                  [](const GraphEntry& e) { return e.exec == nullptr; }),
+                   g_graphs.end());
+}
+
+// Library-owned streams per device, created on first use and kept until the process ends:
+// one for captures (under g_graph_mu), one that replays graphs for null-stream callers.
+std::vector<hipStream_t> g_replay_streams;
+std::mutex g_stream_mu;
+
+int owned_stream(std::vector<hipStream_t>& v, int dev, hipStream_t* out) {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    if ((int)v.size() <= dev) v.resize(dev + 1, nullptr);
+    if (!v[dev]) HIP_TRY(hipStreamCreateWithFlags(&v[dev], hipStreamNonBlocking));
+    *out = v[dev];
+    return EIT_OK;
+}
+int capture_stream(int dev, hipStream_t* out) { return owned_stream(g_capture_streams, dev, out); }
+int replay_stream(int dev, hipStream_t* out) { return owned_stream(g_replay_streams, dev, out); }
+
+int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev);
+
+// The graph of key, captured on first use.
+int step_graph(const StepPlan& sp, GraphKey key, hipGraphExec_t* out) {
+    HIP_TRY(hipGetDevice(&key.device));
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& e : g_graphs)
+        if (e.key == key) {
+            e.used = ++g_graph_clock;
+            *out = e.exec;
+            return EIT_OK;
+        }
+    hipStream_t cs;
+    if (int rc = capture_stream(key.device, &cs)) return rc;
+    GraphEntry ent;
+    ent.key = key;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = EIT_OK;
+    for (int q = 0; q < kStepsPerGraph && !rc; ++q) rc = enqueue_step(sp, cs, nullptr);
+    hipError_t e = hipStreamEndCapture(cs, &ent.graph);
+    if (rc) { destroy_entry(ent); return rc; }
+    if (e != hipSuccess) { destroy_entry(ent); return fail(EIT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e)); }
+    e = hipGraphInstantiate(&ent.exec, ent.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_entry(ent);
+        return fail(EIT_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    if (g_graphs.size() >= kGraphCacheMax) {
+        auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                    [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+        (void)hipDeviceSynchronize();       // the dropped graph may still be replaying
+        destroy_entry(*lru);
+        g_graphs.erase(lru);
+    }
+    ent.used = ++g_graph_clock;
+    g_graphs.push_back(ent);
+    *out = ent.exec;
+    return EIT_OK;
+}
+
 // Replays the step until every slice's optimiser has stopped. Reads back (status, k) of each
 // slice only between rounds of launches; each round enqueues as many steps as the slowest
 // slice still needs iterations (every accepted iteration needs at least one evaluation).
-constexpr int kStepsPerGraph = 4;
 int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-             bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt);
+             hipGraphExec_t exec, hipStream_t st, int* launches_out, PhaseTimer* pt);
 
-// The null stream cannot be captured: graph replays then run on a private non-blocking
-// stream ordered after (and before) the caller's work through events.
+// Graph replays for a null-stream caller run on a library-owned non-blocking stream, ordered
+// after (and before) the caller's work through an event.
 int drive(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-          bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt) {
+          bool use_graph, const GraphKey& key, hipStream_t st, int* launches_out, PhaseTimer* pt) {
     if (pt) use_graph = false;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph)
+        if (int rc = step_graph(sp, key, &exec)) return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
     if (!use_graph || st != nullptr)
-        return drive_on(sp, states, max_iter, max_ls, use_graph, st, launches_out, pt);
+        return drive_on(sp, states, max_iter, max_ls, exec, st, launches_out, pt);
     hipStream_t side = nullptr;
     hipEvent_t ev = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (int rc = replay_stream(dev, &side)) return rc;
     int rc = EIT_OK;
     hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, ev, 0);
     if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "stream ordering: %s", hipGetErrorString(e));
-    if (!rc) rc = drive_on(sp, states, max_iter, max_ls, true, side, launches_out, nullptr);
+    if (!rc) rc = drive_on(sp, states, max_iter, max_ls, exec, side, launches_out, nullptr);
     if (!rc) {
         e = hipEventRecord(ev, side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
         if (e != hipSuccess) rc = fail(EIT_ERR_DEVICE, "stream ordering: %s", hipGetErrorString(e));
     }
-    (void)hipStreamSynchronize(side);
     if (ev) (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(side);
     return rc;
 }
 
 int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int max_iter, int max_ls,
-             bool use_graph, hipStream_t st, int* launches_out, PhaseTimer* pt) {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    // A graph holds kStepsPerGraph consecutive steps: the launch gap between graphs is
-    // larger than between kernels of one graph. Steps past a slice's end are no-ops (its
-    // skip flags are set), so a round may run up to kStepsPerGraph - 1 idle steps.
-    if (use_graph) {
-        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        int rc = EIT_OK;
-        for (int q = 0; q < kStepsPerGraph && !rc; ++q) rc = enqueue_step(sp, st);
-        hipError_t e = hipStreamEndCapture(st, &graph);
-        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
-        if (e != hipSuccess) return fail(EIT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return fail(EIT_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        }
-    }
+             hipGraphExec_t exec, hipStream_t st, int* launches_out, PhaseTimer* pt) {
+    // Steps past a slice's end are no-ops (its skip flags are set), so a round may run up to
+    // kStepsPerGraph - 1 idle steps.
+    const bool use_graph = exec != nullptr;
     const long long cap = (long long)(max_iter + 2) * (max_ls + 2) * 2 + 16;
     long long total = 0;
     int rc = EIT_OK;
@@ -838,8 +943,6 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
         if (total > cap) { rc = fail(EIT_ERR_DEVICE, "optimiser did not stop within %lld steps", cap); break; }
         want = remaining;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     if (launches_out) *launches_out = (int)std::min<long long>(total, 1 << 30);
     return rc;
 }
@@ -932,7 +1035,12 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;
-    if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches, pt))
+    GraphKey key;
+    key.plans = {p};
+    key.ws = ws;
+    key.m = o->lbfgs_m;
+    if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, key, st,
+                       &launches, pt))
         return rc;
     HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 0, st));
     SolverState hs;
@@ -1139,7 +1247,12 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;
-    if (int rc = drive(sp, states, o->max_iter, o->max_ls_trials, o->use_graph != 0, st, &launches, pt))
+    GraphKey key;
+    key.plans.assign(plans, plans + n);
+    key.ws = ws;
+    key.m = o->lbfgs_m;
+    if (int rc = drive(sp, states, o->max_iter, o->max_ls_trials, o->use_graph != 0, key, st,
+                       &launches, pt))
         return rc;
     HIP_TRY(launch_lb_scale(ld, it_vec, n_vec, grid_for(n_vec, kGridCap), 0, st));
     std::vector<SolverState> hs(n);
