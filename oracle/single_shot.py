@@ -92,3 +92,40 @@ def reconstruct(s_exp, theta, n, mask_pos, amp, ctr, sig, kappa):
     mu = fbp(-logT, theta, n)
     de = fbp(integrate_refraction(dl, kappa), theta, n)
     return np.stack([mu, de])
+
+
+# ---------------------------------------------------------------------------------------
+# eq. 3: single-shot retrieval from ONE mask position for a homogeneous object (h-mode).
+# Read (the printed equation carries gamma^-1 where eq. 4 and the homogeneity assumption
+# put gamma): linearising s = T f(m - Delta) with Delta = kappa gamma d/dt R[h] and
+# T d/dt R[h] = -d/dt T gives s/f = T + kappa gamma (f'/f) d/dt T, so in Fourier space along t
+#   T = F^-1[ F[s/f] / (1 + i kappa gamma (f'(m)/f(m)) sin q) ],   R[h] = -log T,
+# with f(m), f'(m) the detector-averaged flat and its slope at the mask position (the paper's
+# definition) and i sin q the symbol of the central difference D (i q in the continuous
+# equation). The division by the flat in F[s/f] is per pixel. Transmissions below
+# EQ3_T_FLOOR are held at the floor before the logarithm.
+EQ3_T_FLOOR = 1e-6
+
+
+def eq3_symbol(n_det: int, beta: float) -> np.ndarray:
+    """1 / (1 + i beta sin q_l), q_l = 2 pi l / n_det (numpy's DFT frequency order)."""
+    q = 2.0 * np.pi * np.arange(n_det) / n_det
+    return 1.0 / (1.0 + 1j * beta * np.sin(q))
+
+
+def retrieve_eq3(s_m: np.ndarray, f_px: np.ndarray, f_mean: float, fp_mean: float,
+                 kappa_gamma: float) -> np.ndarray:
+    """R[h] [n_theta][n_det] from the data at one mask position s_m [n_theta][n_det], the flat
+    at that position per pixel f_px [n_det], and the detector-averaged flat and slope."""
+    r = np.asarray(s_m, dtype=np.float64) / np.asarray(f_px, dtype=np.float64)[None, :]
+    sym = eq3_symbol(r.shape[1], kappa_gamma * fp_mean / f_mean)
+    T = np.real(np.fft.ifft(np.fft.fft(r, axis=1) * sym[None, :], axis=1))
+    return -np.log(np.maximum(T, EQ3_T_FLOOR))
+
+
+def reconstruct_eq3(s_exp, theta, n, mask_index, flat_f, flat_fp, kappa_gamma):
+    """h from eq. 3 at mask position mask_index and the filtered backprojection of R[h].
+    flat_f, flat_fp: [n_det] flat IC and slope of every pixel at that position."""
+    s_m = np.asarray(s_exp, dtype=np.float64)[:, mask_index, :]
+    P = retrieve_eq3(s_m, flat_f, float(np.mean(flat_f)), float(np.mean(flat_fp)), kappa_gamma)
+    return fbp(P, theta, n)

@@ -68,3 +68,55 @@ def test_single_shot_small_case_is_close():
     err_mu = np.linalg.norm(x[0] - c.mu_true) / np.linalg.norm(c.mu_true)
     err_de = np.linalg.norm(x[1] - c.delta_true) / np.linalg.norm(c.delta_true)
     assert err_mu < 0.5 and err_de < 0.7
+
+
+# ------------------------------------------------------------------ eq. 3 (one mask position)
+def _circ_diff(p):
+    return 0.5 * (np.roll(p, -1, axis=-1) - np.roll(p, 1, axis=-1))
+
+
+def test_eq3_inverts_the_linearised_model_exactly():
+    """Data made by the linearised model s/f = T + beta D T (D the circular central difference,
+    beta = kappa gamma f'/f): the retrieval returns -log T to rounding. A wrong sign of the
+    derivative term, q in place of sin q, or beta missing its factor would not."""
+    from oracle import single_shot as ss
+    from paper_2202_08627_amd import synth
+    nt, nd = 7, 64
+    theta = synth.angles(nt)
+    t = np.arange(nd) - (nd - 1) / 2
+    P = 0.3 * synth.ellipse_line_integrals(np.array([[3.0, -2.0, 20.0, 14.0, 0.4, 0.02, 0.0]]),
+                                           5, theta, t)
+    T = np.exp(-P)
+    f_px = np.full(nd, 0.8)
+    fbar, fpbar, kg = 0.8, -0.9, 0.7
+    beta = kg * fpbar / fbar
+    s = f_px * (T + beta * _circ_diff(T))
+    R = ss.retrieve_eq3(s, f_px, fbar, fpbar, kg)
+    assert np.allclose(R, P, rtol=0, atol=1e-12)
+
+
+def test_eq3_error_on_nonlinear_data_is_first_order_in_strength():
+    """Data from the full h-mode model (oracle, one mask position on the slope of a Gaussian
+    flat): the retrieval's relative error comes from the linearisation alone and halves when
+    the object's strength halves."""
+    from oracle import full_model as fm
+    from oracle import single_shot as ss
+    from paper_2202_08627_amd import synth
+    n, nt = 32, 24
+    theta = np.arange(nt) * (2 * np.pi / nt)
+    m = np.array([0.24])
+    nd = n
+    amp, ctr, sig = np.ones(nd), np.zeros(nd), np.full(nd, 0.6)
+    st = fm.Setup(n, theta, nd, m, amp, ctr, sig, kappa=0.14, hmode=True, gamma=5.0)
+    yy, xx = np.mgrid[0:n, 0:n] - (n - 1) / 2
+    disk = ((xx - 2) ** 2 + (yy + 1) ** 2 <= 9.0 ** 2).astype(float)
+    f0 = np.exp(-(m[0]) ** 2 / (2 * 0.36))
+    fp0 = -m[0] / 0.36 * f0
+    errs = []
+    for eps in (0.02, 0.01, 0.005):
+        h = eps * disk
+        P_mu, _, _, _, _, s = fm.forward(st, h.ravel())
+        R = ss.retrieve_eq3(s[:, 0, :], np.full(nd, f0), f0, fp0, 0.14 * 5.0)
+        errs.append(np.linalg.norm(R - P_mu) / np.linalg.norm(P_mu))
+    assert errs[0] < 0.1
+    assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7, errs
