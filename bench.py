@@ -29,7 +29,12 @@ Printed as one JSON line. Extra keys:
 
 Other workloads (`--workload`): batch256 (256 independent slices of mixed size),
 unet_train / unet_infer (the warm-start network), autograd1024 (cost and gradient through the
-autograd node at 1024^2, 1800 angles, M = 12).
+autograd node at 1024^2, 1800 angles, M = 12), paper220 (the paper's acquisition on a
+synthetic granule slice: h-mode, one mask position, 400 angles over 360 deg, drift fitted;
+slice-iters/s and Table 2's four columns: 1 or 20 flat scans, ring term fitted or not, with
+iterations to 1e-3, CNR and the FRC resolution of iterative vs eq. 3 single shot), stack220
+(the 220 x 220 x 75 granule stack through one batch call), sweeps (projector-only times at
+Table 1's four sinogram shapes, and iteration times at N_t = N_theta = 360 / 720 / 1440).
 """
 from __future__ import annotations
 
@@ -382,10 +387,135 @@ def autograd_main(args, log):
     return 0
 
 
+def paper220_main(args, log):
+    """The paper's acquisition on slice 37 of the synthetic 220 x 220 x 75 granule stack
+    (configs.PAPER_220): timed iterations with 20 flat scans, drift fitted, no ring term (the
+    paper's final method), then Table 2's four columns and the FRC resolution comparison."""
+    import torch
+    from paper_2202_08627_amd import configs, experiment, synth
+    cfg = configs.PAPER_220
+    torch.cuda.set_device(0)
+    cases, granules = synth.make_stack(cfg, 75)
+    case = cases[37]
+    s_exp = torch.as_tensor(case.s_exp, device="cuda")
+    plan = experiment.model_plan(case, fit_drift=True, fit_ring=False)
+    kw = experiment.solve_kw(cfg)
+    plan.reconstruct(s_exp, iters=max(args.warmup, 1), **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, rep, _ = plan.reconstruct(s_exp, iters=args.steps, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    _, prep, _ = plan.reconstruct(s_exp, iters=args.steps, profile=True, **kw)
+    rows = experiment.table2(cfg, log=log)
+    frc = experiment.resolution_comparison(cfg, log=log)
+    line = {
+        "metric": "slice-iters/s (220^2, 400 angles over 360 deg, M = 1, h-mode)",
+        "value": round(rep["iters"] / t, 2), "unit": "slice-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper220: h-mode (mu = h, delta = 5 h), one mask position on the "
+                               "IC slope, 400 angles over 360 deg, 220x220 slice of a 3-material "
+                               "granule stack, tabulated flat from 20 scans, drift fitted, no ring "
+                               "term, lambda = 1e-2, from zero",
+                   "iterations": rep["iters"], "evals": rep["evals"],
+                   "phase_ms_per_iter": {k: round(v / max(prep["iters"], 1), 5)
+                                         for k, v in prep["phase_ms"].items()}},
+        "table2": rows,
+        "frc_resolution": frc,
+        "paper_context": {"table2": "Numba columns: 1 flat scan 87 steps with m_r, 37 without; "
+                                    "20 flat scans 51 with m_r, 36 without (6.62 % of 219 s = "
+                                    "14.5 s on one i5 core); CNR PMMA-PP 12.6, PMMA-PS 9.6, PS-PP "
+                                    "2.6 with 20 scans and no m_r",
+                          "frc": "iterative resolution 30 % better than single shot"},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def stack220_main(args, log):
+    """The 220 x 220 x 75 granule stack (paper acquisition, 20 flat scans, drift fitted, no ring
+    term) in one batch call of `--steps` iterations per slice."""
+    import torch
+    from paper_2202_08627_amd import configs, experiment
+    torch.cuda.set_device(0)
+    res, xs, cases, granules, plans = experiment.stack_batch(configs.PAPER_220, 75, iters=args.steps,
+                                                             warmup=max(args.warmup, 1))
+    line = {
+        "metric": "slice-iters/s (220 x 220 x 75 stack, 400 angles over 360 deg, M = 1, h-mode)",
+        "value": res["slice_iters_per_s"], "unit": "slice-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * res["wall_s"] / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stack220: 75 slices of the synthetic granule stack, one batch call",
+                   **res},
+        "paper_context": "220 x 220 x 75 voxels in 23 min on one i5 core",
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def sweeps_main(args, log):
+    """Secondary sweeps (context, not targets): the projector alone at Table 1's sinogram shapes
+    (N_t detector pixels = grid size, N_theta angles over 180 deg, both maps), and full h-mode
+    iterations (one mask position, 360 deg, drift fitted, 20-scan flat table) at
+    N_t = N_theta = 360, 720, 1440."""
+    import dataclasses
+    import torch
+    from paper_2202_08627_amd import _lib, autotune, configs, experiment, ops, synth
+    torch.cuda.set_device(0)
+    out = {"projector": [], "iteration": []}
+    for nt_det, n_th in ((90, 45), (180, 90), (360, 180), (720, 360)):
+        cfg = dataclasses.replace(configs.SMALL_64, n=nt_det, n_theta=n_th, n_det=nt_det,
+                                  mu_scale=configs.mu_range_for(nt_det))
+        c = synth.make_case(cfg)
+        geo = ops.Geometry.from_case(c)
+        plan = ops.Plan(geo, *autotune.tiling_for(geo))
+        x = torch.as_tensor(c.x_true.astype("float32"), device="cuda")
+        sino = torch.empty(plan.sino_shape, device="cuda")
+        ws = plan.workspace(_lib.EIT_OP_PROJECT)
+        for _ in range(3):
+            plan.project(x, out=sino, ws=ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 50
+        e0.record()
+        for _ in range(reps):
+            plan.project(x, out=sino, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out["projector"].append({"N_t": nt_det, "N_theta": n_th, "ms": round(ms, 5),
+                                 "samples_per_s": round(float(nt_det) ** 2 * n_th / (ms * 1e-3), 1)})
+        log(f"# projector {nt_det} x {n_th}: {ms:.4f} ms")
+    for N in (360, 720, 1440):
+        cfg = dataclasses.replace(configs.PAPER_220, n=N, n_det=N, n_theta=N,
+                                  mu_scale=configs.mu_range_for(N))
+        c = synth.make_case(cfg)
+        plan = experiment.model_plan(c, fit_drift=True, fit_ring=False)
+        s_exp = torch.as_tensor(c.s_exp, device="cuda")
+        k = 36
+        t = experiment.time_iterations(plan, s_exp, cfg, k)
+        out["iteration"].append({"N": N, "iters": k, "total_ms": round(1e3 * t, 3),
+                                 "ms_per_iter": round(1e3 * t / k, 4)})
+        log(f"# iteration N = {N}: {1e3 * t / k:.4f} ms per iteration")
+    line = {
+        "metric": "secondary sweeps (projector at Table 1 shapes; h-mode iterations at N = 360/720/1440)",
+        "value": None, "unit": "ms", "n_gpus": 1, "steps": None, "warmup": None,
+        "higher_is_better": False, "dtype": "f32", "data": "synthetic", "sweeps": out,
+        "paper_context": {"table1_relative": "lookup / Numba / OpenMP (3 threads), lookup at "
+                                             "720 x 360 = 100: 90x45 0.74/0.18/0.27, 180x90 3.5/1.4/1.2, "
+                                             "360x180 18/11/5.6, 720x360 100/88/27",
+                          "total_iteration_time_s": {"360": 31, "720": 290, "1440": 2700}},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["slice512", "batch256", "unet_train", "unet_infer",
-                                           "autograd1024"],
+                                           "autograd1024", "paper220", "stack220", "sweeps"],
                     default="slice512",
                     help="slice512 (default): the headline slice; batch256: 256 mixed slices; "
                          "unet_train / unet_infer: the warm-start network; autograd1024: "
@@ -420,6 +550,12 @@ def main():
         return unet_main(args, log, args.workload == "unet_train")
     if args.workload == "autograd1024":
         return autograd_main(args, log)
+    if args.workload == "paper220":
+        return paper220_main(args, log)
+    if args.workload == "stack220":
+        return stack220_main(args, log)
+    if args.workload == "sweeps":
+        return sweeps_main(args, log)
 
     child = None
     if not args.no_cpu_baseline:

@@ -66,6 +66,7 @@ extern "C" {
 #define EIT_MAX_NTHETA 16384
 #define EIT_MAX_NMASK 64
 #define EIT_MAX_LBFGS_M 20
+#define EIT_MAX_NTABLE 1024
 
 typedef struct eit_plan eit_plan;
 
@@ -104,6 +105,41 @@ typedef struct {
     int32_t adj_variant;
     int32_t adj_splits;
 } eit_tiling;
+
+/* The paper's full forward model (theory section, eq. 4), for eit_plan_create_model:
+ *     s_mod(t, theta, m) = exp(-R[mu]) f_t(m - m_o(theta) - m_r(t) - kappa d/dt R[delta])
+ * hmode: nonzero for the homogeneous-object assumption that leads to eq. 4 and eq. 3: one
+ *        map h with mu = h and delta = gamma*h (gamma > 0). The gradient in h is the mu
+ *        gradient plus gamma times the delta gradient.
+ * fit_drift: nonzero makes the per-angle offset of the sample mask m_o(theta) (the drift the
+ *        paper fits, eq. 4) n_theta more unknowns.
+ * fit_ring: nonzero makes the per-pixel offset m_r(t) (eq. 4's ring-artefact term) n_det
+ *        more unknowns. With both offsets the cost has the paper's ambiguity m_o + c, m_r - c.
+ * n_table: 0 keeps the Gaussian flats of eit_setup; >= 4 (<= EIT_MAX_NTABLE) replaces them
+ *        by a measured flat IC, flat_table (host, [n_det][n_table], FP64, read during the
+ *        call), sample q taken at mask offset table_u0 + q*table_du (table_du > 0; the
+ *        experiment section scans one period in 33 steps). The model interpolates it by
+ *        cubic convolution (Keys 1981, a = -1/2) and holds the end values outside the scan
+ *        (slope 0 there). eit_setup's Gaussian parameters may then be NULL.
+ * offset_scale: optimiser scaling of the offsets, z = m / offset_scale (0 means 1).
+ * eq3_mask: h-mode single shot (eq. 3): index of the mask position it reads.
+ * Parameter vector (x and gradient of eit_cost_and_grad, x of eit_reconstruct, x_out of
+ * eit_single_shot): the maps (float[2][n][n], or float[n][n] h in h-mode), then m_o
+ * [n_theta] if fitted, then m_r [n_det] if fitted; eit_param_count gives its length.
+ * eit_project and eit_backproject keep applying R and R^T to two maps. A batch
+ * (eit_reconstruct_batch) takes either only plain plans or only model plans. */
+typedef struct {
+    int32_t hmode;
+    int32_t fit_drift;
+    int32_t fit_ring;
+    int32_t n_table;
+    double gamma;
+    const double* flat_table;
+    double table_u0, table_du;
+    double offset_scale;
+    int32_t eq3_mask;
+    int32_t pad;
+} eit_model;
 
 /* Optimiser options for eit_reconstruct (L-BFGS on the scaled unknowns
  * z = [mu / mu_scale ; delta / delta_scale], cost weight lam on ||z||^2, i.e.
@@ -153,6 +189,17 @@ int eit_plan_create(const eit_dims* dims, const eit_setup* setup, const eit_tili
                     eit_plan** out);
 void eit_plan_destroy(eit_plan* plan);
 
+/* As eit_plan_create, for the full model of eq. 4 described by *model (required, host, read
+ * during the call). Errors as eit_plan_create, plus EIT_ERR_INVALID_ARG for invalid model
+ * options and EIT_ERR_SHAPE for n_table outside [4, EIT_MAX_NTABLE]. */
+int eit_plan_create_model(const eit_dims* dims, const eit_setup* setup, const eit_model* model,
+                          const eit_tiling* tiling, eit_plan** out);
+
+/* Entries of the plan's parameter vector: 2 n^2 for a plain plan; for a model plan the maps
+ * (n^2 in h-mode, else 2 n^2) plus n_theta drift and n_det ring offsets when fitted. 0 for
+ * a NULL plan. Host only. */
+int64_t eit_param_count(const eit_plan* plan);
+
 /* Operation codes for eit_workspace_bytes. */
 #define EIT_OP_PROJECT 1
 #define EIT_OP_BACKPROJECT 2
@@ -188,6 +235,9 @@ int eit_backproject(const eit_plan* plan, const float* sino, float* x_out, void*
 int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, double lam_mu,
                       double lam_delta, double* cost_dev, float* grad, void* ws, size_t ws_bytes,
                       void* stream);
+/* With a model plan, x and grad are parameter vectors (eit_param_count entries, raw units)
+ * and the model is eq. 4 with the plan's options; in h-mode lam_mu weights ||h||^2 and
+ * lam_delta is unused; the offsets are not regularised. */
 
 /* Non-iterative reconstruction (the paper's single-shot route: retrieve each projection
  * pixel, then filtered backprojection), used as the start of the learned warm start.
@@ -200,6 +250,13 @@ int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, 
  * Workspace: eit_workspace_bytes(plan, EIT_OP_SINGLE_SHOT, 0). Asynchronous. */
 int eit_single_shot(const eit_plan* plan, const float* s_exp, float* x_out, void* ws,
                     size_t ws_bytes, void* stream);
+/* With an h-mode model plan the route is eq. 3 (single-shot retrieval from one mask
+ * position, eq3_mask, for a homogeneous object): r = s / f_t(m) per pixel, then in Fourier
+ * space along t, T = F^-1[F[r] / (1 + i kappa gamma (f'/f) sin q)] with f, f' the detector-
+ * averaged flat and slope at m (sin q: the symbol of the central difference), R[h] = -log T
+ * (T held at >= 1e-6); h = Ram-Lak filtered backprojection of R[h] (as above). x_out is a
+ * parameter vector: the map(s), offsets set to 0. A two-map model plan takes the per-pixel
+ * fit above and needs the Gaussian flat parameters (EIT_ERR_INVALID_ARG otherwise). */
 
 /* Minimise the cost of eq. 5 from x (device float[2][n][n], raw units): x holds the start on
  * entry and x_K on return. Theory section: the paper minimises eq. 5 with L-BFGS (SciPy's
@@ -217,11 +274,16 @@ int eit_single_shot(const eit_plan* plan, const float* s_exp, float* x_out, void
  * EIT_ERR_NONFINITE if the cost at the start is not finite. */
 int eit_reconstruct(const eit_plan* plan, const float* s_exp, const eit_opts* opts, float* x,
                     double* cost_hist, eit_report* rep, void* ws, size_t ws_bytes, void* stream);
+/* With a model plan, x is a parameter vector (start in, x_K out); the scaled unknowns are
+ * h / mu_scale in h-mode (delta_scale unused) and the offsets / offset_scale, and lam weights
+ * the squared norm of the scaled maps only. */
 
 /* Many independent slices (3-D as a stack of 2-D problems, combined-results section) in
  * one sequence of persistent launches, optionally replayed from one captured HIP graph.
  * plans/s_exp/x/reps are host arrays of n_slices entries (s_exp[i], x[i] device pointers
- * as in eit_reconstruct; reps may be NULL). Slices may differ in every size. Workspace:
+ * as in eit_reconstruct; reps may be NULL). Slices may differ in every size, and in their
+ * model options if every plan is a model plan (EIT_ERR_INVALID_ARG for a mix of plain and
+ * model plans). Workspace:
  * eit_batch_workspace_bytes. Each slice runs its own optimiser state and line search. */
 size_t eit_batch_workspace_bytes(int32_t n_slices, const eit_plan* const* plans, int32_t lbfgs_m);
 int eit_reconstruct_batch(int32_t n_slices, const eit_plan* const* plans,
@@ -253,6 +315,34 @@ typedef struct {
 int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
                      eit_plan_info* info, double* proj_angles, int32_t* groups, int32_t* win_lo,
                      double* adj_angles);
+
+/* ---------------------------------------------------------------------------------------
+ * Image quality (combined-results and experiment sections), for reconstructions of synthetic
+ * phantoms; both run on `stream` and write their results to device memory.
+ *
+ * Fourier ring correlation of eq. 6 between two n x n images a and b (device float, row-
+ * major, 2 <= n <= EIT_MAX_FRC_N): FRC(r) = sum_ring Re(F_a F_b*) / sqrt(sum_ring |F_a|^2 *
+ * sum_ring |F_b|^2), F the 2-D DFT, ring r the frequencies (kx, ky) (signed, DFT order) with
+ * round(sqrt(kx^2 + ky^2)) = r, r = 0 .. n/2 (the printed equation omits the ring sums and
+ * the real part; this is the standard definition the paper cites). curve and smooth: device
+ * double[n/2 + 1], the curve and its Gaussian smoothing over rings 1 .. n/2 (width sigma
+ * rings, weights renormalised at the ends; ring 0 kept). res: device double[2], the
+ * resolution n / r_c in pixels and r_c, the first ring (linear interpolation) at which the
+ * smoothed curve drops below cutoff (0.5 in the paper), or n/2 if it never does. Workspace:
+ * eit_frc_workspace_bytes(n) (0 for an invalid n), 256-byte aligned. Deterministic (fixed
+ * summation orders). */
+#define EIT_MAX_FRC_N 1024
+size_t eit_frc_workspace_bytes(int32_t n);
+int eit_frc(int32_t n, const float* a, const float* b, double* curve, double* smooth, double* res,
+            double cutoff, double sigma, void* ws, size_t ws_bytes, void* stream);
+
+/* Contrast-to-noise ratio of eq. 7 in the n x n image img (device float): CNR =
+ * |mean_1 - mean_2| / sqrt(std_1^2 + std_2^2) over the pixels whose centres lie within rho of
+ * (x1, y1) and of (x2, y2) (centred coordinates: pixel (i, j) at (i - (n-1)/2, j - (n-1)/2)),
+ * population standard deviations. out: device double[1]. EIT_ERR_INVALID_ARG if a disc holds
+ * no pixel centre (checked on the host). */
+int eit_cnr(int32_t n, const float* img, double x1, double y1, double x2, double y2, double rho,
+            double* out, void* stream);
 
 /* Thread-local message describing the last non-zero return on this thread. */
 const char* eit_last_error(void);

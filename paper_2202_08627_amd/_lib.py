@@ -47,6 +47,13 @@ class Tiling(C.Structure):
                 ("adj_splits", C.c_int32)]
 
 
+class Model(C.Structure):
+    _fields_ = [("hmode", C.c_int32), ("fit_drift", C.c_int32), ("fit_ring", C.c_int32),
+                ("n_table", C.c_int32), ("gamma", C.c_double), ("flat_table", C.POINTER(C.c_double)),
+                ("table_u0", C.c_double), ("table_du", C.c_double), ("offset_scale", C.c_double),
+                ("eq3_mask", C.c_int32), ("pad", C.c_int32)]
+
+
 class Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lbfgs_m", C.c_int32), ("max_ls_trials", C.c_int32),
                 ("use_graph", C.c_int32), ("lam", C.c_double), ("mu_scale", C.c_double),
@@ -83,6 +90,9 @@ IP = C.POINTER(C.c_int32)
 _PROTOS = {
     "eit_plan_create": (C.c_int, [C.POINTER(Dims), C.POINTER(Setup), C.POINTER(Tiling), C.POINTER(VP)]),
     "eit_plan_destroy": (None, [VP]),
+    "eit_plan_create_model": (C.c_int, [C.POINTER(Dims), C.POINTER(Setup), C.POINTER(Model),
+                                        C.POINTER(Tiling), C.POINTER(VP)]),
+    "eit_param_count": (C.c_int64, [VP]),
     "eit_workspace_bytes": (C.c_size_t, [VP, C.c_int32, C.c_int32]),
     "eit_project": (C.c_int, [VP, VP, VP, VP, C.c_size_t, VP]),
     "eit_backproject": (C.c_int, [VP, VP, VP, VP, C.c_size_t, VP]),
@@ -92,6 +102,10 @@ _PROTOS = {
     "eit_reconstruct_batch": (C.c_int, [C.c_int32, C.POINTER(VP), C.POINTER(VP), C.POINTER(VP),
                                         C.POINTER(Opts), C.POINTER(Report), VP, C.c_size_t, VP]),
     "eit_single_shot": (C.c_int, [VP, VP, VP, VP, C.c_size_t, VP]),
+    "eit_frc_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "eit_frc": (C.c_int, [C.c_int32, VP, VP, VP, VP, VP, C.c_double, C.c_double, VP, C.c_size_t, VP]),
+    "eit_cnr": (C.c_int, [C.c_int32, VP, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                          VP, VP]),
     "eit_last_error": (C.c_char_p, []),
     "eit_variant_info": (C.c_int, [C.c_int32, C.c_int32, IP, IP, IP, IP]),
     "eit_plan_inspect": (C.c_int, [C.POINTER(Dims), C.POINTER(Setup), C.POINTER(Tiling),

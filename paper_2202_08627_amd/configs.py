@@ -47,6 +47,14 @@ class SliceConfig:
     delta_scale: float = 1e-3   # delta range [0, 1e-3]
     iters: int = 50
     seed: int = 0
+    # acquisition and object variants of the full model (eq. 4); defaults = the plain model
+    angle_span: float = 1.0     # angles theta_a = a * angle_span * pi / n_theta (2.0: 360 deg)
+    mask_list: Tuple[float, ...] = ()   # explicit mask positions (default: spread over a period)
+    gamma_h: float = 0.0        # > 0: homogeneous object, delta = gamma_h * mu
+    flat_scans: int = 0         # >= 1: the flat IC is measured (tabulated, Poisson noise at
+                                # flat_scans * counts photons) instead of known analytically
+    n_table: int = 33           # flat IC samples over one mask period (tabulated flats)
+    drift_amp: float = 0.0      # amplitude (periods) of a seeded per-angle mask drift m_o
 
     @property
     def lam_mu(self) -> float:
@@ -132,7 +140,19 @@ class WarmStartConfig:
 
 WARMSTART = WarmStartConfig()
 
-CONFIGS = {"small_64": SMALL_64, "slice_512": SLICE_512, "slice_1024": SLICE_1024}
+# The paper's own acquisition (experiment section): homogeneous object (mu = h, delta = gamma h,
+# gamma = 5), one mask position on the slope of the IC, 400 projections over 360 degrees, a
+# 220^2 grid, lambda = 1e-2. The IC is narrower than the plain workloads' (sigma 0.3 period,
+# the position m = 0.3 on its steepest slope) and kappa = 1, so that the refraction shifts of
+# the granule-like phantom stay within the scanned period; the flat IC is measured over one
+# period in 33 steps (1 or 20 flat scans) and the mask drifts by up to 0.02 period.
+PAPER_220 = SliceConfig(n=220, n_theta=400, n_det=220, n_mask=1, phantom="random",
+                        n_ellipses=12, axis_max=0.3, sigma=0.3, sigma_jitter=0.05, kappa=1.0,
+                        iters=100, mu_scale=0.05 * 64 / 220, angle_span=2.0, mask_list=(0.3,),
+                        gamma_h=5.0, flat_scans=20, n_table=33, drift_amp=0.02)
+
+CONFIGS = {"small_64": SMALL_64, "slice_512": SLICE_512, "slice_1024": SLICE_1024,
+           "paper_220": PAPER_220}
 
 
 def with_seed(cfg: SliceConfig, seed: int) -> SliceConfig:

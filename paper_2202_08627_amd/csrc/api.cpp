@@ -43,6 +43,15 @@ int fail(int code, const char* fmt, ...) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+}  // namespace
+
+namespace eit {
+// Error reporting for the library's other translation units.
+int report_failure(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace eit
+
+namespace {
+
 struct Layout {
     size_t off = 0;
     size_t take(size_t bytes) {
@@ -104,6 +113,22 @@ struct eit_plan {
     Item* it_vec = nullptr;
     int n_it_tr, n_it_pr, n_it_ic, n_it_bp, n_it_vec;
     int device;
+    // full model of eq. 4 (ext == 0: the plain two-map model of eq. 2)
+    int ext = 0;
+    int n_maps = 2;        // maps in the parameter vector (1 in h-mode)
+    double gamma = 0.0;    // h-mode: delta = gamma h
+    double off_scale = 1.0;
+    int nq = 0;            // tabulated flat samples per pixel
+    double tab_u0 = 0.0, tab_du = 0.0;
+    int eq3_mask = 0;
+    bool gauss = true;     // Gaussian flat parameters given (the two-map single shot needs them)
+    int64_t nvu = 0;       // parameter-vector entries (= nv for the plain model)
+    double* ftab = nullptr;       // [n_det][nq]
+    double* eq3_kern = nullptr;   // [n_det] circular kernel of eq. 3 (h-mode)
+    double* eq3_invf = nullptr;   // [n_det] 1 / f_k(m_j0)
+    Item* it_uvec = nullptr;      // chunks of the parameter vector
+    Item* it_hvec = nullptr;      // chunks of one map
+    int n_it_uvec = 0, n_it_hvec = 0;
 };
 
 namespace {
@@ -120,7 +145,8 @@ int upload(T** dst, const std::vector<T>& v) {
 void free_plan(eit_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->apairs, p->flat, p->mask,
-                    p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec};
+                    p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec, p->ftab, p->eq3_kern,
+                    p->eq3_invf, p->it_uvec, p->it_hvec};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -200,11 +226,104 @@ struct HostTables {
     std::vector<float4> flat;
     std::vector<double> maskd;
     std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
+    std::vector<double> ftab, eq3_kern, eq3_invf;
+    std::vector<Item> it_uvec, it_hvec;
 };
+
+// Cubic-convolution value and slope (Keys 1981, a = -1/2) of a tabulated flat row F[0..Q) at u,
+// held at the end values (slope 0) outside the scanned period.
+void table_flat(const double* F, int Q, double u0, double du, double u, double* f, double* fp) {
+    const double lo = u0, hi = u0 + (Q - 1) * du;
+    const bool inside = u >= lo && u <= hi;
+    const double xq = (std::min(std::max(u, lo), hi) - lo) / du;
+    const int q = std::min(std::max((int)std::floor(xq), 0), Q - 2);
+    const double t = xq - q, t2 = t * t, t3 = t2 * t;
+    const double F0 = F[std::max(q - 1, 0)], F1 = F[q], F2 = F[q + 1], F3 = F[std::min(q + 2, Q - 1)];
+    *f = 0.5 * ((-t3 + 2 * t2 - t) * F0 + (3 * t3 - 5 * t2 + 2) * F1 + (-3 * t3 + 4 * t2 + t) * F2 +
+                (t3 - t2) * F3);
+    *fp = inside ? 0.5 * ((-3 * t2 + 4 * t - 1) * F0 + (9 * t2 - 10 * t) * F1 +
+                          (-9 * t2 + 8 * t + 1) * F2 + (3 * t2 - 2 * t) * F3) / du
+                 : 0.0;
+}
+
+// Model options: validation and the full model's tables (touches no device).
+int build_model(const eit_setup* setup, const eit_model* m, eit_plan* p, HostTables& h,
+                const std::vector<double>& mpos) {
+    const int nt = p->n_theta, nd = p->n_det;
+    p->ext = 0;
+    p->n_maps = 2;
+    p->nvu = p->nv;
+    if (!m) return EIT_OK;
+    if (m->hmode) {
+        if (!finite_pos(m->gamma)) return fail(EIT_ERR_INVALID_ARG, "h-mode gamma must be finite and > 0");
+        p->ext |= EXT_HMODE;
+        p->gamma = m->gamma;
+        p->n_maps = 1;
+    }
+    if (m->fit_drift) p->ext |= EXT_DRIFT;
+    if (m->fit_ring) p->ext |= EXT_RING;
+    if (m->offset_scale != 0.0 && !finite_pos(m->offset_scale))
+        return fail(EIT_ERR_INVALID_ARG, "offset_scale must be finite and > 0 (or 0 for 1)");
+    p->off_scale = m->offset_scale > 0.0 ? m->offset_scale : 1.0;
+    if (m->n_table != 0) {
+        if (m->n_table < 4 || m->n_table > EIT_MAX_NTABLE)
+            return fail(EIT_ERR_SHAPE, "n_table=%d outside [4, %d]", m->n_table, EIT_MAX_NTABLE);
+        if (!m->flat_table) return fail(EIT_ERR_INVALID_ARG, "flat_table is NULL");
+        if (!std::isfinite(m->table_u0) || !finite_pos(m->table_du))
+            return fail(EIT_ERR_INVALID_ARG, "table_u0 must be finite and table_du finite and > 0");
+        const size_t cnt = (size_t)nd * m->n_table;
+        for (size_t i = 0; i < cnt; ++i)
+            if (!std::isfinite(m->flat_table[i])) return fail(EIT_ERR_INVALID_ARG, "flat_table[%zu] not finite", i);
+        p->ext |= EXT_TABLE;
+        p->nq = m->n_table;
+        p->tab_u0 = m->table_u0;
+        p->tab_du = m->table_du;
+        h.ftab.assign(m->flat_table, m->flat_table + cnt);
+    }
+    if (m->eq3_mask < 0 || m->eq3_mask >= p->n_mask)
+        return fail(EIT_ERR_INVALID_ARG, "eq3_mask=%d outside [0, n_mask)", m->eq3_mask);
+    p->eq3_mask = m->eq3_mask;
+    if (!(p->ext & EXT_TABLE) && !p->gauss)
+        return fail(EIT_ERR_INVALID_ARG, "flat-field IC parameters are NULL and no table is given");
+    p->nvu = (int64_t)p->n_maps * p->n * p->n + ((p->ext & EXT_DRIFT) ? nt : 0) +
+             ((p->ext & EXT_RING) ? nd : 0);
+    if (p->ext & EXT_HMODE) {
+        // eq. 3: r = s / f_k(m_j0) convolved with the real kernel whose DFT is
+        // 1 / (1 + i beta sin(2 pi q / n_det)), beta = kappa gamma f'/f of the detector-averaged flat
+        const double mj = mpos[p->eq3_mask];
+        std::vector<double> f(nd), fp(nd);
+        double fs = 0.0, fps = 0.0;
+        for (int k = 0; k < nd; ++k) {
+            if (p->ext & EXT_TABLE) {
+                table_flat(&h.ftab[(size_t)k * p->nq], p->nq, p->tab_u0, p->tab_du, mj, &f[k], &fp[k]);
+            } else {
+                const double uu = mj - setup->flat_ctr[k], sg = setup->flat_sigma[k];
+                f[k] = setup->flat_amp[k] * std::exp(-uu * uu / (2.0 * sg * sg));
+                fp[k] = -uu / (sg * sg) * f[k];
+            }
+            fs += f[k];
+            fps += fp[k];
+        }
+        const double beta = fs != 0.0 ? p->kappa * p->gamma * (fps / nd) / (fs / nd) : 0.0;
+        h.eq3_invf.resize(nd);
+        for (int k = 0; k < nd; ++k) h.eq3_invf[k] = f[k] > 0.0 ? 1.0 / f[k] : 0.0;
+        h.eq3_kern.assign(nd, 0.0);
+        for (int q = 0; q < nd; ++q) {
+            const double sq = std::sin(2.0 * M_PI * q / nd);
+            const double den = 1.0 + beta * beta * sq * sq;
+            for (int l = 0; l < nd; ++l) {
+                const double ph = 2.0 * M_PI * (double)(((long long)q * l) % nd) / nd;
+                h.eq3_kern[l] += (std::cos(ph) + beta * sq * std::sin(ph)) / den;
+            }
+        }
+        for (int l = 0; l < nd; ++l) h.eq3_kern[l] /= nd;
+    }
+    return EIT_OK;
+}
 
 // Validation and FP64 table construction; touches no device (testable on the host).
 int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* tiling,
-               eit_plan* p, HostTables& h) {
+               eit_plan* p, HostTables& h, const eit_model* model = nullptr) {
     if (!dims || !setup) return fail(EIT_ERR_INVALID_ARG, "dims or setup is NULL");
     const int n = dims->n, nt = dims->n_theta, nd = dims->n_det, nm = dims->n_mask;
     if (n < 2 || n > EIT_MAX_N) return fail(EIT_ERR_SHAPE, "n=%d outside [2, %d]", n, EIT_MAX_N);
@@ -215,7 +334,8 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     if (nm < 1 || nm > EIT_MAX_NMASK)
         return fail(EIT_ERR_SHAPE, "n_mask=%d outside [1, %d]", nm, EIT_MAX_NMASK);
     if (!std::isfinite(dims->kappa)) return fail(EIT_ERR_INVALID_ARG, "kappa is not finite");
-    if (!setup->flat_amp || !setup->flat_ctr || !setup->flat_sigma)
+    p->gauss = setup->flat_amp && setup->flat_ctr && setup->flat_sigma;
+    if (!p->gauss && !(model && model->n_table != 0))
         return fail(EIT_ERR_INVALID_ARG, "flat-field IC parameters are NULL");
     std::vector<double> theta(nt), mpos(nm);
     for (int a = 0; a < nt; ++a) {
@@ -226,7 +346,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         mpos[j] = setup->mask_pos ? setup->mask_pos[j] : (j + 0.5) / nm - 0.5;
         if (!std::isfinite(mpos[j])) return fail(EIT_ERR_INVALID_ARG, "mask_pos[%d] not finite", j);
     }
-    for (int k = 0; k < nd; ++k) {
+    for (int k = 0; k < nd && p->gauss; ++k) {
         if (!finite_pos(setup->flat_amp[k]) || !finite_pos(setup->flat_sigma[k]) ||
             !std::isfinite(setup->flat_ctr[k]))
             return fail(EIT_ERR_INVALID_ARG, "flat-field parameters of pixel %d invalid", k);
@@ -245,7 +365,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
             eit_plan probe{};
             HostTables hh;
             const std::string keep = g_err;
-            if (build_host(dims, setup, &t, &probe, hh) == EIT_OK) { pv = pref[q]; break; }
+            if (build_host(dims, setup, &t, &probe, hh, model) == EIT_OK) { pv = pref[q]; break; }
             g_err = keep;
         }
     }
@@ -359,7 +479,7 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     // ---- detector tables
     std::vector<float4>& flat = h.flat;
     flat.assign(nd, float4{});
-    for (int k = 0; k < nd; ++k) {
+    for (int k = 0; k < nd && p->gauss; ++k) {
         const double sg = setup->flat_sigma[k];
         flat[k] = make_float4((float)setup->flat_amp[k], (float)setup->flat_ctr[k],
                               (float)(1.0 / (2.0 * sg * sg)), (float)(1.0 / (sg * sg)));
@@ -384,18 +504,27 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     p->n_it_tr = (int)it_tr.size(); p->n_it_pr = (int)it_pr.size(); p->n_it_ic = nt;
     p->n_it_bp = (int)it_bp.size(); p->n_it_vec = (int)it_vec.size();
 
+    // ---- full model of eq. 4: parameter vector and its work items
+    if (int rc = build_model(setup, model, p, h, mpos)) return rc;
+    p->n_vblocks = (int)((p->nvu + kVecChunk - 1) / kVecChunk);
+    for (int b = 0; b < p->n_vblocks; ++b) h.it_uvec.push_back(make_int4(0, b, 0, 0));
+    const int hb = (int)(((int64_t)n * n + kVecChunk - 1) / kVecChunk);
+    for (int b = 0; b < hb; ++b) h.it_hvec.push_back(make_int4(0, b, 0, 0));
+    p->n_it_uvec = (int)h.it_uvec.size();
+    p->n_it_hvec = hb;
     return EIT_OK;
 }
 
 }  // namespace
 
-extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
-                               const eit_tiling* tiling, eit_plan** out) {
+namespace {
+int create_plan(const eit_dims* dims, const eit_setup* setup, const eit_model* model,
+                const eit_tiling* tiling, eit_plan** out) {
     if (!out) return fail(EIT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     eit_plan* p = new eit_plan();
     HostTables h;
-    int rc = build_host(dims, setup, tiling, p, h);
+    int rc = build_host(dims, setup, tiling, p, h, model);
     if (rc) {
         delete p;
         return rc;
@@ -411,13 +540,30 @@ extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
         (rc = upload(&p->flat, h.flat)) || (rc = upload(&p->mask, h.maskd)) ||
         (rc = upload(&p->it_tr, h.it_tr)) || (rc = upload(&p->it_pr, h.it_pr)) ||
         (rc = upload(&p->it_ic, h.it_ic)) || (rc = upload(&p->it_bp, h.it_bp)) ||
-        (rc = upload(&p->it_vec, h.it_vec))) {
+        (rc = upload(&p->it_vec, h.it_vec)) || (rc = upload(&p->ftab, h.ftab)) ||
+        (rc = upload(&p->eq3_kern, h.eq3_kern)) || (rc = upload(&p->eq3_invf, h.eq3_invf)) ||
+        (rc = upload(&p->it_uvec, h.it_uvec)) || (rc = upload(&p->it_hvec, h.it_hvec))) {
         free_plan(p);
         return rc;
     }
     *out = p;
     return EIT_OK;
 }
+}  // namespace
+
+extern "C" int eit_plan_create(const eit_dims* dims, const eit_setup* setup,
+                               const eit_tiling* tiling, eit_plan** out) {
+    return create_plan(dims, setup, nullptr, tiling, out);
+}
+
+extern "C" int eit_plan_create_model(const eit_dims* dims, const eit_setup* setup,
+                                     const eit_model* model, const eit_tiling* tiling,
+                                     eit_plan** out) {
+    if (!model) return fail(EIT_ERR_INVALID_ARG, "model is NULL");
+    return create_plan(dims, setup, model, tiling, out);
+}
+
+extern "C" int64_t eit_param_count(const eit_plan* p) { return p ? p->nvu : 0; }
 
 extern "C" int eit_plan_inspect(const eit_dims* dims, const eit_setup* setup,
                                 const eit_tiling* tiling, eit_plan_info* info,
@@ -472,6 +618,7 @@ namespace {
 
 struct EvalLayout {
     size_t desc, xT, P, part_ic, part_reg, cost, bp_part, end;
+    size_t xe, ge, g_mo, g_dl;      // full model only (0 otherwise)
 };
 
 EvalLayout eval_layout(const eit_plan* p, bool need_P, size_t base = 0) {
@@ -485,6 +632,12 @@ EvalLayout eval_layout(const eit_plan* p, bool need_P, size_t base = 0) {
     e.part_reg = L.take(sizeof(double) * 2 * (size_t)p->n_trx * p->n_trx);
     e.cost = L.take(sizeof(double));
     e.bp_part = p->adj_splits > 1 ? L.take(sizeof(double) * p->adj_splits * (size_t)p->nv) : 0;
+    if (p->ext) {
+        e.xe = (p->ext & EXT_HMODE) ? L.take(sizeof(float) * (size_t)p->nv) : 0;
+        e.ge = L.take(sizeof(float) * (size_t)p->nv);
+        e.g_mo = (p->ext & EXT_DRIFT) ? L.take(sizeof(double) * (size_t)p->n_theta) : 0;
+        e.g_dl = (p->ext & EXT_RING) ? L.take(sizeof(double) * (size_t)p->n_theta * p->n_det) : 0;
+    }
     e.end = L.off;
     return e;
 }
@@ -499,7 +652,7 @@ SolveLayout solve_layout(const eit_plan* p, int m, size_t base = 0) {
     s.ev = eval_layout(p, true, base);
     Layout L;
     L.off = s.ev.end;
-    const size_t vb = sizeof(float) * (size_t)p->nv;
+    const size_t vb = sizeof(float) * (size_t)p->nvu;
     s.lbdesc = L.take(sizeof(LbDesc));
     s.state = L.take(sizeof(SolverState));
     s.z = L.take(vb); s.zt = L.take(vb); s.g = L.take(vb); s.gt = L.take(vb); s.d = L.take(vb);
@@ -509,6 +662,8 @@ SolveLayout solve_layout(const eit_plan* p, int m, size_t base = 0) {
     s.end = L.off;
     return s;
 }
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 SliceDesc base_desc(const eit_plan* p) {
     SliceDesc d{};
@@ -524,10 +679,26 @@ SliceDesc base_desc(const eit_plan* p) {
     d.pang = p->pang; d.groups = p->groups; d.win_lo = p->win_lo; d.aang = p->aang;
     d.flat = p->flat; d.mask = p->mask;
     d.n_reg_blocks = p->n_trx * p->n_trx;
+    d.ext = p->ext;
+    d.nq = p->nq; d.tab_u0 = p->tab_u0; d.tab_du = p->tab_du; d.ftab = p->ftab;
+    d.off_scale = 1.0;
+    d.nvu = p->nvu;
     return d;
 }
 
-char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+// Full-model buffers of a descriptor whose evaluation buffers start at `base`: the expanded
+// maps, the adjoint's planes and the offset sums. x_param is the parameter vector of the point.
+void set_ext_buffers(const eit_plan* p, SliceDesc& d, void* base, const EvalLayout& L,
+                     const float* x_param) {
+    const size_t nn = (size_t)p->n * p->n;
+    d.xu = x_param;
+    d.xe = (p->ext & EXT_HMODE) ? (float*)at(base, L.xe) : nullptr;
+    d.x = d.xe ? d.xe : x_param;
+    d.off = (p->ext & (EXT_DRIFT | EXT_RING)) ? x_param + p->n_maps * nn : nullptr;
+    d.g = (float*)at(base, L.ge);
+    d.g_mo = (p->ext & EXT_DRIFT) ? (double*)at(base, L.g_mo) : nullptr;
+    d.g_dl = (p->ext & EXT_RING) ? (double*)at(base, L.g_dl) : nullptr;
+}
 
 // The adjoint's partial-sum planes of a descriptor whose evaluation buffers start at `base`.
 void set_split_buffers(SliceDesc& d, void* base, const EvalLayout& L) {
@@ -640,6 +811,31 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
     d.reg_mu = 2.0 * lam_mu; d.reg_de = 2.0 * lam_delta;
     set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
+    if (p->ext) {
+        // full model: the maps (h expanded to [h, h], P_delta scaled by gamma) through the
+        // two-map kernels, the eq. 4 IC stage, the adjoint without regulariser and the
+        // contraction to the parameter layout
+        set_ext_buffers(p, d, ws, L, x);
+        d.gu = grad;
+        if (p->ext & EXT_HMODE) {
+            d.scale_de = p->gamma;
+            d.lam_de = 0.0;
+            d.reg_de = 0.0;
+        }
+        HIP_TRY(launch_store_desc(d, dd, st));
+        if (p->ext & EXT_HMODE)
+            HIP_TRY(launch_ext_expand(dd, p->it_hvec, p->n_it_hvec, grid_for(p->n_it_hvec, kGridCap), st));
+        HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
+        HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
+                               p->proj_lds, st));
+        HIP_TRY(launch_ic_ext(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap),
+                              grad ? 1 : 0, st));
+        HIP_TRY(launch_cost_reduce(dd, 1, st));
+        if (!grad) return EIT_OK;
+        if (int rc = enqueue_backproject(p, dd, 0, st)) return rc;
+        HIP_TRY(launch_ext_contract(dd, p->it_uvec, p->n_it_uvec, grid_for(p->n_it_uvec, kGridCap), st));
+        return EIT_OK;
+    }
     HIP_TRY(launch_store_desc(d, dd, st));
     if (int rc = enqueue_eval(p, dd, grad != nullptr, false, st)) return rc;
     HIP_TRY(launch_cost_reduce(dd, 1, st));
@@ -660,8 +856,26 @@ extern "C" int eit_single_shot(const eit_plan* p, const float* s_exp, float* x_o
     d.g = x_out;
     set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
-    HIP_TRY(launch_store_desc(d, dd, st));
     const int gi = grid_for(p->n_it_ic, kGridCap);
+    if (p->ext) {
+        // h-mode: eq. 3 from one mask position; two maps: the per-pixel fit (Gaussian flats).
+        // Both planes are backprojected into the workspace and the maps copied out, offsets 0.
+        if (!(p->ext & EXT_HMODE) && !p->gauss)
+            return fail(EIT_ERR_INVALID_ARG, "the two-map single shot needs the Gaussian flat parameters");
+        d.g = (float*)at(ws, L.ge);
+        d.gu = x_out;
+        HIP_TRY(launch_store_desc(d, dd, st));
+        if (p->ext & EXT_HMODE)
+            HIP_TRY(launch_eq3_retrieve(dd, p->it_ic, p->n_it_ic, gi, p->eq3_kern, p->eq3_invf,
+                                        p->eq3_mask, st));
+        else
+            HIP_TRY(launch_ss_retrieve(dd, p->it_ic, p->n_it_ic, gi, st));
+        HIP_TRY(launch_ss_filter(dd, p->it_ic, p->n_it_ic, gi, st));
+        if (int rc = enqueue_backproject(p, dd, 0, st)) return rc;
+        HIP_TRY(launch_ext_take_maps(dd, p->it_uvec, p->n_it_uvec, grid_for(p->n_it_uvec, kGridCap), st));
+        return EIT_OK;
+    }
+    HIP_TRY(launch_store_desc(d, dd, st));
     HIP_TRY(launch_ss_retrieve(dd, p->it_ic, p->n_it_ic, gi, st));
     HIP_TRY(launch_ss_filter(dd, p->it_ic, p->n_it_ic, gi, st));
     return enqueue_backproject(p, dd, 0, st);
@@ -696,6 +910,11 @@ struct StepPlan {
     const Item* it_tr; int n_tr;
     const Item* it_ic; int n_ic;
     const Item* it_vec; int n_vec;
+    // full model of eq. 4 (one slice): vector-form direction, separate transpose, eq. 4 IC
+    // stage, adjoint without regulariser (+ the split's combine pass over it_map), contraction
+    bool ext = false;
+    bool split = false;
+    const Item* it_map = nullptr; int n_map = 0;   // chunks of the two-map planes
 };
 
 // ev: optional array of EIT_N_PHASES + 1 events recorded around the phases.
@@ -705,6 +924,29 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
         return EIT_OK;
     };
     if (int rc = mark(0)) return rc;
+    if (sp.ext) {
+        HIP_TRY(launch_lb_direction_vec(sp.L, sp.D, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+        if (int rc = mark(1)) return rc;
+        HIP_TRY(launch_transpose(sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
+        if (int rc = mark(2)) return rc;
+        for (const auto& l : sp.proj)
+            HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
+        if (int rc = mark(3)) return rc;
+        HIP_TRY(launch_ic_ext(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
+        if (int rc = mark(4)) return rc;
+        HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
+        if (int rc = mark(5)) return rc;
+        for (const auto& l : sp.adj)
+            HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 0, st));
+        if (sp.split)
+            HIP_TRY(launch_bp_combine(sp.D, sp.it_map, sp.n_map, grid_for(sp.n_map, kGridCap), 0, st));
+        HIP_TRY(launch_ext_contract(sp.D, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+        if (int rc = mark(6)) return rc;
+        HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+        if (int rc = mark(7)) return rc;
+        HIP_TRY(launch_lb_finalize(sp.L, sp.n_slices, st));
+        return mark(8);
+    }
     // direction, trial point, its transposed copy and ||zt||^2 partials in one pass
     HIP_TRY(launch_lb_direction(sp.L, sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
     if (int rc = mark(1)) return rc;
@@ -957,6 +1199,10 @@ void set_solver_split(SliceDesc& d, LbDesc& l, void* base, const SolveLayout& S,
     l.gsplits = splits;
     l.reg_mu = d.reg_mu;
     l.reg_de = d.reg_de;
+    if (d.ext) {            // full model: the combine pass and the contraction form gt
+        l.gpart = nullptr;
+        l.gsplits = 1;
+    }
 }
 
 // Descriptors of one slice's optimiser run whose buffers start at `base` with layout S.
@@ -980,6 +1226,7 @@ void solver_descs(const eit_plan* p, const eit_opts* o, void* base, const SolveL
     l = LbDesc{};
     l.nv = p->nv; l.n = p->n; l.n_vblocks = p->n_vblocks;
     l.scale_mu = (float)o->mu_scale; l.scale_de = (float)o->delta_scale;
+    l.nn = (int64_t)p->n * p->n; l.n_maps = 2; l.scale_off = 1.f;
     l.z = (float*)at(base, S.z); l.zt = (float*)at(base, S.zt); l.g = (float*)at(base, S.g);
     l.gt = (float*)at(base, S.gt); l.d = (float*)at(base, S.d);
     l.S = (float*)at(base, S.S); l.Y = (float*)at(base, S.Y);
@@ -987,6 +1234,21 @@ void solver_descs(const eit_plan* p, const eit_opts* o, void* base, const SolveL
     l.st = state;
     l.x_user = x;
     l.cost_hist = cost_hist;
+    if (p->ext) {
+        // full model: the optimiser's vectors are parameter vectors (maps, then offsets); the
+        // update reads the contracted gradient gt, the split's parts are combined beforehand
+        set_ext_buffers(p, d, base, S.ev, (const float*)at(base, S.zt));
+        d.gu = (float*)at(base, S.gt);
+        d.off_scale = p->off_scale;
+        if (p->ext & EXT_HMODE) {
+            d.scale_de = p->gamma * o->mu_scale;
+            d.lam_de = 0.0;
+            d.reg_de = 0.0;
+        }
+        l.nv = p->nvu;
+        l.n_maps = p->n_maps;
+        l.scale_off = (float)p->off_scale;
+    }
     set_solver_split(d, l, base, S, p->adj_splits);
 }
 
@@ -1022,8 +1284,8 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     HIP_TRY(launch_store_desc(d, dd, st));
     HIP_TRY(launch_store_lbdesc(l, ld, st));
     HIP_TRY(launch_lb_init(ld, 1, o->lbfgs_m, o->max_iter, o->max_ls_trials, o->c1, o->tol_rel_step, st));
-    const int gv = grid_for(p->n_it_vec, kGridCap);
-    HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 1, st));
+    const int gv = grid_for(p->n_it_uvec, kGridCap);
+    HIP_TRY(launch_lb_scale(ld, p->it_uvec, p->n_it_uvec, gv, 1, st));
 
     StepPlan sp;
     sp.D = dd; sp.L = ld; sp.n_slices = 1;
@@ -1031,7 +1293,10 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     sp.adj.push_back({p->adj_v, p->it_bp, p->n_it_bp, 0});
     sp.it_tr = p->it_tr; sp.n_tr = p->n_it_tr;
     sp.it_ic = p->it_ic; sp.n_ic = p->n_it_ic;
-    sp.it_vec = p->it_vec; sp.n_vec = p->n_it_vec;
+    sp.it_vec = p->it_uvec; sp.n_vec = p->n_it_uvec;
+    sp.ext = p->ext != 0;
+    sp.split = p->adj_splits > 1;
+    sp.it_map = p->it_vec; sp.n_map = p->n_it_vec;
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;
@@ -1042,7 +1307,7 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     if (int rc = drive(sp, {state}, o->max_iter, o->max_ls_trials, o->use_graph != 0, key, st,
                        &launches, pt))
         return rc;
-    HIP_TRY(launch_lb_scale(ld, p->it_vec, p->n_it_vec, gv, 0, st));
+    HIP_TRY(launch_lb_scale(ld, p->it_uvec, p->n_it_uvec, gv, 0, st));
     SolverState hs;
     HIP_TRY(hipMemcpyAsync(&hs, state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1115,6 +1380,9 @@ struct BatchLayout {
     std::vector<Item> items_h;        // all work items, grouped by launch
     // item ranges (offset, count) in items_h
     std::pair<int, int> r_dir, r_ic, r_vec;
+    std::pair<int, int> r_map{0, 0};  // full model: chunks of every slice's two-map planes
+    bool ext = false;                 // full-model batch (every plan has model options)
+    bool any_split = false;
     std::vector<std::tuple<int, int, int, size_t>> r_proj, r_adj;   // variant, off, count, lds
 };
 
@@ -1124,6 +1392,11 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     if (m < 1 || m > EIT_MAX_LBFGS_M) return fail(EIT_ERR_INVALID_ARG, "lbfgs_m=%d out of range", m);
     for (int i = 0; i < n; ++i)
         if (!plans[i]) return fail(EIT_ERR_INVALID_ARG, "plans[%d] is NULL", i);
+    B.ext = plans[0]->ext != 0;
+    for (int i = 1; i < n; ++i)
+        if ((plans[i]->ext != 0) != B.ext)
+            return fail(EIT_ERR_INVALID_ARG, "plans[%d]: a batch takes either only plain plans or only "
+                        "full-model plans", i);
     B.order.resize(n);
     for (int i = 0; i < n; ++i) B.order[i] = i;
     auto work = [&](int i) { return (double)plans[i]->n * plans[i]->n * plans[i]->n_theta; };
@@ -1164,6 +1437,14 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     for (int i = 0; i < n; ++i) tiles += (long long)plans[i]->n_tx * plans[i]->n_ty;
     B.splits.resize(n);
     for (int i = 0; i < n; ++i) B.splits[i] = tiles >= kSplitTarget ? 1 : plans[i]->adj_splits;
+    B.any_split = false;
+    for (int i = 0; i < n; ++i) B.any_split = B.any_split || B.splits[i] > 1;
+    B.r_map = {(int)H.size(), 0};
+    if (B.ext && B.any_split) {
+        for (int i : B.order)
+            for (int b = 0; b < plans[i]->n_it_vec; ++b) H.push_back(make_int4(i, b, 0, 0));
+        B.r_map.second = (int)H.size() - B.r_map.first;
+    }
     for (int v = 0; v < adj_variant_count(); ++v) {
         const int off = (int)H.size();
         for (int i : B.order) {
@@ -1244,6 +1525,9 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     sp.it_tr = it + B.r_dir.first; sp.n_tr = B.r_dir.second;
     sp.it_ic = it + B.r_ic.first; sp.n_ic = B.r_ic.second;
     sp.it_vec = it_vec; sp.n_vec = n_vec;
+    sp.ext = B.ext;
+    sp.split = B.any_split;
+    sp.it_map = it + B.r_map.first; sp.n_map = B.r_map.second;
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;

@@ -80,7 +80,26 @@ struct SliceDesc {
     int32_t adj_splits, n_pairs;   // n_pairs: entries of apairs (mirror-pair adjoint only)
     const int2* apairs;            // [n_pairs] (angle, mirror angle or -1)
     double* bp_part;               // [G][2][n][n] FP64 partial sums of the adjoint (G > 1)
+    // Full model of eq. 4 (ext != 0; the plain two-map model leaves every field below zero).
+    // The unknowns form one parameter vector xu: the maps (two, or h alone in h-mode, where
+    // the evaluation runs on the expanded pair [h, h] with P_delta scaled by gamma), then the
+    // per-angle drift m_o and the per-pixel ring term m_r when fitted.
+    int32_t ext;                   // EXT_* flags
+    int32_t nq;                    // tabulated flat: samples per pixel
+    double tab_u0, tab_du;         // sample q of the table sits at u = tab_u0 + q tab_du
+    const double* ftab;            // [n_det][nq] measured flat IC (EXT_TABLE)
+    const float* xu;               // parameter vector of the evaluation point
+    float* xe;                     // [2][n][n] expanded maps (h-mode)
+    const float* off;              // offsets of the point: m_o [n_theta] then m_r [n_det]
+    double off_scale;              // raw offset = off_scale * off
+    double* g_mo;                  // [n_theta] sum over pixels of G_Delta (drift)
+    double* g_dl;                  // [n_theta][n_det] G_Delta (ring)
+    float* gu;                     // gradient in the parameter vector's layout
+    int64_t nvu;                   // entries of the parameter vector
 };
+
+// SliceDesc::ext flags.
+constexpr int EXT_HMODE = 1, EXT_DRIFT = 2, EXT_RING = 4, EXT_TABLE = 8;
 
 // Work items: (slice, a, b, c) -- meaning depends on the kernel.
 using Item = int4;
@@ -112,9 +131,12 @@ struct SolverState {
 
 // Per-slice optimiser buffers.
 struct LbDesc {
-    int64_t nv;                  // 2 n^2
+    int64_t nv;                  // entries of the optimiser's vectors (2 n^2 for the plain model)
     int32_t n, n_vblocks;
-    float scale_mu, scale_de;
+    float scale_mu, scale_de;    // z = x / scale: first map, second map (or h-mode's h alone)
+    int64_t nn;                  // n^2
+    int32_t n_maps;              // maps in the vector (2, or 1 in h-mode); offsets follow
+    float scale_off;             // scaling of the offsets (full model)
     float* z;  float* zt;  float* g;  float* gt;  float* d;
     float* S;  float* Y;         // [(m+1)][nv] each
     double* part;                // [n_vblocks][max_dots(m)]
@@ -138,6 +160,21 @@ hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int
                             hipStream_t s);
 hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s);
 hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s);
+hipError_t launch_lb_direction_vec(const LbDesc* L, const SliceDesc* D, const Item* items,
+                                   int n_items, int grid, hipStream_t s);
+
+// full model of eq. 4 (model_ext.hip)
+hipError_t launch_ext_expand(const SliceDesc* D, const Item* items, int n_items, int grid,
+                             hipStream_t s);
+hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int grid,
+                         int want_seeds, hipStream_t s);
+hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
+                               hipStream_t s);
+hipError_t launch_eq3_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,
+                               const double* kern, const double* inv_flat, int mask_index,
+                               hipStream_t s);
+hipError_t launch_ext_take_maps(const SliceDesc* D, const Item* items, int n_items, int grid,
+                                hipStream_t s);
 hipError_t launch_store_desc(const SliceDesc& v, SliceDesc* dst, hipStream_t s);
 hipError_t launch_store_lbdesc(const LbDesc& v, LbDesc* dst, hipStream_t s);
 

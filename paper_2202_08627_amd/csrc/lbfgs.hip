@@ -32,11 +32,11 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_scale(const LbDesc* __restri
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const LbDesc& l = L[w.x];
-        const int64_t half = l.nv / 2;
         const int64_t e0 = (int64_t)w.y * kVecChunk;
         const int64_t e1 = min(e0 + kVecChunk, l.nv);
+        const int64_t maps_end = l.n_maps * l.nn;
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
-            const float sc = e < half ? l.scale_mu : l.scale_de;
+            const float sc = e < l.nn ? l.scale_mu : (e < maps_end ? l.scale_de : l.scale_off);
             if (to_z) l.z[e] = l.x_user[e] / sc;
             else l.x_user[e] = l.z[e] * sc;
         }
@@ -194,6 +194,53 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
             p[1] = sq[1];
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------ direction (vector form)
+// Item (slice, chunk) over the optimiser's vector, for the full model of eq. 4 whose vector
+// (maps, then offsets) is not a pair of maps: the same direction and trial point as
+// k_lb_direction, element by element, without the fused transpose. In h-mode the trial
+// point's map is also written twice into the expanded pair D.xe the two-map kernels evaluate.
+__global__ __launch_bounds__(kVecThreads) void k_lb_direction_vec(const LbDesc* __restrict__ L,
+                                                                 const SliceDesc* __restrict__ D,
+                                                                 const Item* __restrict__ items,
+                                                                 int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const LbDesc& l = L[w.x];
+        const SliceDesc& dsc = D[w.x];
+        const SolverState& s = *l.st;
+        if (s.skip) continue;
+        const int mode = s.mode;
+        const int mc = mode == MODE_NEW_DIR ? s.m_cur : 0;
+        const double alpha = s.alpha, gamma = s.gamma;
+        const bool expand = (dsc.ext & EXT_HMODE) != 0;
+        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, l.nv);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            const float z = l.z[e];
+            float t = z;
+            if (mode != MODE_INIT) {
+                double dv;
+                if (mode == MODE_NEW_DIR) {
+                    dv = -gamma * (double)l.g[e];
+                    for (int q = 0; q < mc; ++q) {
+                        const int64_t o = (int64_t)s.order[q] * l.nv + e;
+                        dv = fma(-s.ee[q], (double)l.S[o], dv);
+                        dv = fma(s.cc[q], (double)l.Y[o], dv);
+                    }
+                    l.d[e] = (float)dv;
+                } else {
+                    dv = (double)l.d[e];
+                }
+                t = (float)fma(alpha, dv, (double)z);
+            }
+            l.zt[e] = t;
+            if (expand && e < l.nn) {
+                dsc.xe[e] = t;
+                dsc.xe[l.nn + e] = t;
+            }
+        }
     }
 }
 
@@ -419,6 +466,11 @@ hipError_t launch_lb_scale(const LbDesc* L, const Item* items, int n_items, int 
 hipError_t launch_lb_direction(const LbDesc* L, const SliceDesc* D, const Item* items, int n_items,
                                int grid, hipStream_t s) {
     k_lb_direction<<<grid, kTrThreads, 0, s>>>(L, D, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_lb_direction_vec(const LbDesc* L, const SliceDesc* D, const Item* items,
+                                   int n_items, int grid, hipStream_t s) {
+    k_lb_direction_vec<<<grid, kVecThreads, 0, s>>>(L, D, items, n_items);
     return hipGetLastError();
 }
 hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int grid,

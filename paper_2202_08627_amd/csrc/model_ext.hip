@@ -1,0 +1,258 @@
+// The paper's full forward model (theory section, eq. 4) on top of the two-map kernels:
+//   s_mod[a][j][k] = T[a][k] f_k(m_j - m_o[a] - m_r[k] - Delta[a][k]),
+// with three extensions of the plain model, each optional (SliceDesc::ext):
+//   * h-mode (homogeneous object): one map h with mu = h and delta = gamma h. The projector and
+//     the adjoint run unchanged on the expanded pair [h, h] with P_delta scaled by gamma, and
+//     the gradient is the sum of the two adjoint planes (chain rule: d/dh = d/dmu + gamma d/ddelta);
+//   * per-angle drift m_o and per-pixel ring term m_r of the sample mask: unknowns whose
+//     derivatives are sums of G_Delta = dS/dDelta over pixels (m_o) or angles (m_r), since u
+//     depends on m_o, m_r and Delta with the same coefficient;
+//   * a tabulated (measured) flat IC: F[k][q] at u_q = u0 + q du over one mask period (the
+//     experiment section scans it in 33 steps), interpolated by cubic convolution (Keys 1981,
+//     a = -1/2, continuously differentiable) and held at its end values outside the scan.
+// Also the single-shot retrieval of eq. 3 for the h-mode (one mask position).
+#include "device_common.h"
+
+namespace eit {
+
+// ------------------------------------------------------------------------ flat IC
+// (f, f') of pixel k at u: Gaussian (A, c, 1/(2 s^2), 1/s^2) or the table.
+__device__ __forceinline__ void flat_eval(const SliceDesc& d, int k, float4 fl, double u, double& f,
+                                          double& fp) {
+    if (d.ext & EXT_TABLE) {
+        const int Q = d.nq;
+        const double lo = d.tab_u0, hi = d.tab_u0 + (Q - 1) * d.tab_du;
+        const bool inside = u >= lo && u <= hi;
+        const double uc = fmin(fmax(u, lo), hi);
+        const double xq = (uc - lo) / d.tab_du;
+        const int q = min(max((int)floor(xq), 0), Q - 2);
+        const double t = xq - q, t2 = t * t, t3 = t2 * t;
+        const double* F = d.ftab + (size_t)k * Q;
+        const double f0 = F[max(q - 1, 0)], f1 = F[q], f2 = F[q + 1], f3 = F[min(q + 2, Q - 1)];
+        // Keys' cubic convolution weights of samples q-1 .. q+2 and their t-derivatives
+        const double w0 = 0.5 * (-t3 + 2.0 * t2 - t), w1 = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+        const double w2 = 0.5 * (-3.0 * t3 + 4.0 * t2 + t), w3 = 0.5 * (t3 - t2);
+        const double v0 = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0), v1 = 0.5 * (9.0 * t2 - 10.0 * t);
+        const double v2 = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0), v3 = 0.5 * (3.0 * t2 - 2.0 * t);
+        f = w0 * f0 + w1 * f1 + w2 * f2 + w3 * f3;
+        fp = inside ? (v0 * f0 + v1 * f1 + v2 * f2 + v3 * f3) / d.tab_du : 0.0;
+    } else {
+        const double uu = u - (double)fl.y;
+        f = (double)fl.x * exp(-uu * uu * (double)fl.z);
+        fp = -uu * (double)fl.w * f;
+    }
+}
+
+// ------------------------------------------------------------------------ IC model (eq. 4)
+// Item (slice, angle, -, -). As the plain IC stage (FP64 model from FP32 projections, seeds
+// in place of the projections), with the offsets of the point and the flat of the plan.
+// Also: g_mo[a] = sum_k G_Delta[a][k] (drift, fixed-order block sum) and g_dl[a][k] =
+// G_Delta[a][k] (ring; summed over angles by the contraction pass).
+constexpr int kExtIcThreads = 512;
+constexpr int kExtMaxDet = 4096;
+__global__ __launch_bounds__(kExtIcThreads) void k_ic_ext(const SliceDesc* __restrict__ D,
+                                                         const Item* __restrict__ items,
+                                                         int n_items, int want_seeds) {
+    __shared__ double gdl[kExtMaxDet];
+    __shared__ double red[kExtIcThreads / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped(d)) continue;
+        const int a = w.y, nd = d.n_det, M = d.n_mask, nt = d.n_theta;
+        float* Pm = d.P + (size_t)a * nd;
+        float* Pd = d.P + ((size_t)nt + a) * nd;
+        const float* se = d.s_exp + (size_t)a * M * nd;
+        const double sm = d.scale_mu, sdl = d.scale_de;
+        const double kap = (double)d.kappa;
+        const double mo = (d.ext & EXT_DRIFT) ? d.off_scale * (double)d.off[a] : 0.0;
+        const float* mr = (d.ext & EXT_RING) ? d.off + ((d.ext & EXT_DRIFT) ? nt : 0) : nullptr;
+        double r2 = 0.0, gsum = 0.0;
+        for (int k = threadIdx.x; k < nd; k += kExtIcThreads) {
+            const double pm = sm * (double)Pm[k];
+            const double pp = k + 1 < nd ? sdl * (double)Pd[k + 1] : 0.0;
+            const double pn = k > 0 ? sdl * (double)Pd[k - 1] : 0.0;
+            const double T = exp(-pm);
+            const double dl = kap * 0.5 * (pp - pn);
+            const double base = -mo - (mr ? d.off_scale * (double)mr[k] : 0.0) - dl;
+            const float4 fl = d.flat[k];
+            double sf = 0.0, sfp = 0.0;
+            for (int j = 0; j < M; ++j) {
+                double f, fp;
+                flat_eval(d, k, fl, d.mask[j] + base, f, fp);
+                const double r = fma(T, f, -(double)se[(size_t)j * nd + k]);
+                r2 = fma(r, r, r2);
+                sf = fma(r, f, sf);
+                sfp = fma(r, fp, sfp);
+            }
+            const double gD = -2.0 * T * sfp;                 // G_Delta
+            if (want_seeds) {
+                Pm[k] = (float)(sm * (-2.0 * T * sf));        // G_Pmu, scaled
+                gdl[k] = gD;
+                if (mr) d.g_dl[(size_t)a * nd + k] = gD;
+            }
+            gsum += gD;
+        }
+        __syncthreads();   // every read of Pd done, gdl complete
+        if (want_seeds) {
+            for (int k = threadIdx.x; k < nd; k += kExtIcThreads) {
+                const double gp = k + 1 < nd ? gdl[k + 1] : 0.0;
+                const double gn = k > 0 ? gdl[k - 1] : 0.0;
+                Pd[k] = (float)(sdl * (-kap * 0.5 * (gp - gn)));
+            }
+        }
+        r2 = block_sum(r2, red);
+        if (want_seeds && (d.ext & EXT_DRIFT)) {
+            gsum = block_sum(gsum, red);
+            if (threadIdx.x == 0) d.g_mo[a] = gsum;
+        }
+        if (threadIdx.x == 0) d.part_ic[a] = r2;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------ expansion
+// Item (slice, chunk): h-mode point [h] -> the pair [h, h] the two-map kernels evaluate.
+__global__ __launch_bounds__(kVecThreads) void k_ext_expand(const SliceDesc* __restrict__ D,
+                                                           const Item* __restrict__ items,
+                                                           int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped(d)) continue;
+        const int64_t nn = (int64_t)d.n * d.n;
+        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, nn);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            const float v = d.xu[e];
+            d.xe[e] = v;
+            d.xe[nn + e] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------ contraction
+// Item (slice, chunk) over the parameter vector: the gradient in the parameter layout from
+// the adjoint's two planes g (computed without the regulariser), the point xu and the
+// offset sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h);
+// drift: off_scale * g_mo[a]; ring: off_scale * sum_a g_dl[a][k] (angles in order).
+__global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* __restrict__ D,
+                                                             const Item* __restrict__ items,
+                                                             int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped_adj(d)) continue;
+        const int64_t nn = (int64_t)d.n * d.n;
+        const bool hm = (d.ext & EXT_HMODE) != 0;
+        const int64_t maps_end = hm ? nn : 2 * nn;
+        const int64_t mo_end = maps_end + ((d.ext & EXT_DRIFT) ? d.n_theta : 0);
+        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, d.nvu);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
+            double v;
+            if (e < maps_end) {
+                if (hm) {
+                    v = (double)d.g[e] + (double)d.g[nn + e];
+                    v = fma(d.reg_mu, (double)d.xu[e], v);
+                } else {
+                    v = fma(e < nn ? d.reg_mu : d.reg_de, (double)d.xu[e], (double)d.g[e]);
+                }
+            } else if (e < mo_end) {
+                v = d.off_scale * d.g_mo[e - maps_end];
+            } else {
+                const int k = (int)(e - mo_end);
+                double acc = 0.0;
+                for (int a = 0; a < d.n_theta; ++a) acc += d.g_dl[(size_t)a * d.n_det + k];
+                v = d.off_scale * acc;
+            }
+            d.gu[e] = (float)v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------ eq. 3 single shot
+// Item (slice, angle). h-mode with one mask position j0: r_k = s[a][j0][k] / f_k(m_j0), then
+// T = circular convolution of r with the real kernel whose DFT is 1 / (1 + i beta sin q)
+// (eq. 3 with the central difference's symbol; beta = kappa gamma f'/f of the detector-
+// averaged flat, folded into the kernel on the host), R[h] = -log(max(T, 1e-6)) into the
+// first sinogram plane, zeros into the second (the filtered backprojection follows).
+constexpr int kEq3Threads = 256;
+constexpr double kEq3TFloor = 1e-6;
+__global__ __launch_bounds__(kEq3Threads) void k_eq3_retrieve(const SliceDesc* __restrict__ D,
+                                                             const Item* __restrict__ items,
+                                                             int n_items,
+                                                             const double* __restrict__ kern,
+                                                             const double* __restrict__ inv_flat,
+                                                             int j0) {
+    __shared__ double r[kExtMaxDet];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        const int a = w.y, nd = d.n_det;
+        const float* se = d.s_exp + ((size_t)a * d.n_mask + j0) * nd;
+        __syncthreads();
+        for (int k = threadIdx.x; k < nd; k += kEq3Threads) r[k] = (double)se[k] * inv_flat[k];
+        __syncthreads();
+        float* P0 = d.P + (size_t)a * nd;
+        float* P1 = d.P + ((size_t)d.n_theta + a) * nd;
+        for (int k = threadIdx.x; k < nd; k += kEq3Threads) {
+            double T = 0.0;
+            for (int l = 0; l < nd; ++l) {
+                const int src = k - l < 0 ? k - l + nd : k - l;
+                T = fma(kern[l], r[src], T);
+            }
+            P0[k] = (float)(-log(fmax(T, kEq3TFloor)));
+            P1[k] = 0.f;
+        }
+    }
+}
+
+// Item (slice, chunk) over the parameter vector: the parameter vector of a single-shot start
+// from the backprojected planes in g: the maps (h alone in h-mode: the first plane), offsets 0.
+__global__ __launch_bounds__(kVecThreads) void k_ext_take_maps(const SliceDesc* __restrict__ D,
+                                                              const Item* __restrict__ items,
+                                                              int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        const int64_t nn = (int64_t)d.n * d.n;
+        const int64_t maps_end = (d.ext & EXT_HMODE) ? nn : 2 * nn;
+        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, d.nvu);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads)
+            d.gu[e] = e < maps_end ? d.g[e] : 0.f;
+    }
+}
+
+// ------------------------------------------------------------------------ launchers
+hipError_t launch_ext_expand(const SliceDesc* D, const Item* items, int n_items, int grid,
+                             hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_ext_expand<<<grid, kVecThreads, 0, s>>>(D, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int grid,
+                         int want_seeds, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_ic_ext<<<grid, kExtIcThreads, 0, s>>>(D, items, n_items, want_seeds);
+    return hipGetLastError();
+}
+hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
+                               hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_ext_contract<<<grid, kVecThreads, 0, s>>>(D, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_eq3_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,
+                               const double* kern, const double* inv_flat, int mask_index,
+                               hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_eq3_retrieve<<<grid, kEq3Threads, 0, s>>>(D, items, n_items, kern, inv_flat, mask_index);
+    return hipGetLastError();
+}
+hipError_t launch_ext_take_maps(const SliceDesc* D, const Item* items, int n_items, int grid,
+                                hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_ext_take_maps<<<grid, kVecThreads, 0, s>>>(D, items, n_items);
+    return hipGetLastError();
+}
+
+}  // namespace eit

@@ -60,12 +60,53 @@ class Geometry:
                    case.flat_amp, case.flat_ctr, case.flat_sigma)
 
     def c_args(self):
-        arrs = [_f64(self.theta, self.n_theta), _f64(self.mask_pos, self.n_mask),
-                _f64(self.flat_amp, self.n_det), _f64(self.flat_ctr, self.n_det),
-                _f64(self.flat_sigma, self.n_det)]
+        """(dims, setup, arrays to keep alive); Gaussian flat parameters may be None when a
+        model plan brings a measured flat table."""
+        arrs = [_f64(self.theta, self.n_theta), _f64(self.mask_pos, self.n_mask)]
+        arrs += [None if a is None else _f64(a, self.n_det)
+                 for a in (self.flat_amp, self.flat_ctr, self.flat_sigma)]
         dims = L.Dims(self.n, self.n_theta, self.n_det, self.n_mask, float(self.kappa))
         setup = L.Setup(*[L.dptr(a) for a in arrs])
         return dims, setup, arrs
+
+
+@dataclass
+class Model:
+    """Full-model options of eq. 4 (eit_model): h-mode (mu = h, delta = gamma h), fitted
+    per-angle drift and per-pixel ring offsets, a measured flat table [n_det][Q] at
+    u_q = table_u0 + q table_du."""
+    hmode: bool = False
+    gamma: float = 5.0
+    fit_drift: bool = False
+    fit_ring: bool = False
+    flat_table: np.ndarray | None = None
+    table_u0: float = -0.5
+    table_du: float = 1.0 / 32.0
+    offset_scale: float = 1.0
+    eq3_mask: int = 0
+
+    @classmethod
+    def from_case(cls, case, hmode=None, fit_drift=False, fit_ring=False, use_table=None, **kw):
+        """Options matching a simulated case: h-mode when the object is homogeneous, the
+        measured flat table when the case has one (use_table=None)."""
+        cfg = case.cfg
+        hm = cfg.gamma_h > 0 if hmode is None else hmode
+        tab = case.flat_table if (use_table is None or use_table) else None
+        return cls(hmode=hm, gamma=cfg.gamma_h if cfg.gamma_h > 0 else 5.0, fit_drift=fit_drift,
+                   fit_ring=fit_ring, flat_table=tab, table_u0=case.table_u0,
+                   table_du=case.table_du if tab is not None else 1.0 / 32.0, **kw)
+
+    def c_args(self, n_det: int):
+        tab = None
+        if self.flat_table is not None:
+            tab = np.ascontiguousarray(np.asarray(self.flat_table, dtype=np.float64))
+            if tab.ndim != 2 or tab.shape[0] != n_det:
+                raise ValueError(f"flat_table must be [n_det][Q], got {tab.shape}")
+        m = L.Model(1 if self.hmode else 0, 1 if self.fit_drift else 0, 1 if self.fit_ring else 0,
+                    0 if tab is None else tab.shape[1], float(self.gamma), L.dptr(tab),
+                    float(self.table_u0), float(self.table_du), float(self.offset_scale),
+                    int(self.eq3_mask), 0)
+        return m, tab
 
 
 def inspect(geo: Geometry, proj_variant: int = -1, adj_variant: int = -1, adj_splits: int = 0,
@@ -118,18 +159,27 @@ class Plan:
     """Owns one eit_plan (device angle/detector tables) for a slice geometry."""
 
     def __init__(self, geo: Geometry, proj_variant: int = -1, adj_variant: int = -1,
-                 adj_splits: int = 0):
-        """adj_splits: blocks per adjoint voxel tile (0 = the library's automatic choice)."""
+                 adj_splits: int = 0, model: Model | None = None):
+        """adj_splits: blocks per adjoint voxel tile (0 = the library's automatic choice).
+        model: full-model options of eq. 4 (None: the plain two-map model)."""
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
         self.geo = geo
+        self.model = model
         dims, setup, keep = geo.c_args()
         til = L.Tiling(proj_variant, adj_variant, adj_splits)
         h = C.c_void_p()
         torch.cuda.current_device()
-        L.check(L.lib().eit_plan_create(C.byref(dims), C.byref(setup), C.byref(til), C.byref(h)))
+        if model is None:
+            L.check(L.lib().eit_plan_create(C.byref(dims), C.byref(setup), C.byref(til), C.byref(h)))
+        else:
+            m, tab = model.c_args(geo.n_det)
+            L.check(L.lib().eit_plan_create_model(C.byref(dims), C.byref(setup), C.byref(m),
+                                                  C.byref(til), C.byref(h)))
+            del tab
         del keep
         self._h = h
+        self.n_params = int(L.lib().eit_param_count(h))
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
@@ -157,6 +207,12 @@ class Plan:
     @property
     def x_shape(self):
         return (2, self.geo.n, self.geo.n)
+
+    @property
+    def param_shape(self):
+        """Shape of x / gradient / reconstruction: [2][n][n] for the plain model, the flat
+        parameter vector (maps, then offsets) for a model plan."""
+        return self.x_shape if self.model is None else (self.n_params,)
 
     @property
     def sino_shape(self):
@@ -193,11 +249,11 @@ class Plan:
 
     def cost_and_grad(self, x, s_exp, lam_mu: float, lam_delta: float, want_grad: bool = True,
                       ws=None):
-        """(cost as a 0-d float64 device tensor, gradient [2][n][n] or None)."""
-        _require(x, self.x_shape, name="x")
+        """(cost as a 0-d float64 device tensor, gradient of param_shape or None)."""
+        _require(x, self.param_shape, name="x")
         _require(s_exp, self.data_shape, name="s_exp")
         cost = torch.empty((), dtype=torch.float64, device=x.device)
-        grad = torch.empty(self.x_shape, dtype=torch.float32, device=x.device) if want_grad else None
+        grad = torch.empty(self.param_shape, dtype=torch.float32, device=x.device) if want_grad else None
         ws = self.workspace(L.EIT_OP_COST_GRAD) if ws is None else ws
         L.check(L.lib().eit_cost_and_grad(self.handle, _ptr(x), _ptr(s_exp), float(lam_mu),
                                           float(lam_delta), _ptr(cost), _ptr(grad), _ptr(ws),
@@ -205,9 +261,9 @@ class Plan:
         return cost, grad
 
     def single_shot(self, s_exp, out=None, ws=None):
-        """Single-shot (retrieve + filtered backprojection) reconstruction [2][n][n]."""
+        """Single-shot (retrieve + filtered backprojection) reconstruction of param_shape."""
         _require(s_exp, self.data_shape, name="s_exp")
-        out = torch.empty(self.x_shape, dtype=torch.float32, device=s_exp.device) if out is None else out
+        out = torch.empty(self.param_shape, dtype=torch.float32, device=s_exp.device) if out is None else out
         ws = self.workspace(L.EIT_OP_SINGLE_SHOT) if ws is None else ws
         L.check(L.lib().eit_single_shot(self.handle, _ptr(s_exp), _ptr(out), _ptr(ws), ws.numel(),
                                         _stream()))
@@ -220,9 +276,9 @@ class Plan:
         """L-BFGS reconstruction; returns (x_K, report dict, cost history or None)."""
         _require(s_exp, self.data_shape, name="s_exp")
         if x0 is None:
-            x = torch.zeros(self.x_shape, dtype=torch.float32, device=s_exp.device)
+            x = torch.zeros(self.param_shape, dtype=torch.float32, device=s_exp.device)
         else:
-            _require(x0, self.x_shape, name="x0")
+            _require(x0, self.param_shape, name="x0")
             x = x0.clone()
         hist = torch.zeros(iters + 1, dtype=torch.float64, device=s_exp.device) if cost_hist else None
         opts = L.Opts(iters, m, max_ls, 1 if use_graph else 0, lam, mu_scale, delta_scale,
@@ -302,3 +358,34 @@ class EITCost(torch.autograd.Function):
 
 def eit_cost(x, s_exp, plan: Plan, lam_mu: float, lam_delta: float):
     return EITCost.apply(x, s_exp, plan, lam_mu, lam_delta)
+
+
+def frc(a, b, cutoff: float = 0.5, sigma: float = 1.0):
+    """Fourier ring correlation (eq. 6) of two n x n device images on the device: (curve,
+    smoothed curve, resolution in pixels, crossing ring), the curves as float64 device tensors."""
+    n = int(a.shape[-1])
+    _require(a, (n, n), name="a")
+    _require(b, (n, n), name="b")
+    nr = n // 2 + 1
+    curve = torch.empty(nr, dtype=torch.float64, device=a.device)
+    smooth = torch.empty(nr, dtype=torch.float64, device=a.device)
+    res = torch.empty(2, dtype=torch.float64, device=a.device)
+    nb = int(L.lib().eit_frc_workspace_bytes(n))
+    if nb == 0:
+        L.check(L.EIT_ERR_SHAPE)
+    ws = torch.empty(nb, dtype=torch.uint8, device=a.device)
+    L.check(L.lib().eit_frc(n, _ptr(a), _ptr(b), _ptr(curve), _ptr(smooth), _ptr(res), float(cutoff),
+                            float(sigma), _ptr(ws), nb, _stream()))
+    r = res.cpu()
+    return curve, smooth, float(r[0]), float(r[1])
+
+
+def cnr(img, c1, c2, rho: float) -> float:
+    """Contrast-to-noise ratio (eq. 7) between two discs of radius rho (centred coordinates)
+    of an n x n device image, computed on the device."""
+    n = int(img.shape[-1])
+    _require(img, (n, n), name="img")
+    out = torch.empty(1, dtype=torch.float64, device=img.device)
+    L.check(L.lib().eit_cnr(n, _ptr(img), float(c1[0]), float(c1[1]), float(c2[0]), float(c2[1]),
+                            float(rho), _ptr(out), _stream()))
+    return float(out.cpu()[0])
