@@ -239,6 +239,21 @@ int eit_cost_and_grad(const eit_plan* plan, const float* x, const float* s_exp, 
  * and the model is eq. 4 with the plan's options; in h-mode lam_mu weights ||h||^2 and
  * lam_delta is unused; the offsets are not regularised. */
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): eit_cost_and_grad with its scratch
+ * buffers in a static device array of EIT_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, instead of a caller workspace. Same
+ * arguments and results as eit_cost_and_grad (same kernels and buffer layout, so the outputs
+ * are identical). Calls nothing that allocates. Returns EIT_ERR_NOMEM, before enqueueing
+ * anything, when eit_workspace_bytes(plan, EIT_OP_COST_GRAD, 0) exceeds the limit (e.g.
+ * 1024^2 / 1800 angles with a split adjoint), EIT_ERR_DEVICE if the array's device address
+ * cannot be looked up. All calls on one GPU share the array: calls that overlap on one GPU
+ * (two streams, two threads) race and must be serialised by the caller. */
+#define EIT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int eit_cost_and_grad_noalloc(const eit_plan* plan, const float* x, const float* s_exp,
+                              double lam_mu, double lam_delta, double* cost_dev, float* grad,
+                              void* stream);
+
 /* Non-iterative reconstruction (the paper's single-shot route: retrieve each projection
  * pixel, then filtered backprojection), used as the start of the learned warm start.
  * With several mask positions per IC both channels are retrieved per pixel: a weighted

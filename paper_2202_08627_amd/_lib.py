@@ -101,6 +101,7 @@ _PROTOS = {
     "eit_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(VP), C.c_int32]),
     "eit_reconstruct_batch": (C.c_int, [C.c_int32, C.POINTER(VP), C.POINTER(VP), C.POINTER(VP),
                                         C.POINTER(Opts), C.POINTER(Report), VP, C.c_size_t, VP]),
+    "eit_cost_and_grad_noalloc": (C.c_int, [VP, VP, VP, C.c_double, C.c_double, VP, VP, VP]),
     "eit_single_shot": (C.c_int, [VP, VP, VP, VP, C.c_size_t, VP]),
     "eit_frc_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "eit_frc": (C.c_int, [C.c_int32, VP, VP, VP, VP, VP, C.c_double, C.c_double, VP, C.c_size_t, VP]),

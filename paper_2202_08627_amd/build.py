@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeitomo.so")
 SOURCES = ["kernels.hip", "lbfgs.hip", "single_shot.hip", "nn_kernels.hip", "nn_misc.hip",
-           "unet.cpp", "api.cpp", "model_ext.hip", "quality.hip"]
+           "unet.cpp", "api.cpp", "noalloc.hip", "model_ext.hip", "quality.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EIT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
