@@ -408,7 +408,7 @@ def paper220_main(args, log):
     t = time.perf_counter() - t0
     _, prep, _ = plan.reconstruct(s_exp, iters=args.steps, profile=True, **kw)
     rows = experiment.table2(cfg, log=log)
-    frc = experiment.resolution_comparison(cfg, log=log)
+    frc = [experiment.resolution_comparison(cfg, counts=c, log=log) for c in (cfg.counts, 1e3)]
     line = {
         "metric": "slice-iters/s (220^2, 400 angles over 360 deg, M = 1, h-mode)",
         "value": round(rep["iters"] / t, 2), "unit": "slice-iters/s", "n_gpus": 1,

@@ -143,11 +143,13 @@ WARMSTART = WarmStartConfig()
 # The paper's own acquisition (experiment section): homogeneous object (mu = h, delta = gamma h,
 # gamma = 5), one mask position on the slope of the IC, 400 projections over 360 degrees, a
 # 220^2 grid, lambda = 1e-2. The IC is narrower than the plain workloads' (sigma 0.3 period,
-# the position m = 0.3 on its steepest slope) and kappa = 1, so that the refraction shifts of
-# the granule-like phantom stay within the scanned period; the flat IC is measured over one
-# period in 33 steps (1 or 20 flat scans) and the mask drifts by up to 0.02 period.
+# the position m = 0.3 on its steepest slope) and kappa = 0.3, so that the refraction shifts
+# of the granule-like phantom stay near 0.1 period (with kappa = 1 they reach a period at
+# object edges, where the central-difference model cannot follow the data); the flat IC is
+# measured over one period in 33 steps (1 or 20 flat scans) and the mask drifts by up to
+# 0.02 period.
 PAPER_220 = SliceConfig(n=220, n_theta=400, n_det=220, n_mask=1, phantom="random",
-                        n_ellipses=12, axis_max=0.3, sigma=0.3, sigma_jitter=0.05, kappa=1.0,
+                        n_ellipses=12, axis_max=0.3, sigma=0.3, sigma_jitter=0.05, kappa=0.3,
                         iters=100, mu_scale=0.05 * 64 / 220, angle_span=2.0, mask_list=(0.3,),
                         gamma_h=5.0, flat_scans=20, n_table=33, drift_amp=0.02)
 

@@ -128,7 +128,8 @@ struct eit_plan {
     double* eq3_invf = nullptr;   // [n_det] 1 / f_k(m_j0)
     Item* it_uvec = nullptr;      // chunks of the parameter vector
     Item* it_hvec = nullptr;      // chunks of one map
-    int n_it_uvec = 0, n_it_hvec = 0;
+    Item* it_ring = nullptr;      // pixel blocks of the ring term's gradient
+    int n_it_uvec = 0, n_it_hvec = 0, n_it_ring = 0;
 };
 
 namespace {
@@ -146,7 +147,7 @@ void free_plan(eit_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->apairs, p->flat, p->mask,
                     p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec, p->ftab, p->eq3_kern,
-                    p->eq3_invf, p->it_uvec, p->it_hvec};
+                    p->eq3_invf, p->it_uvec, p->it_hvec, p->it_ring};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -227,7 +228,7 @@ struct HostTables {
     std::vector<double> maskd;
     std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
     std::vector<double> ftab, eq3_kern, eq3_invf;
-    std::vector<Item> it_uvec, it_hvec;
+    std::vector<Item> it_uvec, it_hvec, it_ring;
 };
 
 // Cubic-convolution value and slope (Keys 1981, a = -1/2) of a tabulated flat row F[0..Q) at u,
@@ -512,6 +513,10 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
     for (int b = 0; b < hb; ++b) h.it_hvec.push_back(make_int4(0, b, 0, 0));
     p->n_it_uvec = (int)h.it_uvec.size();
     p->n_it_hvec = hb;
+    if (p->ext & EXT_RING)
+        for (int b = 0; b < (nd + kRingPixPerItem - 1) / kRingPixPerItem; ++b)
+            h.it_ring.push_back(make_int4(0, b, 0, 0));
+    p->n_it_ring = (int)h.it_ring.size();
     return EIT_OK;
 }
 
@@ -542,7 +547,8 @@ int create_plan(const eit_dims* dims, const eit_setup* setup, const eit_model* m
         (rc = upload(&p->it_ic, h.it_ic)) || (rc = upload(&p->it_bp, h.it_bp)) ||
         (rc = upload(&p->it_vec, h.it_vec)) || (rc = upload(&p->ftab, h.ftab)) ||
         (rc = upload(&p->eq3_kern, h.eq3_kern)) || (rc = upload(&p->eq3_invf, h.eq3_invf)) ||
-        (rc = upload(&p->it_uvec, h.it_uvec)) || (rc = upload(&p->it_hvec, h.it_hvec))) {
+        (rc = upload(&p->it_uvec, h.it_uvec)) || (rc = upload(&p->it_hvec, h.it_hvec)) ||
+        (rc = upload(&p->it_ring, h.it_ring))) {
         free_plan(p);
         return rc;
     }
@@ -834,6 +840,7 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
         if (!grad) return EIT_OK;
         if (int rc = enqueue_backproject(p, dd, 0, st)) return rc;
         HIP_TRY(launch_ext_contract(dd, p->it_uvec, p->n_it_uvec, grid_for(p->n_it_uvec, kGridCap), st));
+        HIP_TRY(launch_ext_ring_grad(dd, p->it_ring, p->n_it_ring, grid_for(p->n_it_ring, kGridCap), st));
         return EIT_OK;
     }
     HIP_TRY(launch_store_desc(d, dd, st));
@@ -915,6 +922,7 @@ struct StepPlan {
     bool ext = false;
     bool split = false;
     const Item* it_map = nullptr; int n_map = 0;   // chunks of the two-map planes
+    const Item* it_ring = nullptr; int n_ring = 0; // pixel blocks of ring-term gradients
 };
 
 // ev: optional array of EIT_N_PHASES + 1 events recorded around the phases.
@@ -941,6 +949,7 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
         if (sp.split)
             HIP_TRY(launch_bp_combine(sp.D, sp.it_map, sp.n_map, grid_for(sp.n_map, kGridCap), 0, st));
         HIP_TRY(launch_ext_contract(sp.D, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+        HIP_TRY(launch_ext_ring_grad(sp.D, sp.it_ring, sp.n_ring, grid_for(sp.n_ring, kGridCap), st));
         if (int rc = mark(6)) return rc;
         HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
         if (int rc = mark(7)) return rc;
@@ -1297,6 +1306,7 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     sp.ext = p->ext != 0;
     sp.split = p->adj_splits > 1;
     sp.it_map = p->it_vec; sp.n_map = p->n_it_vec;
+    sp.it_ring = p->it_ring; sp.n_ring = p->n_it_ring;
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;
@@ -1381,6 +1391,7 @@ struct BatchLayout {
     // item ranges (offset, count) in items_h
     std::pair<int, int> r_dir, r_ic, r_vec;
     std::pair<int, int> r_map{0, 0};  // full model: chunks of every slice's two-map planes
+    std::pair<int, int> r_ring{0, 0}; // full model: pixel blocks of ring-term gradients
     bool ext = false;                 // full-model batch (every plan has model options)
     bool any_split = false;
     std::vector<std::tuple<int, int, int, size_t>> r_proj, r_adj;   // variant, off, count, lds
@@ -1445,6 +1456,10 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
             for (int b = 0; b < plans[i]->n_it_vec; ++b) H.push_back(make_int4(i, b, 0, 0));
         B.r_map.second = (int)H.size() - B.r_map.first;
     }
+    B.r_ring = {(int)H.size(), 0};
+    for (int i : B.order)
+        for (int b = 0; b < plans[i]->n_it_ring; ++b) H.push_back(make_int4(i, b, 0, 0));
+    B.r_ring.second = (int)H.size() - B.r_ring.first;
     for (int v = 0; v < adj_variant_count(); ++v) {
         const int off = (int)H.size();
         for (int i : B.order) {
@@ -1528,6 +1543,7 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     sp.ext = B.ext;
     sp.split = B.any_split;
     sp.it_map = it + B.r_map.first; sp.n_map = B.r_map.second;
+    sp.it_ring = it + B.r_ring.first; sp.n_ring = B.r_ring.second;
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;

@@ -170,6 +170,9 @@ hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int
                          int want_seeds, hipStream_t s);
 hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
                                hipStream_t s);
+hipError_t launch_ext_ring_grad(const SliceDesc* D, const Item* items, int n_items, int grid,
+                                hipStream_t s);
+constexpr int kRingPixPerItem = 64;     // pixels per item of launch_ext_ring_grad
 hipError_t launch_eq3_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,
                                const double* kern, const double* inv_flat, int mask_index,
                                hipStream_t s);

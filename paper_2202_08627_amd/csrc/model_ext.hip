@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_expand(const SliceDesc* __r
 // Item (slice, chunk) over the parameter vector: the gradient in the parameter layout from
 // the adjoint's two planes g (computed without the regulariser), the point xu and the
 // offset sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h);
-// drift: off_scale * g_mo[a]; ring: off_scale * sum_a g_dl[a][k] (angles in order).
+// drift: off_scale * g_mo[a]. The ring entries are written by k_ext_ring_grad.
 __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* __restrict__ D,
                                                              const Item* __restrict__ items,
                                                              int n_items) {
@@ -159,13 +159,43 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* _
             } else if (e < mo_end) {
                 v = d.off_scale * d.g_mo[e - maps_end];
             } else {
-                const int k = (int)(e - mo_end);
-                double acc = 0.0;
-                for (int a = 0; a < d.n_theta; ++a) acc += d.g_dl[(size_t)a * d.n_det + k];
-                v = d.off_scale * acc;
+                continue;                                      // ring term: k_ext_ring_grad
             }
             d.gu[e] = (float)v;
         }
+    }
+}
+
+// Item (slice, pixel block): the ring term's gradient off_scale * sum_a g_dl[a][k] for 64
+// pixels k; the block's four wavefronts take every fourth angle (coalesced rows of g_dl) and
+// their partial sums are added in wavefront order.
+constexpr int kRingThreads = 256, kRingPix = 64;
+__global__ __launch_bounds__(kRingThreads) void k_ext_ring_grad(const SliceDesc* __restrict__ D,
+                                                               const Item* __restrict__ items,
+                                                               int n_items) {
+    __shared__ double part[kRingThreads / kRingPix][kRingPix];
+    const int lane = threadIdx.x % kRingPix, wv = threadIdx.x / kRingPix;
+    constexpr int NW = kRingThreads / kRingPix;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const SliceDesc& d = D[w.x];
+        if (skipped_adj(d) || !(d.ext & EXT_RING)) continue;
+        const int nd = d.n_det, nt = d.n_theta;
+        const int k = w.y * kRingPix + lane;
+        double acc = 0.0;
+        if (k < nd)
+            for (int a = wv; a < nt; a += NW) acc += d.g_dl[(size_t)a * nd + k];
+        part[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && k < nd) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) v += part[q][lane];
+            const int64_t nn = (int64_t)d.n * d.n;
+            const int64_t base = ((d.ext & EXT_HMODE) ? nn : 2 * nn) + ((d.ext & EXT_DRIFT) ? nt : 0);
+            d.gu[base + k] = (float)(d.off_scale * v);
+        }
+        __syncthreads();
     }
 }
 
@@ -239,6 +269,12 @@ hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_item
                                hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     k_ext_contract<<<grid, kVecThreads, 0, s>>>(D, items, n_items);
+    return hipGetLastError();
+}
+hipError_t launch_ext_ring_grad(const SliceDesc* D, const Item* items, int n_items, int grid,
+                                hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_ext_ring_grad<<<grid, kRingThreads, 0, s>>>(D, items, n_items);
     return hipGetLastError();
 }
 hipError_t launch_eq3_retrieve(const SliceDesc* D, const Item* items, int n_items, int grid,

@@ -136,10 +136,13 @@ def table2(cfg=configs.PAPER_220, n_slices: int = 75, z: int | None = None, k_ma
 
 
 def resolution_comparison(cfg=configs.PAPER_220, n_slices: int = 75, z: int | None = None,
-                          k_max: int = 3000, log=print):
+                          k_max: int = 3000, counts: float | None = None, log=print):
     """FRC resolution (eq. 6) of the iterative solution and of the eq. 3 single shot, from two
-    independent noise realisations of slice z (20 flat scans, drift fitted, no ring term)."""
+    independent noise realisations of slice z (20 flat scans, drift fitted, no ring term),
+    at the configuration's photon count or at `counts`."""
     z = n_slices // 2 if z is None else z
+    if counts is not None:
+        cfg = dataclasses.replace(cfg, counts=counts)
     it_imgs, ss_imgs = [], []
     for noise in (101, 202):
         cases, _ = synth.make_stack(cfg, n_slices, noise_seed=noise)
@@ -152,7 +155,7 @@ def resolution_comparison(cfg=configs.PAPER_220, n_slices: int = 75, z: int | No
         plan.close()
     _, _, r_it, _ = ops.frc(*it_imgs)
     _, _, r_ss, _ = ops.frc(*ss_imgs)
-    out = {"iterative_px": round(r_it, 3), "single_shot_px": round(r_ss, 3),
+    out = {"counts": cfg.counts, "iterative_px": round(r_it, 3), "single_shot_px": round(r_ss, 3),
            "iterative_over_single_shot": round(r_it / r_ss, 4)}
     log(f"# FRC resolution: {out}")
     return out

@@ -310,9 +310,9 @@ def reconstruct_batch(plans, s_exps, x0s=None, iters: int = 50, lam: float = 1e-
     for i, (p, s) in enumerate(zip(plans, s_exps)):
         _require(s, p.data_shape, name=f"s_exps[{i}]")
         if x0s is None:
-            xs.append(torch.zeros(p.x_shape, dtype=torch.float32, device=s.device))
+            xs.append(torch.zeros(p.param_shape, dtype=torch.float32, device=s.device))
         else:
-            _require(x0s[i], p.x_shape, name=f"x0s[{i}]")
+            _require(x0s[i], p.param_shape, name=f"x0s[{i}]")
             xs.append(x0s[i].clone())
     H = (C.c_void_p * n)(*[p.handle for p in plans])
     SP = (C.c_void_p * n)(*[s.data_ptr() for s in s_exps])

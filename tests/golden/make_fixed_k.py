@@ -7,7 +7,7 @@ path. Each fixture holds x_K (stored FP32: the parity bound is 1e-3 relative L2,
 storage adds ~1e-7), the per-iteration trace (accepted cost, step length, trials) and the
 run's settings.
 
-    python tests/golden/make_fixed_k.py slice512       # 512^2 / 720 / M = 8, K = 100
+    python tests/golden/make_fixed_k.py slice512 [K ...]  # 512^2 / 720 / M = 8, x_K (default K = 100)
     python tests/golden/make_fixed_k.py batch_classes  # one slice per batch size class, K = 5
 
 The optimiser reading (theory section: L-BFGS through SciPy, settings unstated) is the
@@ -56,14 +56,21 @@ def batch_class_slices(per_class: int = 1):
     return [item for k in sorted(out) for item in out[k]]
 
 
-def run_oracle(case, lam, mu_scale, delta_scale, iters, m=10):
+def run_oracle(case, lam, mu_scale, delta_scale, iters, m=10, snapshots=(), on_snapshot=None):
+    """The oracle's run from zero; x at each iteration count in `snapshots` is passed to
+    on_snapshot(k, x, state) on the way."""
     cfg = case.cfg
     geo = omodel.Geometry(cfg.n, case.theta, cfg.n_det, case.mask_pos, case.flat_amp,
                           case.flat_ctr, case.flat_sigma, cfg.kappa)
     prob = omodel.ScaledProblem(case.s_exp, geo, lam, mu_scale, delta_scale)
     t0 = time.time()
-    x, st, tr = olbfgs.reconstruct(prob, np.zeros((2, cfg.n, cfg.n)), iters, m=m)
-    return x, st, tr, time.time() - t0
+
+    def cb(st):
+        if st.k in snapshots and on_snapshot is not None:
+            on_snapshot(st.k, prob.to_x(st.z), st)
+    z, st, tr = olbfgs.minimize(prob, prob.to_z(np.zeros((2, cfg.n, cfg.n))), iters, m=m,
+                                callback=cb)
+    return prob.to_x(z), st, tr, time.time() - t0
 
 
 def save(path, x, st, tr, meta):
@@ -74,16 +81,40 @@ def save(path, x, st, tr, meta):
     print(f"wrote {path}: {meta}", flush=True)
 
 
-def make_slice512(iters=100):
+def make_slice512(iters=100, snapshots=(), out_dir=HERE):
+    """x_iters of the benchmark slice (slice512_k<iters>.npz), and x_k for every k in
+    snapshots on the way (slice512_k<k>.npz)."""
     cfg = configs.SLICE_512
     case = synth.make_case(cfg)
-    x, st, tr, dt = run_oracle(case, cfg.lam, cfg.mu_scale, cfg.delta_scale, iters)
-    meta = dict(workload="512x512, 720 angles, 512 detector pixels, M=8, Shepp-Logan-style "
-                "phantom, seed 0, Poisson 1e4, from zero", n=cfg.n, n_theta=cfg.n_theta,
-                n_mask=cfg.n_mask, seed=cfg.seed, iters=iters, m=10, lam=cfg.lam,
-                mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale, oracle_s=round(dt, 1),
-                command="python tests/golden/make_fixed_k.py slice512")
-    save(os.path.join(HERE, "slice512_k100.npz"), x, st, tr, meta)
+    t0 = time.time()
+
+    def meta_for(k, dt):
+        return dict(workload="512x512, 720 angles, 512 detector pixels, M=8, Shepp-Logan-style "
+                    "phantom, seed 0, Poisson 1e4, from zero", n=cfg.n, n_theta=cfg.n_theta,
+                    n_mask=cfg.n_mask, seed=cfg.seed, iters=k, m=10, lam=cfg.lam,
+                    mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale, oracle_s=round(dt, 1),
+                    command=f"python tests/golden/make_fixed_k.py slice512 {k}")
+
+    class _Tr:      # trace prefix of a snapshot
+        def __init__(self, tr, k):
+            self.cost, self.alpha, self.trials, self.status = tr.cost[:k], tr.alpha[:k], tr.trials[:k], 0
+
+    trace = olbfgs.Trace()
+
+    def snap(k, x, st):
+        save(os.path.join(out_dir, f"slice512_k{k}.npz"), x, st, _Tr(trace, k), meta_for(k, time.time() - t0))
+    cfg_case = case
+    geo = omodel.Geometry(cfg.n, cfg_case.theta, cfg.n_det, cfg_case.mask_pos, cfg_case.flat_amp,
+                          cfg_case.flat_ctr, cfg_case.flat_sigma, cfg.kappa)
+    prob = omodel.ScaledProblem(cfg_case.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
+
+    def cb(st):
+        if st.k in snapshots:
+            snap(st.k, prob.to_x(st.z), st)
+    z, st, tr = olbfgs.minimize(prob, prob.to_z(np.zeros((2, cfg.n, cfg.n))), iters, m=10,
+                                trace=trace, callback=cb)
+    save(os.path.join(out_dir, f"slice512_k{iters}.npz"), prob.to_x(z), st, tr,
+         meta_for(iters, time.time() - t0))
 
 
 def make_batch_classes(iters=5):
@@ -100,4 +131,8 @@ def make_batch_classes(iters=5):
 
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "slice512"
-    {"slice512": make_slice512, "batch_classes": make_batch_classes}[what]()
+    if what == "slice512":
+        ks = [int(a) for a in sys.argv[2:]] or [100]
+        make_slice512(max(ks), snapshots=tuple(k for k in ks if k != max(ks)))
+    else:
+        make_batch_classes()

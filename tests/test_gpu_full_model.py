@@ -156,3 +156,30 @@ def test_eq3_single_shot_parity(ops, cfg, use_table):
     say(f"eq. 3 single shot {cfg.n}^2 table={use_table}: rel-L2 {e:.2e}")
     assert e < 1e-4
     assert np.all(out[nn:] == 0.0)
+
+
+def test_model_batch_equals_single_slice_runs(ops):
+    """Model plans of different options in one batch (h-mode with drift and ring, h-mode with
+    drift, two maps with drift and a table): each slice equals its own run bitwise; a batch
+    mixing plain and model plans is refused."""
+    cases, _ = synth.make_stack(dataclasses.replace(SMALL_H, n=40, n_det=44), 3, n_granules=4)
+    opts = [dict(hmode=True, fit_drift=True, fit_ring=True), dict(hmode=True, fit_drift=True),
+            dict(hmode=True, fit_ring=True, use_table=False)]
+    plans = [ops.Plan(ops.Geometry.from_case(c), model=ops.Model.from_case(c, **o))
+             for c, o in zip(cases, opts)]
+    two = synth.make_case(dataclasses.replace(SMALL_EXT, n=36, n_theta=50, n_det=36))
+    plans.append(ops.Plan(ops.Geometry.from_case(two), adj_splits=2,
+                          model=ops.Model.from_case(two, hmode=False, fit_drift=True)))
+    s = [dev(c.s_exp) for c in cases] + [dev(two.s_exp)]
+    kw = dict(iters=15, lam=1e-2, mu_scale=SMALL_H.mu_scale, delta_scale=1e-3)
+    xs, reps = ops.reconstruct_batch(plans, s, **kw)
+    for i, (p, si) in enumerate(zip(plans, s)):
+        x1, r1, _ = p.reconstruct(si, **kw)
+        assert reps[i]["status"] == 0 and reps[i]["iters"] == 15, (i, reps[i])
+        assert r1["evals"] == reps[i]["evals"]
+        assert torch.equal(x1, xs[i]), i
+    plain = ops.Plan(ops.Geometry.from_case(two))
+    from paper_2202_08627_amd import _lib as L
+    with pytest.raises(L.EitError) as e:
+        ops.reconstruct_batch([plans[0], plain], [s[0], dev(two.s_exp)], iters=2)
+    assert e.value.code == L.EIT_ERR_INVALID_ARG
