@@ -407,8 +407,10 @@ def paper220_main(args, log):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     _, prep, _ = plan.reconstruct(s_exp, iters=args.steps, profile=True, **kw)
-    rows = experiment.table2(cfg, log=log)
-    frc = [experiment.resolution_comparison(cfg, counts=c, log=log) for c in (cfg.counts, 1e3)]
+    rows = frc = None
+    if not args.no_experiment:
+        rows = experiment.table2(cfg, log=log)
+        frc = [experiment.resolution_comparison(cfg, counts=c, log=log) for c in (cfg.counts, 1e3)]
     line = {
         "metric": "slice-iters/s (220^2, 400 angles over 360 deg, M = 1, h-mode)",
         "value": round(rep["iters"] / t, 2), "unit": "slice-iters/s", "n_gpus": 1,
@@ -527,6 +529,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-host-baseline", action="store_true",
                     help="skip the oracle run on every host core")
+    ap.add_argument("--no-experiment", action="store_true",
+                    help="paper220: time the iterations only (no Table 2 columns, no FRC)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain 256 MiB device copy (HBM counter scaling)")
     ap.add_argument("--cpu-evals", type=int, default=2)

@@ -9,7 +9,7 @@ partial sums are added by the update pass instead of a separate one, and the cho
 fastest per evaluation there. `tiling_for(geo)` returns the cached (projector variant,
 adjoint variant, adjoint split), or (-1, -1, 0) = library defaults.
 
-    python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json]
+    python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json] [--angle-span 2]
 """
 from __future__ import annotations
 
@@ -179,9 +179,10 @@ def tune_and_store(geo, path: str = DEFAULT_CACHE, reps: int = 20, verbose: bool
     return rec
 
 
-def geometry_for(n: int, n_theta: int, n_det: int | None = None, n_mask: int = 8):
+def geometry_for(n: int, n_theta: int, n_det: int | None = None, n_mask: int = 8,
+                 angle_span: float = 1.0):
     nd = n if n_det is None else n_det
-    return ops.Geometry(n, n_theta, nd, n_mask, 10.0, synth.angles(n_theta),
+    return ops.Geometry(n, n_theta, nd, n_mask, 10.0, synth.angles(n_theta, angle_span),
                         synth.mask_positions(n_mask), np.ones(nd), np.zeros(nd), np.full(nd, 0.6))
 
 
@@ -191,9 +192,11 @@ def main():
     ap.add_argument("--n-theta", type=int, nargs="+", default=[720])
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--angle-span", type=float, default=1.0,
+                    help="angles a * span * pi / n_theta (2 for 360 degrees)")
     a = ap.parse_args()
     for n, nt in zip(a.n, a.n_theta):
-        geo = geometry_for(n, nt)
+        geo = geometry_for(n, nt, angle_span=a.angle_span)
         print(f"tuning {size_key(geo)}", flush=True)
         rec = tune_and_store(geo, a.cache, a.reps)
         print(json.dumps(rec), flush=True)

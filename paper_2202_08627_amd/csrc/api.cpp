@@ -835,7 +835,7 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
         HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
                                p->proj_lds, st));
         HIP_TRY(launch_ic_ext(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap),
-                              grad ? 1 : 0, st));
+                              grad ? 1 : 0, p->n_det, st));
         HIP_TRY(launch_cost_reduce(dd, 1, st));
         if (!grad) return EIT_OK;
         if (int rc = enqueue_backproject(p, dd, 0, st)) return rc;
@@ -923,6 +923,7 @@ struct StepPlan {
     bool split = false;
     const Item* it_map = nullptr; int n_map = 0;   // chunks of the two-map planes
     const Item* it_ring = nullptr; int n_ring = 0; // pixel blocks of ring-term gradients
+    int max_det = 0;                               // widest slice (n_det) of the launch
 };
 
 // ev: optional array of EIT_N_PHASES + 1 events recorded around the phases.
@@ -940,7 +941,7 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
         for (const auto& l : sp.proj)
             HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
         if (int rc = mark(3)) return rc;
-        HIP_TRY(launch_ic_ext(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
+        HIP_TRY(launch_ic_ext(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, sp.max_det, st));
         if (int rc = mark(4)) return rc;
         HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
         if (int rc = mark(5)) return rc;
@@ -1307,6 +1308,7 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     sp.split = p->adj_splits > 1;
     sp.it_map = p->it_vec; sp.n_map = p->n_it_vec;
     sp.it_ring = p->it_ring; sp.n_ring = p->n_it_ring;
+    sp.max_det = p->n_det;
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;
@@ -1544,6 +1546,7 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     sp.split = B.any_split;
     sp.it_map = it + B.r_map.first; sp.n_map = B.r_map.second;
     sp.it_ring = it + B.r_ring.first; sp.n_ring = B.r_ring.second;
+    for (int i = 0; i < n; ++i) sp.max_det = std::max(sp.max_det, plans[i]->n_det);
     int launches = 0;
     PhaseTimer timer;
     PhaseTimer* pt = o->profile ? &timer : nullptr;

@@ -167,7 +167,7 @@ hipError_t launch_lb_direction_vec(const LbDesc* L, const SliceDesc* D, const It
 hipError_t launch_ext_expand(const SliceDesc* D, const Item* items, int n_items, int grid,
                              hipStream_t s);
 hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int grid,
-                         int want_seeds, hipStream_t s);
+                         int want_seeds, int max_det, hipStream_t s);   // max_det: widest slice
 hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
                                hipStream_t s);
 hipError_t launch_ext_ring_grad(const SliceDesc* D, const Item* items, int n_items, int grid,

@@ -197,53 +197,6 @@ __global__ __launch_bounds__(kTrThreads) void k_lb_direction(const LbDesc* __res
     }
 }
 
-// ------------------------------------------------------------------------ direction (vector form)
-// Item (slice, chunk) over the optimiser's vector, for the full model of eq. 4 whose vector
-// (maps, then offsets) is not a pair of maps: the same direction and trial point as
-// k_lb_direction, element by element, without the fused transpose. In h-mode the trial
-// point's map is also written twice into the expanded pair D.xe the two-map kernels evaluate.
-__global__ __launch_bounds__(kVecThreads) void k_lb_direction_vec(const LbDesc* __restrict__ L,
-                                                                 const SliceDesc* __restrict__ D,
-                                                                 const Item* __restrict__ items,
-                                                                 int n_items) {
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const Item w = items[it];
-        const LbDesc& l = L[w.x];
-        const SliceDesc& dsc = D[w.x];
-        const SolverState& s = *l.st;
-        if (s.skip) continue;
-        const int mode = s.mode;
-        const int mc = mode == MODE_NEW_DIR ? s.m_cur : 0;
-        const double alpha = s.alpha, gamma = s.gamma;
-        const bool expand = (dsc.ext & EXT_HMODE) != 0;
-        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, l.nv);
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
-            const float z = l.z[e];
-            float t = z;
-            if (mode != MODE_INIT) {
-                double dv;
-                if (mode == MODE_NEW_DIR) {
-                    dv = -gamma * (double)l.g[e];
-                    for (int q = 0; q < mc; ++q) {
-                        const int64_t o = (int64_t)s.order[q] * l.nv + e;
-                        dv = fma(-s.ee[q], (double)l.S[o], dv);
-                        dv = fma(s.cc[q], (double)l.Y[o], dv);
-                    }
-                    l.d[e] = (float)dv;
-                } else {
-                    dv = (double)l.d[e];
-                }
-                t = (float)fma(alpha, dv, (double)z);
-            }
-            l.zt[e] = t;
-            if (expand && e < l.nn) {
-                dsc.xe[e] = t;
-                dsc.xe[l.nn + e] = t;
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------------ accept: update + dots
 // s_new = zt - z, y_new = gt - g into the spare slot; z <- zt, g <- gt; per-block partial
 // inner products: [0] g.g [1] s.s [2] y.y [3] s.y [4] z_old.z_old [5] s.g [6] y.g and, for
@@ -271,6 +224,84 @@ __device__ __forceinline__ void st8(float* __restrict__ p, int64_t e, int64_t nv
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (e + u < nv) p[e + u] = v[u];
+    }
+}
+
+// ------------------------------------------------------------------------ direction (vector form)
+// Item (slice, chunk) over the optimiser's vector, for the full model of eq. 4 whose vector
+// (maps, then offsets) is not a pair of maps: the same direction and trial point as
+// k_lb_direction (FP64 combination, history slots requested a batch at a time), a thread
+// owning 8 consecutive elements, without the fused transpose. In h-mode the trial point's
+// map is also written twice into the expanded pair D.xe that the two-map kernels evaluate.
+__global__ __launch_bounds__(kVecThreads) void k_lb_direction_vec(const LbDesc* __restrict__ L,
+                                                                 const SliceDesc* __restrict__ D,
+                                                                 const Item* __restrict__ items,
+                                                                 int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item w = items[it];
+        const LbDesc& l = L[w.x];
+        const SliceDesc& dsc = D[w.x];
+        const SolverState& s = *l.st;
+        if (s.skip) continue;
+        const int mode = s.mode;
+        const int mc = mode == MODE_NEW_DIR ? s.m_cur : 0;
+        const double alpha = s.alpha, gamma = s.gamma;
+        const int64_t nv = l.nv;
+        const int64_t e = (int64_t)w.y * kVecChunk + 8 * (int64_t)threadIdx.x;
+        if (e >= nv) continue;
+        const bool vec = (nv & 3) == 0 && e + 8 <= nv;
+        float zv[8], tv[8];
+        ld8(l.z, e, nv, vec, zv);
+        if (mode == MODE_INIT) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv[u] = zv[u];
+        } else {
+            double dv[8];
+            float tmp[8];
+            if (mode == MODE_NEW_DIR) {
+                ld8(l.g, e, nv, vec, tmp);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dv[u] = -gamma * (double)tmp[u];
+                for (int r0 = 0; r0 < mc; r0 += kSlotBatch) {
+                    float sb[kSlotBatch][8], yb[kSlotBatch][8];
+#pragma unroll
+                    for (int b = 0; b < kSlotBatch; ++b) {
+                        if (r0 + b < mc) {
+                            const int64_t o = (int64_t)s.order[r0 + b] * nv;
+                            ld8(l.S + o, e, nv, vec, sb[b]);
+                            ld8(l.Y + o, e, nv, vec, yb[b]);
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < kSlotBatch; ++b) {
+                        if (r0 + b < mc) {
+                            const double ee = -s.ee[r0 + b], cc = s.cc[r0 + b];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                dv[u] = fma(cc, (double)yb[b][u], fma(ee, (double)sb[b][u], dv[u]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tmp[u] = (float)dv[u];
+                st8(l.d, e, nv, vec, tmp);
+            } else {
+                ld8(l.d, e, nv, vec, tmp);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dv[u] = (double)tmp[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv[u] = (float)fma(alpha, dv[u], (double)zv[u]);
+        }
+        st8(l.zt, e, nv, vec, tv);
+        if ((dsc.ext & EXT_HMODE) && e < l.nn) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < l.nn) {
+                    dsc.xe[e + u] = tv[u];
+                    dsc.xe[l.nn + e + u] = tv[u];
+                }
+        }
     }
 }
 

@@ -47,14 +47,16 @@ __device__ __forceinline__ void flat_eval(const SliceDesc& d, int k, float4 fl, 
 // Item (slice, angle, -, -). As the plain IC stage (FP64 model from FP32 projections, seeds
 // in place of the projections), with the offsets of the point and the flat of the plan.
 // Also: g_mo[a] = sum_k G_Delta[a][k] (drift, fixed-order block sum) and g_dl[a][k] =
-// G_Delta[a][k] (ring; summed over angles by the contraction pass).
-constexpr int kExtIcThreads = 512;
+// G_Delta[a][k] (ring; summed over angles by k_ext_ring_grad). G_Delta of the angle's row
+// waits in dynamically sized LDS (n_det doubles of the widest slice in the launch), and the
+// block has 256 threads when no slice has more than 256 detector pixels, else 512.
 constexpr int kExtMaxDet = 4096;
-__global__ __launch_bounds__(kExtIcThreads) void k_ic_ext(const SliceDesc* __restrict__ D,
-                                                         const Item* __restrict__ items,
-                                                         int n_items, int want_seeds) {
-    __shared__ double gdl[kExtMaxDet];
-    __shared__ double red[kExtIcThreads / 64];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ic_ext(const SliceDesc* __restrict__ D,
+                                               const Item* __restrict__ items,
+                                               int n_items, int want_seeds) {
+    extern __shared__ double gdl[];
+    __shared__ double red[NT / 64];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kExtIcThreads) void k_ic_ext(const SliceDesc* __res
         const double mo = (d.ext & EXT_DRIFT) ? d.off_scale * (double)d.off[a] : 0.0;
         const float* mr = (d.ext & EXT_RING) ? d.off + ((d.ext & EXT_DRIFT) ? nt : 0) : nullptr;
         double r2 = 0.0, gsum = 0.0;
-        for (int k = threadIdx.x; k < nd; k += kExtIcThreads) {
+        for (int k = threadIdx.x; k < nd; k += NT) {
             const double pm = sm * (double)Pm[k];
             const double pp = k + 1 < nd ? sdl * (double)Pd[k + 1] : 0.0;
             const double pn = k > 0 ? sdl * (double)Pd[k - 1] : 0.0;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kExtIcThreads) void k_ic_ext(const SliceDesc* __res
         }
         __syncthreads();   // every read of Pd done, gdl complete
         if (want_seeds) {
-            for (int k = threadIdx.x; k < nd; k += kExtIcThreads) {
+            for (int k = threadIdx.x; k < nd; k += NT) {
                 const double gp = k + 1 < nd ? gdl[k + 1] : 0.0;
                 const double gn = k > 0 ? gdl[k - 1] : 0.0;
                 Pd[k] = (float)(sdl * (-kap * 0.5 * (gp - gn)));
@@ -167,25 +169,32 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* _
 }
 
 // Item (slice, pixel block): the ring term's gradient off_scale * sum_a g_dl[a][k] for 64
-// pixels k; the block's four wavefronts take every fourth angle (coalesced rows of g_dl) and
-// their partial sums are added in wavefront order.
-constexpr int kRingThreads = 256, kRingPix = 64;
+// pixels k. The block's 16 wavefronts take every 16th angle (coalesced rows of g_dl), each
+// with four independent partial sums so that its loads overlap; the partials are added in a
+// fixed order (wavefront, then partial).
+constexpr int kRingThreads = 1024, kRingPix = 64, kRingAcc = 4;
 __global__ __launch_bounds__(kRingThreads) void k_ext_ring_grad(const SliceDesc* __restrict__ D,
                                                                const Item* __restrict__ items,
                                                                int n_items) {
-    __shared__ double part[kRingThreads / kRingPix][kRingPix];
-    const int lane = threadIdx.x % kRingPix, wv = threadIdx.x / kRingPix;
     constexpr int NW = kRingThreads / kRingPix;
+    __shared__ double part[NW][kRingPix];
+    const int lane = threadIdx.x % kRingPix, wv = threadIdx.x / kRingPix;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item w = items[it];
         const SliceDesc& d = D[w.x];
         if (skipped_adj(d) || !(d.ext & EXT_RING)) continue;
         const int nd = d.n_det, nt = d.n_theta;
         const int k = w.y * kRingPix + lane;
-        double acc = 0.0;
-        if (k < nd)
-            for (int a = wv; a < nt; a += NW) acc += d.g_dl[(size_t)a * nd + k];
-        part[wv][lane] = acc;
+        double acc[kRingAcc] = {0.0, 0.0, 0.0, 0.0};
+        if (k < nd) {
+            int a = wv;
+            for (; a + (kRingAcc - 1) * NW < nt; a += kRingAcc * NW) {
+#pragma unroll
+                for (int q = 0; q < kRingAcc; ++q) acc[q] += d.g_dl[(size_t)(a + q * NW) * nd + k];
+            }
+            for (int q = 0; a < nt; a += NW, ++q) acc[q] += d.g_dl[(size_t)a * nd + k];
+        }
+        part[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         __syncthreads();
         if (wv == 0 && k < nd) {
             double v = 0.0;
@@ -260,9 +269,14 @@ hipError_t launch_ext_expand(const SliceDesc* D, const Item* items, int n_items,
     return hipGetLastError();
 }
 hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int grid,
-                         int want_seeds, hipStream_t s) {
+                         int want_seeds, int max_det, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    k_ic_ext<<<grid, kExtIcThreads, 0, s>>>(D, items, n_items, want_seeds);
+    if (max_det < 1 || max_det > kExtMaxDet) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * (size_t)max_det;
+    if (max_det <= 256)
+        k_ic_ext<256><<<grid, 256, lds, s>>>(D, items, n_items, want_seeds);
+    else
+        k_ic_ext<512><<<grid, 512, lds, s>>>(D, items, n_items, want_seeds);
     return hipGetLastError();
 }
 hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
