@@ -134,9 +134,12 @@ template <int BM, int BN, int WM, int WN, class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kps) {
     constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
     static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
-    constexpr int GP = 5;                      // groups per LDS row: 4 + 1 pad (bank spread)
+    // LDS rows of 4 groups (64 bytes, 16 banks), group g of row r stored in slot
+    // g ^ ((r >> 2) & 3): the 16 lanes that read one group of 16 consecutive rows, and the 16
+    // threads that write the 4 groups of 4 consecutive rows, each cover all 64 banks once.
     constexpr int SA = (BM * 4 + 255) / 256, SB = (BN * 4 + 255) / 256;
-    __shared__ bf16x8 As[BM * GP], Bs[BN * GP];
+    __shared__ bf16x8 As[BM * 4], Bs[BN * 4];
+    auto slot = [](int r, int g) { return r * 4 + (g ^ ((r >> 2) & 3)); };
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -171,20 +174,20 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
 #pragma unroll
         for (int q = 0; q < SA; ++q) {
             const int e = tid + q * 256;
-            if (e < BM * 4) As[(e >> 2) * GP + (e & 3)] = ra[q];
+            if (e < BM * 4) As[slot(e >> 2, e & 3)] = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < SB; ++q) {
             const int e = tid + q * 256;
-            if (e < BN * 4) Bs[(e >> 2) * GP + (e & 3)] = rb[q];
+            if (e < BN * 4) Bs[slot(e >> 2, e & 3)] = rb[q];
         }
         __syncthreads();
         if (k0 + 32 < ke) fetch(k0 + 32);
         bf16x8 a[TM], b[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = As[(wm * TM * 16 + i * 16 + (lane & 15)) * GP + (lane >> 4)];
+        for (int i = 0; i < TM; ++i) a[i] = As[slot(wm * TM * 16 + i * 16 + (lane & 15), lane >> 4)];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = Bs[(wn * TN * 16 + j * 16 + (lane & 15)) * GP + (lane >> 4)];
+        for (int j = 0; j < TN; ++j) b[j] = Bs[slot(wn * TN * 16 + j * 16 + (lane & 15), lane >> 4)];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
