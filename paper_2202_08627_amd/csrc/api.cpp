@@ -129,7 +129,8 @@ struct eit_plan {
     Item* it_uvec = nullptr;      // chunks of the parameter vector
     Item* it_hvec = nullptr;      // chunks of one map
     Item* it_ring = nullptr;      // pixel blocks of the ring term's gradient
-    int n_it_uvec = 0, n_it_hvec = 0, n_it_ring = 0;
+    Item* it_cvec = nullptr;      // small chunks of the parameter vector (contraction)
+    int n_it_uvec = 0, n_it_hvec = 0, n_it_ring = 0, n_it_cvec = 0;
 };
 
 namespace {
@@ -147,7 +148,7 @@ void free_plan(eit_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->pang, p->groups, p->win_lo, p->aang, p->apairs, p->flat, p->mask,
                     p->it_tr, p->it_pr, p->it_ic, p->it_bp, p->it_vec, p->ftab, p->eq3_kern,
-                    p->eq3_invf, p->it_uvec, p->it_hvec, p->it_ring};
+                    p->eq3_invf, p->it_uvec, p->it_hvec, p->it_ring, p->it_cvec};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -228,7 +229,7 @@ struct HostTables {
     std::vector<double> maskd;
     std::vector<Item> it_tr, it_pr, it_ic, it_bp, it_vec;
     std::vector<double> ftab, eq3_kern, eq3_invf;
-    std::vector<Item> it_uvec, it_hvec, it_ring;
+    std::vector<Item> it_uvec, it_hvec, it_ring, it_cvec;
 };
 
 // Cubic-convolution value and slope (Keys 1981, a = -1/2) of a tabulated flat row F[0..Q) at u,
@@ -517,6 +518,10 @@ int build_host(const eit_dims* dims, const eit_setup* setup, const eit_tiling* t
         for (int b = 0; b < (nd + kRingPixPerItem - 1) / kRingPixPerItem; ++b)
             h.it_ring.push_back(make_int4(0, b, 0, 0));
     p->n_it_ring = (int)h.it_ring.size();
+    if (p->ext)
+        for (int64_t b = 0; b < (p->nvu + kContractChunk - 1) / kContractChunk; ++b)
+            h.it_cvec.push_back(make_int4(0, (int)b, 0, 0));
+    p->n_it_cvec = (int)h.it_cvec.size();
     return EIT_OK;
 }
 
@@ -548,7 +553,7 @@ int create_plan(const eit_dims* dims, const eit_setup* setup, const eit_model* m
         (rc = upload(&p->it_vec, h.it_vec)) || (rc = upload(&p->ftab, h.ftab)) ||
         (rc = upload(&p->eq3_kern, h.eq3_kern)) || (rc = upload(&p->eq3_invf, h.eq3_invf)) ||
         (rc = upload(&p->it_uvec, h.it_uvec)) || (rc = upload(&p->it_hvec, h.it_hvec)) ||
-        (rc = upload(&p->it_ring, h.it_ring))) {
+        (rc = upload(&p->it_ring, h.it_ring)) || (rc = upload(&p->it_cvec, h.it_cvec))) {
         free_plan(p);
         return rc;
     }
@@ -838,8 +843,10 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
                               grad ? 1 : 0, p->n_det, st));
         HIP_TRY(launch_cost_reduce(dd, 1, st));
         if (!grad) return EIT_OK;
-        if (int rc = enqueue_backproject(p, dd, 0, st)) return rc;
-        HIP_TRY(launch_ext_contract(dd, p->it_uvec, p->n_it_uvec, grid_for(p->n_it_uvec, kGridCap), st));
+        // the contraction adds a split adjoint's partial planes itself (no combine pass)
+        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
+                                   0, st));
+        HIP_TRY(launch_ext_contract(dd, p->it_cvec, p->n_it_cvec, grid_for(p->n_it_cvec, kGridCap), st));
         HIP_TRY(launch_ext_ring_grad(dd, p->it_ring, p->n_it_ring, grid_for(p->n_it_ring, kGridCap), st));
         return EIT_OK;
     }
@@ -917,12 +924,11 @@ struct StepPlan {
     const Item* it_tr; int n_tr;
     const Item* it_ic; int n_ic;
     const Item* it_vec; int n_vec;
-    // full model of eq. 4 (one slice): vector-form direction, separate transpose, eq. 4 IC
-    // stage, adjoint without regulariser (+ the split's combine pass over it_map), contraction
+    // full model of eq. 4: vector-form direction, separate transpose, eq. 4 IC stage, adjoint
+    // without regulariser, contraction (which adds a split adjoint's parts), ring sums
     bool ext = false;
-    bool split = false;
-    const Item* it_map = nullptr; int n_map = 0;   // chunks of the two-map planes
     const Item* it_ring = nullptr; int n_ring = 0; // pixel blocks of ring-term gradients
+    const Item* it_cvec = nullptr; int n_cvec = 0; // contraction chunks
     int max_det = 0;                               // widest slice (n_det) of the launch
 };
 
@@ -947,9 +953,8 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
         if (int rc = mark(5)) return rc;
         for (const auto& l : sp.adj)
             HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 0, st));
-        if (sp.split)
-            HIP_TRY(launch_bp_combine(sp.D, sp.it_map, sp.n_map, grid_for(sp.n_map, kGridCap), 0, st));
-        HIP_TRY(launch_ext_contract(sp.D, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
+        // the contraction adds a split adjoint's partial planes itself
+        HIP_TRY(launch_ext_contract(sp.D, sp.it_cvec, sp.n_cvec, grid_for(sp.n_cvec, kGridCap), st));
         HIP_TRY(launch_ext_ring_grad(sp.D, sp.it_ring, sp.n_ring, grid_for(sp.n_ring, kGridCap), st));
         if (int rc = mark(6)) return rc;
         HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
@@ -1305,9 +1310,8 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
     sp.it_ic = p->it_ic; sp.n_ic = p->n_it_ic;
     sp.it_vec = p->it_uvec; sp.n_vec = p->n_it_uvec;
     sp.ext = p->ext != 0;
-    sp.split = p->adj_splits > 1;
-    sp.it_map = p->it_vec; sp.n_map = p->n_it_vec;
     sp.it_ring = p->it_ring; sp.n_ring = p->n_it_ring;
+    sp.it_cvec = p->it_cvec; sp.n_cvec = p->n_it_cvec;
     sp.max_det = p->n_det;
     int launches = 0;
     PhaseTimer timer;
@@ -1392,10 +1396,9 @@ struct BatchLayout {
     std::vector<Item> items_h;        // all work items, grouped by launch
     // item ranges (offset, count) in items_h
     std::pair<int, int> r_dir, r_ic, r_vec;
-    std::pair<int, int> r_map{0, 0};  // full model: chunks of every slice's two-map planes
     std::pair<int, int> r_ring{0, 0}; // full model: pixel blocks of ring-term gradients
+    std::pair<int, int> r_cvec{0, 0}; // full model: contraction chunks
     bool ext = false;                 // full-model batch (every plan has model options)
-    bool any_split = false;
     std::vector<std::tuple<int, int, int, size_t>> r_proj, r_adj;   // variant, off, count, lds
 };
 
@@ -1450,18 +1453,14 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     for (int i = 0; i < n; ++i) tiles += (long long)plans[i]->n_tx * plans[i]->n_ty;
     B.splits.resize(n);
     for (int i = 0; i < n; ++i) B.splits[i] = tiles >= kSplitTarget ? 1 : plans[i]->adj_splits;
-    B.any_split = false;
-    for (int i = 0; i < n; ++i) B.any_split = B.any_split || B.splits[i] > 1;
-    B.r_map = {(int)H.size(), 0};
-    if (B.ext && B.any_split) {
-        for (int i : B.order)
-            for (int b = 0; b < plans[i]->n_it_vec; ++b) H.push_back(make_int4(i, b, 0, 0));
-        B.r_map.second = (int)H.size() - B.r_map.first;
-    }
     B.r_ring = {(int)H.size(), 0};
     for (int i : B.order)
         for (int b = 0; b < plans[i]->n_it_ring; ++b) H.push_back(make_int4(i, b, 0, 0));
     B.r_ring.second = (int)H.size() - B.r_ring.first;
+    B.r_cvec = {(int)H.size(), 0};
+    for (int i : B.order)
+        for (int b = 0; b < plans[i]->n_it_cvec; ++b) H.push_back(make_int4(i, b, 0, 0));
+    B.r_cvec.second = (int)H.size() - B.r_cvec.first;
     for (int v = 0; v < adj_variant_count(); ++v) {
         const int off = (int)H.size();
         for (int i : B.order) {
@@ -1543,9 +1542,8 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     sp.it_ic = it + B.r_ic.first; sp.n_ic = B.r_ic.second;
     sp.it_vec = it_vec; sp.n_vec = n_vec;
     sp.ext = B.ext;
-    sp.split = B.any_split;
-    sp.it_map = it + B.r_map.first; sp.n_map = B.r_map.second;
     sp.it_ring = it + B.r_ring.first; sp.n_ring = B.r_ring.second;
+    sp.it_cvec = it + B.r_cvec.first; sp.n_cvec = B.r_cvec.second;
     for (int i = 0; i < n; ++i) sp.max_det = std::max(sp.max_det, plans[i]->n_det);
     int launches = 0;
     PhaseTimer timer;

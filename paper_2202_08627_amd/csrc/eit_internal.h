@@ -170,6 +170,7 @@ hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int
                          int want_seeds, int max_det, hipStream_t s);   // max_det: widest slice
 hipError_t launch_ext_contract(const SliceDesc* D, const Item* items, int n_items, int grid,
                                hipStream_t s);
+constexpr int kContractChunk = 256;     // parameter-vector entries per item of the contraction
 hipError_t launch_ext_ring_grad(const SliceDesc* D, const Item* items, int n_items, int grid,
                                 hipStream_t s);
 constexpr int kRingPixPerItem = 64;     // pixels per item of launch_ext_ring_grad

@@ -134,9 +134,17 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_expand(const SliceDesc* __r
 
 // ------------------------------------------------------------------------ contraction
 // Item (slice, chunk) over the parameter vector: the gradient in the parameter layout from
-// the adjoint's two planes g (computed without the regulariser), the point xu and the
-// offset sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h);
-// drift: off_scale * g_mo[a]. The ring entries are written by k_ext_ring_grad.
+// the adjoint's two planes (computed without the regulariser), the point xu and the offset
+// sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h);
+// drift: off_scale * g_mo[a]. The ring entries are written by k_ext_ring_grad. The planes are
+// g, or with a split adjoint the FP64 partial planes added here in part order.
+__device__ __forceinline__ double adj_plane(const SliceDesc& d, int64_t e, int64_t nv2) {
+    if (d.adj_splits <= 1) return (double)d.g[e];
+    double v = 0.0;
+    for (int g = 0; g < d.adj_splits; ++g) v += d.bp_part[g * nv2 + e];
+    return v;
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* __restrict__ D,
                                                              const Item* __restrict__ items,
                                                              int n_items) {
@@ -148,15 +156,15 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* _
         const bool hm = (d.ext & EXT_HMODE) != 0;
         const int64_t maps_end = hm ? nn : 2 * nn;
         const int64_t mo_end = maps_end + ((d.ext & EXT_DRIFT) ? d.n_theta : 0);
-        const int64_t e0 = (int64_t)w.y * kVecChunk, e1 = min(e0 + kVecChunk, d.nvu);
+        const int64_t e0 = (int64_t)w.y * kContractChunk, e1 = min(e0 + kContractChunk, d.nvu);
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
             double v;
             if (e < maps_end) {
                 if (hm) {
-                    v = (double)d.g[e] + (double)d.g[nn + e];
+                    v = adj_plane(d, e, 2 * nn) + adj_plane(d, nn + e, 2 * nn);
                     v = fma(d.reg_mu, (double)d.xu[e], v);
                 } else {
-                    v = fma(e < nn ? d.reg_mu : d.reg_de, (double)d.xu[e], (double)d.g[e]);
+                    v = fma(e < nn ? d.reg_mu : d.reg_de, (double)d.xu[e], adj_plane(d, e, 2 * nn));
                 }
             } else if (e < mo_end) {
                 v = d.off_scale * d.g_mo[e - maps_end];

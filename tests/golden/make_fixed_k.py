@@ -9,6 +9,7 @@ run's settings.
 
     python tests/golden/make_fixed_k.py slice512 [K ...]  # 512^2 / 720 / M = 8, x_K (default K = 100)
     python tests/golden/make_fixed_k.py batch_classes  # one slice per batch size class, K = 5
+    python tests/golden/make_fixed_k.py paper220       # the paper's acquisition (eq. 4 model), K = 50
 
 The optimiser reading (theory section: L-BFGS through SciPy, settings unstated) is the
 oracle's: memory 10, first trial 1/||g||, Armijo c1 = 1e-4 with halving, at most 20
@@ -33,6 +34,7 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 from paper_2202_08627_amd import configs, synth  # noqa: E402
+from oracle import full_model as ofull  # noqa: E402
 from oracle import lbfgs as olbfgs  # noqa: E402
 from oracle import model as omodel  # noqa: E402
 
@@ -103,10 +105,9 @@ def make_slice512(iters=100, snapshots=(), out_dir=HERE):
 
     def snap(k, x, st):
         save(os.path.join(out_dir, f"slice512_k{k}.npz"), x, st, _Tr(trace, k), meta_for(k, time.time() - t0))
-    cfg_case = case
-    geo = omodel.Geometry(cfg.n, cfg_case.theta, cfg.n_det, cfg_case.mask_pos, cfg_case.flat_amp,
-                          cfg_case.flat_ctr, cfg_case.flat_sigma, cfg.kappa)
-    prob = omodel.ScaledProblem(cfg_case.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
+    geo = omodel.Geometry(cfg.n, case.theta, cfg.n_det, case.mask_pos, case.flat_amp,
+                          case.flat_ctr, case.flat_sigma, cfg.kappa)
+    prob = omodel.ScaledProblem(case.s_exp, geo, cfg.lam, cfg.mu_scale, cfg.delta_scale)
 
     def cb(st):
         if st.k in snapshots:
@@ -129,10 +130,33 @@ def make_batch_classes(iters=5):
         save(os.path.join(HERE, f"batch_slice{s}_{cfg.n}_k{iters}.npz"), x, st, tr, meta)
 
 
+def make_paper220(iters=50, z=37):
+    """Slice z of the 220 x 220 x 75 granule stack at the paper's acquisition: h-mode
+    (gamma = 5), one mask position, 400 angles over 360 deg, 20-scan flat table, drift m_o
+    fitted, no ring term; x_K is the parameter vector [h (n^2), m_o (n_theta)]."""
+    cfg = configs.PAPER_220
+    cases, _ = synth.make_stack(cfg, 75)
+    c = cases[z]
+    st = ofull.Setup(cfg.n, c.theta, cfg.n_det, c.mask_pos, c.flat_amp, c.flat_ctr, c.flat_sigma,
+                     cfg.kappa, hmode=True, gamma=cfg.gamma_h, fit_mo=True, fit_mr=False,
+                     flat_table=c.flat_table, table_u0=c.table_u0, table_du=c.table_du)
+    prob = ofull.ScaledProblem(st, c.s_exp, cfg.lam, cfg.mu_scale, 1.0)
+    t0 = time.time()
+    zk, stt, tr = olbfgs.minimize(prob, np.zeros(st.n_params), iters, m=10)
+    meta = dict(workload=f"paper acquisition, granule stack slice {z}: 220x220, 400 angles over "
+                "360 deg, M=1, h-mode gamma=5, 20-scan flat table, drift fitted, from zero",
+                n=cfg.n, n_theta=cfg.n_theta, n_mask=cfg.n_mask, slice=z, iters=iters, m=10,
+                lam=cfg.lam, mu_scale=cfg.mu_scale, offset_scale=1.0, oracle_s=round(time.time() - t0, 1),
+                command="python tests/golden/make_fixed_k.py paper220")
+    save(os.path.join(HERE, f"paper220_k{iters}.npz"), prob.to_p(zk), stt, tr, meta)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "slice512"
     if what == "slice512":
         ks = [int(a) for a in sys.argv[2:]] or [100]
         make_slice512(max(ks), snapshots=tuple(k for k in ks if k != max(ks)))
+    elif what == "paper220":
+        make_paper220()
     else:
         make_batch_classes()
