@@ -4,6 +4,7 @@ the benchmark times.
 * The 512^2 / 720-angle / M = 8 benchmark slice: x_K from zero with the tuned tiles, per-map
   relative L2 <= 1e-3 against the oracle's x_K (tests/golden/slice512_k<K>.npz, written by
   tests/golden/make_fixed_k.py from oracle/ only).
+* The paper's acquisition (full eq. 4 model) on one slice of the granule stack, K = 50.
 * The mixed-size batch: three slices of each size class (256^2/360, 512^2/720, 768^2/1080,
   M = 8) in one batch call with the tuned tiles; that many adjoint tiles put the batch in the
   regime where every adjoint runs unsplit. Each slice equals its own single-slice run with an
@@ -139,3 +140,28 @@ def test_mixed_batch_in_benchmark_shape(ops):
         assert e_mu < TOL_X and e_de < TOL_X
         checked += 1
     assert checked == 3
+
+
+def test_fixed_k_paper_acquisition(ops):
+    """The paper's acquisition (eq. 4 model: h-mode, one mask position, 400 angles over 360 deg,
+    20-scan flat table, drift fitted) on slice 37 of the granule stack, in the benchmark's
+    launch configuration: x_50 (h and m_o) within 1e-3 of the FP64 oracle's."""
+    from paper_2202_08627_amd import experiment
+    fx, meta = load_fixture("paper220_k50.npz")
+    cfg = configs.PAPER_220
+    K = meta["iters"]
+    cases, _ = synth.make_stack(cfg, 75)
+    c = cases[meta["slice"]]
+    plan = experiment.model_plan(c, fit_drift=True, fit_ring=False)
+    x, rep, hist = plan.reconstruct(dev(c.s_exp), iters=K, cost_hist=True, **experiment.solve_kw(cfg))
+    X = x.cpu().numpy().astype(np.float64)
+    xo = fx["x"].astype(np.float64)
+    nn = cfg.n * cfg.n
+    e_h, e_mo = rel_l2(X[:nn], xo[:nn]), rel_l2(X[nn:], xo[nn:])
+    h = hist.cpu().numpy()[1:]
+    print(f"fixed-K paper220 K={K}: rel-L2 h {e_h:.3e} m_o {e_mo:.3e} (bound {TOL_X}); evals GPU "
+          f"{rep['evals']} oracle {int(fx['evals'])}; first cost divergence > 1e-4 at iteration "
+          f"{first_divergence(h, fx['cost'])}", flush=True)
+    assert rep["rc"] == 0 and rep["iters"] == K
+    assert e_h < TOL_X and e_mo < TOL_X
+    assert np.allclose(h, fx["cost"], rtol=1e-4)
