@@ -125,6 +125,18 @@ struct EpiPart {
     }
 };
 
+// --------------------------------------------------------------------------- tile order
+// The dispatcher hands workgroup L (linear id, x fastest) to XCD L % kXcds, and every XCD has
+// an L2 of its own. tile_order(L, total) renumbers the workgroups so that XCD j takes the
+// contiguous range of tile numbers [start_j, start_j + count_j) (a bijection on [0, total)):
+// tiles that read the same activation rows then share one L2 instead of fetching them once
+// per XCD.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int tile_order(int L, int total) {
+    const int xcd = L % kXcds, local = L / kXcds, q = total / kXcds, r = total % kXcds;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 // --------------------------------------------------------------------------- GEMM
 // Block tile BM x BN with 4 wavefronts in a WM x WN grid; k advances 32 per step. Grid
 // (ceil(M/BM), ceil(N/BN), splits); split z covers k in [z*kps, min(K, (z+1)*kps)). Each
@@ -142,8 +154,12 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
     auto slot = [](int r, int g) { return r * 4 + (g ^ ((r >> 2) & 3)); };
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int kb = blockIdx.z * kps, ke = min(K, kb + kps);
+    // tile t: output-channel tiles of one pixel tile adjacent, then pixel tiles, split slowest
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = tile_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bz = t / (gx * gy), bx = (t / gy) % gx, by = t % gy;
+    const int m0 = bx * BM, n0 = by * BN;
+    const int kb = bz * kps, ke = min(K, kb + kps);
     typename LA::Ctx ca[SA];
     typename LB::Ctx cb[SB];
 #pragma unroll
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
                 const int n = n0 + wn * TN * 16 + j * 16 + (lane & 15);
-                if (m < M) ep(m, n, acc[i][j][r], blockIdx.z);
+                if (m < M) ep(m, n, acc[i][j][r], bz);
             }
 }
 
@@ -299,8 +315,12 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     __shared__ __attribute__((aligned(16))) bf16 As[TM * kWgRow], Bs[TN * kWgRow];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-    const int pb = blockIdx.z * kps, pe = min(P, pb + kps);
+    // tile t: the (m, n) tiles of one pixel slab adjacent, slabs in order
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = tile_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bz = t / (gx * gy), bx = t % gx, by = (t / gx) % gy;
+    const int m0 = bx * TM, n0 = by * TN;
+    const int pb = bz * kps, pe = min(P, pb + kps);
     const int Co = dz.C, Ci = x.C;
     const int M = UP ? 4 * Co : Co, N = UP ? Ci : 9 * Ci;
     const int H = x.H, W = x.W;                  // the pixel grid p runs over
@@ -387,7 +407,7 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
         }
     }
-    float* dst = part + (size_t)blockIdx.z * Co * NTAP * Ci;
+    float* dst = part + (size_t)bz * Co * NTAP * Ci;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
