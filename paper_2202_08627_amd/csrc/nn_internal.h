@@ -22,21 +22,27 @@ struct Tensor {
 // GEMM-based layers (nn_kernels.hip)
 hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu, const Tensor& y,
                     int ksize, hipStream_t s);
-hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s);
-// Weight gradients write part[z][co][tap][ci] for z < wgrad_splits_used(pixels, splits)
+// Data gradients; with relu_of (the post-ReLU activation at dx's positions) the stored
+// gradient is zeroed where that activation is not positive.
+hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s,
+                      const Tensor* relu_of = nullptr);
+// Weight gradients write part[z][co][tap][ci] for z < wgrad_splits_used(pixels, splits); the
+// 3x3 conv's part[z] holds Co * 9 * Ci weight partials followed by Co bias partials
 hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
                       hipStream_t s);
 hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
                       hipStream_t s);
-hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s);
+hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s,
+                        const Tensor* relu_of = nullptr);
 hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s);
 
 // element-wise and reduction kernels (nn_misc.hip)
 hipError_t pack_input(const float* x, int B, int H, int W, const Tensor& out, hipStream_t s);
 hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s);
+// dx += the pooled gradient dy routed to each window's maximum, then dx *= (x > 0) (x is the
+// post-ReLU pooling input); the windows cover x (even sides)
 hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
                            hipStream_t s);
-hipError_t relu_mask(const Tensor& y, const Tensor& dy, hipStream_t s);     // dy *= (y > 0)
 hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s);
 hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s);
 hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in,

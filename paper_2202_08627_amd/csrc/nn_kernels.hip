@@ -27,16 +27,27 @@ __device__ __forceinline__ bf16x8 zero8() {
 }
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *(const bf16x8*)p; }
 
+// Buffer loads of 16 bytes: a load at a byte offset >= the resource's extent returns zeros
+// without touching memory. The GEMM loaders turn every out-of-range or padding access into
+// such an offset instead of a branch, so a step's loads are straight-line code (the
+// compiler then tracks each register set's loads separately and can keep several steps'
+// loads in flight). Extents stay below 2^31 bytes (tensor sizes are checked on the host).
+constexpr int kOOB = 0x7ffffff0;
+__device__ __forceinline__ bf16x8 bld8(const bf16* base, int bytes, int off) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 // --------------------------------------------------------------------------- loaders
 // A loader is used in two stages: row(m, M) decodes row m once per output tile (pixel
-// coordinates and validity), load(ctx, k0) returns the 8 consecutive k (k0 .. k0+7,
-// k0 % 8 == 0) of that row, zeros outside.
+// coordinates and validity), load(ctx, k0, ok) returns the 8 consecutive k (k0 .. k0+7,
+// k0 % 8 == 0) of that row, zeros outside or when !ok.
 struct PixRow { int b, y, x; bool ok; };
 
 // 3x3 convolution input patches, k = tap * C + c (C % 8 == 0, power of two). flip = 1 gives
 // the data-gradient form (input pixel p - (tap - 4) instead of p + (tap - 4)).
 struct LoadConvA {
-    const bf16* t; int B, H, W, C, cs, coff, cshift, K, flip, ksize;
+    const bf16* t; int B, H, W, C, cs, coff, cshift, K, flip, ksize, bytes;
     typedef PixRow Ctx;
     __device__ Ctx row(int m, int M) const {
         Ctx c;
@@ -48,33 +59,30 @@ struct LoadConvA {
         c.y = yb - c.b * H;
         return c;
     }
-    __device__ bf16x8 load(const Ctx& r, int k0) const {
-        if (!r.ok || k0 >= K) return zero8();
+    __device__ bf16x8 load(const Ctx& r, int k0, bool ok) const {
         const int tap = k0 >> cshift, c = k0 & (C - 1);
-        int dy, dx;
-        if (ksize == 3) { dy = tap / 3 - 1; dx = tap % 3 - 1; } else { dy = 0; dx = 0; }
+        int dy = ksize == 3 ? tap / 3 - 1 : 0, dx = ksize == 3 ? tap - 3 * (tap / 3) - 1 : 0;
         if (flip) { dy = -dy; dx = -dx; }
         const int yy = r.y + dy, xx = r.x + dx;
-        if ((unsigned)yy >= (unsigned)H || (unsigned)xx >= (unsigned)W) return zero8();
-        return ld8(t + ((size_t)(r.b * H + yy) * W + xx) * cs + coff + c);
+        ok = ok && r.ok && k0 < K && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+        return bld8(t, bytes, ok ? 2 * (((r.b * H + yy) * W + xx) * cs + coff + c) : kOOB);
     }
 };
 
 // Dense row-major matrix [rows][K] (K contiguous, K % 8 == 0).
 struct LoadRows {
-    const bf16* t; int rows, K, ld;
-    struct Ctx { const bf16* p; };
-    __device__ Ctx row(int r, int) const { return Ctx{r < rows ? t + (size_t)r * ld : nullptr}; }
-    __device__ bf16x8 load(const Ctx& r, int k0) const {
-        if (!r.p || k0 >= K) return zero8();
-        return ld8(r.p + k0);
+    const bf16* t; int rows, K, ld, bytes;
+    struct Ctx { int off; bool ok; };
+    __device__ Ctx row(int r, int) const { return Ctx{r < rows ? 2 * r * ld : 0, r < rows}; }
+    __device__ bf16x8 load(const Ctx& r, int k0, bool ok) const {
+        return bld8(t, bytes, ok && r.ok && k0 < K ? r.off + 2 * k0 : kOOB);
     }
 };
 
 // Transposed-convolution (2x2, stride 2) output gradient seen from an input pixel:
 // row m = input pixel (b, y, x), k = d * C + c, value = g[b, 2y + d/2, 2x + d%2, c].
 struct LoadUpGradA {
-    const bf16* t; int B, H, W, C, cs, coff, cshift, K;   // H, W of the input (half size)
+    const bf16* t; int B, H, W, C, cs, coff, cshift, K, bytes;   // H, W of the input (half size)
     typedef PixRow Ctx;
     __device__ Ctx row(int m, int M) const {
         Ctx c;
@@ -86,22 +94,26 @@ struct LoadUpGradA {
         c.y = yb - c.b * H;
         return c;
     }
-    __device__ bf16x8 load(const Ctx& r, int k0) const {
-        if (!r.ok || k0 >= K) return zero8();
+    __device__ bf16x8 load(const Ctx& r, int k0, bool ok) const {
         const int d = k0 >> cshift, c = k0 & (C - 1);
         const int yy = 2 * r.y + (d >> 1), xx = 2 * r.x + (d & 1);
-        return ld8(t + ((size_t)(r.b * 2 * H + yy) * (2 * W) + xx) * cs + coff + c);
+        ok = ok && r.ok && k0 < K;
+        return bld8(t, bytes, ok ? 2 * (((r.b * 2 * H + yy) * (2 * W) + xx) * cs + coff + c) : kOOB);
     }
 };
 
 // --------------------------------------------------------------------------- epilogues
-// NHWC store with optional bias and ReLU.
+// NHWC store with optional bias and ReLU; with `mask` (an NHWC view of a post-ReLU activation
+// of the output's shape) the value is zeroed where the activation is not positive: the
+// ReLU derivative of the layer that produced that activation, applied to its gradient.
 struct EpiAct {
     bf16* t; const float* bias; int cs, coff, relu, N;
+    const bf16* mask; int mcs, mcoff;
     __device__ void operator()(int m, int n, float v, int) const {
         if (n >= N) return;
         if (bias) v += bias[n];
         if (relu) v = fmaxf(v, 0.f);
+        if (mask && !((float)mask[(size_t)m * mcs + mcoff + n] > 0.f)) v = 0.f;
         t[(size_t)m * cs + coff + n] = (__bf16)v;
     }
 };
@@ -142,6 +154,8 @@ __device__ __forceinline__ int tile_order(int L, int total) {
 // (ceil(M/BM), ceil(N/BN), splits); split z covers k in [z*kps, min(K, (z+1)*kps)). Each
 // thread stages fixed (row, 8-k group) slots of the tiles: rows are decoded once per tile,
 // and the next step's groups are loaded into registers while the current step multiplies.
+// (Two or three steps of loads in flight measured slower: the extra registers cost more
+// resident blocks than the deeper prefetch hides.)
 template <int BM, int BN, int WM, int WN, class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kps) {
     constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
@@ -171,12 +185,12 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
 #pragma unroll
         for (int q = 0; q < SA; ++q) {
             const int e = tid + q * 256, k = k0 + 8 * (e & 3);
-            ra[q] = (e < BM * 4 && k < ke) ? la.load(ca[q], k) : zero8();
+            ra[q] = la.load(ca[q], k, e < BM * 4 && k < ke);
         }
 #pragma unroll
         for (int q = 0; q < SB; ++q) {
             const int e = tid + q * 256, k = k0 + 8 * (e & 3);
-            rb[q] = (e < BN * 4 && k < ke) ? lb.load(cb[q], k) : zero8();
+            rb[q] = lb.load(cb[q], k, e < BN * 4 && k < ke);
         }
     };
     f32x4 acc[TM][TN];
@@ -246,38 +260,46 @@ int ilog2(int v) {
 }
 
 // --------------------------------------------------------------------------- layer ops
+// Byte extents of the loaders' buffers (below 2^31 by the host's size checks).
+inline int tensor_bytes(const Tensor& t) { return (int)((size_t)t.B * t.H * t.W * t.cs * sizeof(bf16)); }
+inline int matrix_bytes(int rows, int cols) { return (int)((size_t)rows * cols * sizeof(bf16)); }
+
 hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu, const Tensor& y,
                     int ksize, hipStream_t s) {
     const int taps = ksize * ksize;
-    LoadConvA la{x.p, x.B, x.H, x.W, x.C, x.cs, x.coff, ilog2(x.C), taps * x.C, 0, ksize};
-    LoadRows lb{w, y.C, taps * x.C, taps * x.C};
+    LoadConvA la{x.p, x.B, x.H, x.W, x.C, x.cs, x.coff, ilog2(x.C), taps * x.C, 0, ksize, tensor_bytes(x)};
+    LoadRows lb{w, y.C, taps * x.C, taps * x.C, matrix_bytes(y.C, taps * x.C)};
     EpiAct ep{y.p, bias, y.cs, y.coff, relu, y.C};
     return gemm(la, lb, ep, x.B * x.H * x.W, y.C, taps * x.C, 1, s);
 }
 
 // dx[p][ci] = sum_{tap, co} dz[p - off(tap)][co] wt[ci][tap][co]
-hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s) {
+hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s,
+                      const Tensor* relu_of) {
     const int taps = ksize * ksize;
-    LoadConvA la{dz.p, dz.B, dz.H, dz.W, dz.C, dz.cs, dz.coff, ilog2(dz.C), taps * dz.C, 1, ksize};
-    LoadRows lb{wt, dx.C, taps * dz.C, taps * dz.C};
-    EpiAct ep{dx.p, nullptr, dx.cs, dx.coff, 0, dx.C};
+    LoadConvA la{dz.p, dz.B, dz.H, dz.W, dz.C, dz.cs, dz.coff, ilog2(dz.C), taps * dz.C, 1, ksize, tensor_bytes(dz)};
+    LoadRows lb{wt, dx.C, taps * dz.C, taps * dz.C, matrix_bytes(dx.C, taps * dz.C)};
+    EpiAct ep{dx.p, nullptr, dx.cs, dx.coff, 0, dx.C, relu_of ? relu_of->p : nullptr,
+              relu_of ? relu_of->cs : 0, relu_of ? relu_of->coff : 0};
     return gemm(la, lb, ep, dz.B * dz.H * dz.W, dx.C, taps * dz.C, 1, s);
 }
 
 // y[b, 2y+d/2, 2x+d%2, co] = sum_ci x[b,y,x,ci] w[co][d][ci] + bias[co]
 hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
                       hipStream_t s) {
-    LoadRows la{x.p + x.coff, x.B * x.H * x.W, x.C, x.cs};
-    LoadRows lb{w, 4 * y.C, x.C, x.C};
+    LoadRows la{x.p + x.coff, x.B * x.H * x.W, x.C, x.cs, tensor_bytes(x) - 2 * x.coff};
+    LoadRows lb{w, 4 * y.C, x.C, x.C, matrix_bytes(4 * y.C, x.C)};
     EpiUp ep{y.p, bias, x.B, x.H, x.W, y.C, y.cs, y.coff, 4 * y.C};
     return gemm(la, lb, ep, x.B * x.H * x.W, 4 * y.C, x.C, 1, s);
 }
 
 // dx[b,y,x,ci] = sum_{d,co} g[b,2y+d/2,2x+d%2,co] wt[ci][d][co]
-hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s) {
-    LoadUpGradA la{g.p, dx.B, dx.H, dx.W, g.C, g.cs, g.coff, ilog2(g.C), 4 * g.C};
-    LoadRows lb{wt, dx.C, 4 * g.C, 4 * g.C};
-    EpiAct ep{dx.p, nullptr, dx.cs, dx.coff, 0, dx.C};
+hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s,
+                        const Tensor* relu_of) {
+    LoadUpGradA la{g.p, dx.B, dx.H, dx.W, g.C, g.cs, g.coff, ilog2(g.C), 4 * g.C, tensor_bytes(g)};
+    LoadRows lb{wt, dx.C, 4 * g.C, 4 * g.C, matrix_bytes(dx.C, 4 * g.C)};
+    EpiAct ep{dx.p, nullptr, dx.cs, dx.coff, 0, dx.C, relu_of ? relu_of->p : nullptr,
+              relu_of ? relu_of->cs : 0, relu_of ? relu_of->coff : 0};
     return gemm(la, lb, ep, dx.B * dx.H * dx.W, dx.C, 4 * g.C, 1, s);
 }
 
@@ -286,7 +308,11 @@ hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipSt
 //   3x3 conv:    m = co, n = tap * Ci + ci:   sum_p dZ[p][co] X[p + off(tap)][ci]
 //   2x2 up-conv: m = d * Co + co, n = ci:     sum_p G[b, 2y + d/2, 2x + d%2][co] X[p][ci]
 //                (p = (b, y, x) over the up-conv's input)
-// stored as part[z][co][tap][ci] (tap = d for the up-conv). Pixels are strided in NHWC, so
+// stored as part[z][co][tap][ci] (tap = d for the up-conv). For the 3x3 conv each split also
+// stores the bias-gradient partials sum_p dZ[p][co] after its weight block, part[z] being
+// Co * 9 * Ci + Co floats (the parameter layout's weights-then-bias order, so one split-K
+// reduction yields both): the blocks of the first n tile add up the dZ rows they stage.
+// Pixels are strided in NHWC, so
 // each 64-pixel step stages both operands transposed into LDS ([row][pixel], rows padded to
 // 72 elements): a thread loads 16 bytes (8 consecutive channels = 8 rows of one tap) for each
 // of a few consecutive pixels and writes them as 8 short row segments, and an MFMA fragment
@@ -340,20 +366,19 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     bf16x8 av[AP], bv[BP];
+    const int a_bytes = (int)((size_t)dz.B * dz.H * dz.W * dz.cs * sizeof(bf16));
+    const int b_bytes = (int)((size_t)x.B * x.H * x.W * x.cs * sizeof(bf16));
     auto load = [&](int k0) {
-        if (a_act) {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv)
+        {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv); threads
+            // past the OA row groups have m_ok false, so their loads return zeros
             int p = k0 + AP * ga;
             int yb = p / W, xx = p - yb * W;     // one division per step, then carries
             int b = yb / H, yy = yb - b * H;
 #pragma unroll
             for (int q = 0; q < AP; ++q) {
-                av[q] = zero8();
-                if (p < pe && m_ok) {
-                    size_t o;
-                    if (UP) o = ((size_t)(b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs;
-                    else o = (size_t)p * dz.cs;
-                    av[q] = ld8(dz.p + o + dz.coff + co);
-                }
+                const int o = UP ? ((b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs
+                                 : p * dz.cs;
+                av[q] = bld8(dz.p, a_bytes, p < pe && m_ok ? 2 * (o + dz.coff + co) : kOOB);
                 ++p;
                 if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
             }
@@ -364,15 +389,20 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
             int b = yb / H, yy = yb - b * H;
 #pragma unroll
             for (int q = 0; q < BP; ++q) {
-                bv[q] = zero8();
                 const int sy = yy + dy, sx = xx + dx;
-                if (p < pe && n_ok && (unsigned)sy < (unsigned)H && (unsigned)sx < (unsigned)W)
-                    bv[q] = ld8(x.p + ((size_t)(b * H + sy) * W + sx) * x.cs + x.coff + ci);
+                const bool ok = p < pe && n_ok && (unsigned)sy < (unsigned)H && (unsigned)sx < (unsigned)W;
+                bv[q] = bld8(x.p, b_bytes, ok ? 2 * (((b * H + sy) * W + sx) * x.cs + x.coff + ci) : kOOB);
                 ++p;
                 if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
             }
         }
     };
+    // bias partials (3x3 conv, first n tile): thread t adds 8 pixels of rows t / 8 + 32 r
+    constexpr int BR = TM / 32;
+    const bool bias_blk = !UP && by == 0;
+    float bsum[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) bsum[r] = 0.f;
     load(pb);
     for (int k0 = pb; k0 < pe; k0 += kWgStep) {
         __syncthreads();                       // previous step's fragments consumed
@@ -392,6 +422,14 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
         }
         __syncthreads();
         if (k0 + kWgStep < pe) load(k0 + kWgStep);
+        if (bias_blk) {
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const bf16x8 v = *(const bf16x8*)(As + ((tid >> 3) + 32 * r) * kWgRow + 8 * (tid & 7));
+#pragma unroll
+                for (int u = 0; u < 8; ++u) bsum[r] += (float)v[u];
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < kWgStep; kk += 32) {
             bf16x8 a[2], bb[2];
@@ -407,7 +445,18 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
         }
     }
-    float* dst = part + (size_t)bz * Co * NTAP * Ci;
+    float* dst = part + (size_t)bz * (Co * NTAP * Ci + (UP ? 0 : Co));
+    if (bias_blk) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            float v = bsum[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            const int o = m0 + (tid >> 3) + 32 * r;
+            if ((tid & 7) == 0 && o < M) dst[(size_t)M * N + o] = v;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll

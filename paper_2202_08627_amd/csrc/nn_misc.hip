@@ -1,6 +1,6 @@
 // Element-wise and reduction kernels of the warm-start network: input packing, 2x2 max
-// pooling and its gradient, ReLU masks, deterministic channel sums, split-K reduction, the
-// 1x1 residual head, the MSE loss and Adam with FP32 master weights.
+// pooling and its gradient (with the ReLU mask of its input), deterministic channel sums,
+// split-K reduction, the 1x1 residual head, the MSE loss and Adam with FP32 master weights.
 #include <algorithm>
 
 #include "nn_internal.h"
@@ -42,7 +42,8 @@ __global__ void k_pool(Tensor x, Tensor y) {
     }
 }
 
-// The gradient goes to the first input (row-major in the window) equal to the maximum.
+// The gradient goes to the first input (row-major in the window) equal to the maximum; then
+// every input of the window takes the ReLU derivative of x (the layer that produced x).
 __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
     const size_t n = (size_t)y.B * y.H * y.W * y.C;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
@@ -54,33 +55,17 @@ __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
         bool done = false;
         for (int q = 0; q < 4; ++q) {
             const int iy = 2 * yy + (q >> 1), ix = 2 * xx + (q & 1);
-            if (!done && (float)x.p[at4(x, b, iy, ix, c)] == m) {
-                const size_t o = at4(dx, b, iy, ix, c);
-                dx.p[o] = (bf16)((float)dx.p[o] + g);
-                done = true;
-            }
+            const float xv = (float)x.p[at4(x, b, iy, ix, c)];
+            const bool arg = !done && xv == m;
+            done = done || arg;
+            const size_t o = at4(dx, b, iy, ix, c);
+            if (!(xv > 0.f)) dx.p[o] = (bf16)0.f;
+            else if (arg) dx.p[o] = (bf16)((float)dx.p[o] + g);
         }
     }
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// dy *= (y > 0), eight channels (16 bytes) per thread
-__global__ void k_relu_mask(Tensor y, Tensor dy) {
-    const int G = y.C / 8;
-    const size_t n = (size_t)y.B * y.H * y.W * G;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int g = e % G;
-        const size_t p = e / G;
-        const bf16x8 v = *(const bf16x8*)(y.p + p * y.cs + y.coff + 8 * g);
-        bf16x8* q = (bf16x8*)(dy.p + p * dy.cs + dy.coff + 8 * g);
-        bf16x8 d = *q;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (!((float)v[i] > 0.f)) d[i] = (bf16)0.f;
-        *q = d;
-    }
-}
 
 // Stage 1: block k sums pixels [k*P/nblk, (k+1)*P/nblk) of every channel -> part[k][C].
 // Thread (channel group g of 8 channels, pixel lane pl) reads 16 bytes per pixel; the pixel
@@ -274,10 +259,6 @@ hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s) {
 hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
                            hipStream_t s) {
     k_pool_bwd<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(x, y, dy, dx);
-    return hipGetLastError();
-}
-hipError_t relu_mask(const Tensor& y, const Tensor& dy, hipStream_t s) {
-    k_relu_mask<<<nblocks((size_t)y.B * y.H * y.W * (y.C / 8)), kT, 0, s>>>(y, dy);
     return hipGetLastError();
 }
 hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s) {

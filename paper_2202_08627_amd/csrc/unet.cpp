@@ -113,7 +113,7 @@ WsLayout layout(const eit_unet* u, int nb, int h, int w, bool train) {
             if (i >= D3A && i <= UP2) { hh = h / 4; ww = w / 4; }
             if (i >= D2A && i <= UP1) { hh = h / 2; ww = w / 2; }
             const size_t pix = (size_t)nb * hh * ww;
-            const size_t mn = l.kind == 0 ? (size_t)l.cout * 9 * l.cin : (size_t)4 * l.cout * l.cin;
+            const size_t mn = l.kind == 0 ? (size_t)l.cout * 9 * l.cin + l.cout : (size_t)4 * l.cout * l.cin;
             if (l.kind != 2) pe = std::max(pe, mn * wgrad_splits(pix));
         }
     }
@@ -193,20 +193,24 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
     const auto& L = c.u->L;
     const int C = c.u->base;
     const hipStream_t s = c.s;
-    // conv layer li with input X, output Y (post-ReLU), incoming dY (overwritten by dZ);
-    // writes dW, db and, if dX.p, the input gradient
-    auto conv_b = [&](int li, const Tensor& X, const Tensor& Y, const Tensor& dY, const Tensor* dX) -> int {
-        NN_TRY(relu_mask(Y, dY, s));
+    // conv layer li with input X and incoming gradient dY, already multiplied by the ReLU
+    // derivative of the layer's output by whichever kernel produced it (a data gradient's
+    // epilogue, the pooling backward or the head's backward); writes dW, db and, if dX is
+    // given, the input gradient, masked by X > 0 when mask_dx (X the post-ReLU output of
+    // the layer before, whose backward consumes dX directly)
+    auto conv_b = [&](int li, const Tensor& X, const Tensor& dY, const Tensor* dX, bool mask_dx) -> int {
         const size_t pix = (size_t)X.B * X.H * X.W;
         const int sp = wgrad_splits(pix);
+        // weight and bias partials; one reduction writes both (the bias directly follows the
+        // weights in the parameter layout)
         NN_TRY(conv_wgrad(X, dY, part, sp, 3, s));
-        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), L[li].cout * 9 * L[li].cin,
+        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), L[li].cout * 9 * L[li].cin + L[li].cout,
                              grad + L[li].w, s));
-        NN_TRY(channel_sums(dY, sums, kSumBlocks, grad + L[li].b, s));
-        if (dX) NN_TRY(conv_dgrad(dY, c.wt + L[li].wt, *dX, 3, s));
+        if (dX) NN_TRY(conv_dgrad(dY, c.wt + L[li].wt, *dX, 3, s, mask_dx ? &X : nullptr));
         return EIT_OK;
     };
-    // transposed conv li: input X (half size), output-gradient view gY, writes dX
+    // transposed conv li: input X (half size, the post-ReLU output of the layer before),
+    // output-gradient view gY, writes dX masked by X > 0
     auto up_b = [&](int li, const Tensor& X, const Tensor& gY, const Tensor& dX) -> int {
         const size_t pix = (size_t)X.B * X.H * X.W;
         const int sp = wgrad_splits(pix);
@@ -214,36 +218,39 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
         NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), 4 * L[li].cout * L[li].cin,
                              grad + L[li].w, s));
         NN_TRY(channel_sums(gY, sums, kSumBlocks, grad + L[li].b, s));
-        NN_TRY(upconv_dgrad(gY, c.wt + L[li].wt, dX, s));
+        NN_TRY(upconv_dgrad(gY, c.wt + L[li].wt, dX, s, &X));
         return EIT_OK;
     };
     int rc;
     // head: dD1b = (W^T dout) masked by D1b > 0, head dW/db
     NN_TRY(head_bwd(A.D1b, c.prm + L[HEAD].w, dout, nb, h, w, grad + L[HEAD].w, grad + L[HEAD].b,
                     sums, kSumBlocks, G.D1b, s));
-    // d1b already masked by head_bwd: relu_mask is idempotent, so conv_b applies it again
-    if ((rc = conv_b(D1B, A.D1a, A.D1b, G.D1b, &G.D1a))) return rc;
-    if ((rc = conv_b(D1A, A.CAT1, A.D1a, G.D1a, &G.CAT1))) return rc;
+    // D1b's gradient leaves head_bwd masked. A block's first conv (input: a concatenation,
+    // a pooled map or the packed input) writes its input gradient unmasked: the up-conv half
+    // of a concatenation has no ReLU, and the skip half and the pooled maps are masked by the
+    // pooling backward, after the pooled gradient has been added.
+    if ((rc = conv_b(D1B, A.D1a, G.D1b, &G.D1a, true))) return rc;
+    if ((rc = conv_b(D1A, A.CAT1, G.D1a, &G.CAT1, false))) return rc;
     if ((rc = up_b(UP1, A.D2b, view(G.CAT1, 0, C), G.D2b))) return rc;
-    if ((rc = conv_b(D2B, A.D2a, A.D2b, G.D2b, &G.D2a))) return rc;
-    if ((rc = conv_b(D2A, A.CAT2, A.D2a, G.D2a, &G.CAT2))) return rc;
+    if ((rc = conv_b(D2B, A.D2a, G.D2b, &G.D2a, true))) return rc;
+    if ((rc = conv_b(D2A, A.CAT2, G.D2a, &G.CAT2, false))) return rc;
     if ((rc = up_b(UP2, A.D3b, view(G.CAT2, 0, 2 * C), G.D3b))) return rc;
-    if ((rc = conv_b(D3B, A.D3a, A.D3b, G.D3b, &G.D3a))) return rc;
-    if ((rc = conv_b(D3A, A.CAT3, A.D3a, G.D3a, &G.CAT3))) return rc;
+    if ((rc = conv_b(D3B, A.D3a, G.D3b, &G.D3a, true))) return rc;
+    if ((rc = conv_b(D3A, A.CAT3, G.D3a, &G.CAT3, false))) return rc;
     if ((rc = up_b(UP3, A.E4b, view(G.CAT3, 0, 4 * C), G.E4b))) return rc;
-    if ((rc = conv_b(B4, A.E4a, A.E4b, G.E4b, &G.E4a))) return rc;
-    if ((rc = conv_b(A4, A.P3, A.E4a, G.E4a, &G.P3))) return rc;
+    if ((rc = conv_b(B4, A.E4a, G.E4b, &G.E4a, true))) return rc;
+    if ((rc = conv_b(A4, A.P3, G.E4a, &G.P3, false))) return rc;
     const Tensor S1 = view(A.CAT1, C, C), S2 = view(A.CAT2, 2 * C, 2 * C), S3 = view(A.CAT3, 4 * C, 4 * C);
     const Tensor dS1 = view(G.CAT1, C, C), dS2 = view(G.CAT2, 2 * C, 2 * C), dS3 = view(G.CAT3, 4 * C, 4 * C);
     NN_TRY(maxpool_bwd_add(S3, A.P3, G.P3, dS3, s));          // skip gradient + pooled gradient
-    if ((rc = conv_b(B3, A.E3a, S3, dS3, &G.E3a))) return rc;
-    if ((rc = conv_b(A3, A.P2, A.E3a, G.E3a, &G.P2))) return rc;
+    if ((rc = conv_b(B3, A.E3a, dS3, &G.E3a, true))) return rc;
+    if ((rc = conv_b(A3, A.P2, G.E3a, &G.P2, false))) return rc;
     NN_TRY(maxpool_bwd_add(S2, A.P2, G.P2, dS2, s));
-    if ((rc = conv_b(B2, A.E2a, S2, dS2, &G.E2a))) return rc;
-    if ((rc = conv_b(A2, A.P1, A.E2a, G.E2a, &G.P1))) return rc;
+    if ((rc = conv_b(B2, A.E2a, dS2, &G.E2a, true))) return rc;
+    if ((rc = conv_b(A2, A.P1, G.E2a, &G.P1, false))) return rc;
     NN_TRY(maxpool_bwd_add(S1, A.P1, G.P1, dS1, s));
-    if ((rc = conv_b(B1, A.E1a, S1, dS1, &G.E1a))) return rc;
-    if ((rc = conv_b(A1, A.X0, A.E1a, G.E1a, nullptr))) return rc;
+    if ((rc = conv_b(B1, A.E1a, dS1, &G.E1a, true))) return rc;
+    if ((rc = conv_b(A1, A.X0, G.E1a, nullptr, false))) return rc;
     return EIT_OK;
 }
 
