@@ -106,19 +106,32 @@ struct LoadUpGradA {
 // NHWC store with optional bias and ReLU; with `mask` (an NHWC view of a post-ReLU activation
 // of the output's shape) the value is zeroed where the activation is not positive: the
 // ReLU derivative of the layer that produced that activation, applied to its gradient.
+// The GEMM stores it in two stages (kVector): pre() adds the bias and applies the ReLU to one
+// value, the block stages the rounded tile in LDS, and store8() applies the mask to 8
+// consecutive channels and writes them with one 16-byte store (N, cs, coff, mcs and mcoff
+// are multiples of 8).
 struct EpiAct {
+    static constexpr bool kVector = true;
     bf16* t; const float* bias; int cs, coff, relu, N;
     const bf16* mask; int mcs, mcoff;
-    __device__ void operator()(int m, int n, float v, int) const {
-        if (n >= N) return;
-        if (bias) v += bias[n];
+    __device__ float pre(int n, float v) const {
+        if (bias && n < N) v += bias[n];
         if (relu) v = fmaxf(v, 0.f);
-        if (mask && !((float)mask[(size_t)m * mcs + mcoff + n] > 0.f)) v = 0.f;
-        t[(size_t)m * cs + coff + n] = (__bf16)v;
+        return v;
+    }
+    __device__ void store8(int m, int n, bf16x8 v) const {
+        if (mask) {
+            const bf16x8 mk = *(const bf16x8*)(mask + (size_t)m * mcs + mcoff + n);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (!((float)mk[i] > 0.f)) v[i] = (__bf16)0.f;
+        }
+        *(bf16x8*)(t + (size_t)m * cs + coff + n) = v;
     }
 };
 // Transposed conv forward: n = 4 * c + d -> output pixel (2y + d/2, 2x + d%2), channel c.
 struct EpiUp {
+    static constexpr bool kVector = false;
     bf16* t; const float* bias; int B, H, W, C, cs, coff, N;
     __device__ void operator()(int m, int n, float v, int) const {
         if (n >= N) return;
@@ -130,6 +143,7 @@ struct EpiUp {
 };
 // FP32 split-K partials [split][M][N].
 struct EpiPart {
+    static constexpr bool kVector = false;
     float* t; int M, N;
     __device__ void operator()(int m, int n, float v, int z) const {
         if (n >= N) return;
@@ -155,16 +169,24 @@ __device__ __forceinline__ int tile_order(int L, int total) {
 // thread stages fixed (row, 8-k group) slots of the tiles: rows are decoded once per tile,
 // and the next step's groups are loaded into registers while the current step multiplies.
 // (Two or three steps of loads in flight measured slower: the extra registers cost more
-// resident blocks than the deeper prefetch hides.)
+// resident blocks than the deeper prefetch hides. For the same reason the kernel is held to
+// the registers of six wavefronts per SIMD.)
 template <int BM, int BN, int WM, int WN, class LA, class LB, class EP>
-__global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kps) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kps) {
     constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
     static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
     // LDS rows of 4 groups (64 bytes, 16 banks), group g of row r stored in slot
     // g ^ ((r >> 2) & 3): the 16 lanes that read one group of 16 consecutive rows, and the 16
     // threads that write the 4 groups of 4 consecutive rows, each cover all 64 banks once.
     constexpr int SA = (BM * 4 + 255) / 256, SB = (BN * 4 + 255) / 256;
-    __shared__ bf16x8 As[BM * 4], Bs[BN * 4];
+    // LDS: the operand tiles during the k loop; with a vector epilogue, afterwards, the
+    // output tile as BF16 rows of BN + 8 elements (the padding spreads the four rows a
+    // wavefront writes per instruction over distinct banks)
+    constexpr int LDR = BN + 8;
+    constexpr int OPS = BM * 4 + BN * 4, OUT = EP::kVector ? BM * LDR / 8 : 0;
+    __shared__ bf16x8 smem[OPS > OUT ? OPS : OUT];
+    bf16x8* const As = smem;
+    bf16x8* const Bs = smem + BM * 4;
     auto slot = [](int r, int g) { return r * 4 + (g ^ ((r >> 2) & 3)); };
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv / WN, wn = wv % WN;
@@ -224,16 +246,38 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
             for (int j = 0; j < TN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if constexpr (EP::kVector) {
+        bf16* const tile = (bf16*)smem;
+        __syncthreads();                       // every wavefront done with the operand tiles
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
-                const int n = n0 + wn * TN * 16 + j * 16 + (lane & 15);
-                if (m < M) ep(m, n, acc[i][j][r], bz);
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+                    const int col = wn * TN * 16 + j * 16 + (lane & 15);
+                    tile[row * LDR + col] = (__bf16)ep.pre(n0 + col, acc[i][j][r]);
+                }
+        __syncthreads();
+        constexpr int GPR = BN / 8;            // 8-channel groups per row
+        for (int e = tid; e < BM * GPR; e += 256) {
+            const int row = e / GPR, g = e - row * GPR;
+            const int m = m0 + row, n = n0 + 8 * g;
+            if (m < M && n < ep.N) ep.store8(m, n, *(const bf16x8*)(tile + row * LDR + 8 * g));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+                    const int n = n0 + wn * TN * 16 + j * 16 + (lane & 15);
+                    if (m < M) ep(m, n, acc[i][j][r], bz);
+                }
+    }
 }
 
 template <class LA, class LB, class EP>
@@ -322,11 +366,12 @@ hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipSt
 // Block: TM x TN output tile (TM * TN = 64 * 64, 4 wavefronts of 32 x 32; TM = 32 when m
 // has at most 32 rows); grid (m tiles, n tiles, splits), split z covering pixels
 // [z kps, min(P, (z + 1) kps)), kps a multiple of 32. Channel counts are multiples of 8, so
-// an 8-row group never straddles a tap or a sub-pixel.
+// an 8-row group never straddles a tap or a sub-pixel. Registers are held to five wavefronts
+// per SIMD (measured faster than four with the compiler's free choice).
 constexpr int kWgStep = 64;
 constexpr int kWgRow = kWgStep + 8;
 template <int UP, int TM>
-__global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __restrict__ part,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgrad(Tensor dz, Tensor x, float* __restrict__ part,
                                                int P, int kps) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -369,8 +414,7 @@ __global__ __launch_bounds__(256) void k_wgrad(Tensor dz, Tensor x, float* __res
     const int a_bytes = (int)((size_t)dz.B * dz.H * dz.W * dz.cs * sizeof(bf16));
     const int b_bytes = (int)((size_t)x.B * x.H * x.W * x.cs * sizeof(bf16));
     auto load = [&](int k0) {
-        {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv); threads
-            // past the OA row groups have m_ok false, so their loads return zeros
+        if (a_act) {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv)
             int p = k0 + AP * ga;
             int yb = p / W, xx = p - yb * W;     // one division per step, then carries
             int b = yb / H, yy = yb - b * H;

@@ -14,6 +14,7 @@ __device__ __forceinline__ size_t at4(const Tensor& t, int b, int y, int x, int 
 }
 
 constexpr int kT = 256;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 inline int nblocks(size_t n) { return (int)std::min<size_t>((n + kT - 1) / kT, 65535 * 8); }
 
 // FP32 [B][2][H][W] -> NHWC BF16 with 8 channels (channels 2..7 zero)
@@ -22,50 +23,71 @@ __global__ void k_pack(const float* x, int B, int H, int W, Tensor o) {
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
         bf16* q = o.p + at4(o, b, y, xx, 0);
-        q[0] = (bf16)x[((size_t)(b * 2 + 0) * H + y) * W + xx];
-        q[1] = (bf16)x[((size_t)(b * 2 + 1) * H + y) * W + xx];
-        for (int c = 2; c < o.C; ++c) q[c] = (bf16)0.f;
+        bf16x8 v;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = (bf16)0.f;
+        v[0] = (bf16)x[((size_t)(b * 2 + 0) * H + y) * W + xx];
+        v[1] = (bf16)x[((size_t)(b * 2 + 1) * H + y) * W + xx];
+        *(bf16x8*)q = v;
+        for (int c = 8; c < o.C; c += 8) *(bf16x8*)(q + c) = bf16x8{};
     }
 }
 
+__device__ __forceinline__ bf16x8 vld(const Tensor& t, int b, int y, int x, int c) {
+    return *(const bf16x8*)(t.p + at4(t, b, y, x, c));
+}
+__device__ __forceinline__ void vst(const Tensor& t, int b, int y, int x, int c, bf16x8 v) {
+    *(bf16x8*)(t.p + at4(t, b, y, x, c)) = v;
+}
+
+// 2x2 max pooling; thread = (output pixel, group of 8 channels), 16-byte accesses
 __global__ void k_pool(Tensor x, Tensor y) {
-    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    const int G = y.C / 8;
+    const size_t n = (size_t)y.B * y.H * y.W * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % y.C;
-        const size_t p = e / y.C;
+        const int c = 8 * (int)(e % G);
+        const size_t p = e / G;
         const int xx = p % y.W, yb = p / y.W, yy = yb % y.H, b = yb / y.H;
-        float m = (float)x.p[at4(x, b, 2 * yy, 2 * xx, c)];
-        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy, 2 * xx + 1, c)]);
-        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy + 1, 2 * xx, c)]);
-        m = fmaxf(m, (float)x.p[at4(x, b, 2 * yy + 1, 2 * xx + 1, c)]);
-        y.p[at4(y, b, yy, xx, c)] = (bf16)m;
+        const bf16x8 v0 = vld(x, b, 2 * yy, 2 * xx, c), v1 = vld(x, b, 2 * yy, 2 * xx + 1, c);
+        const bf16x8 v2 = vld(x, b, 2 * yy + 1, 2 * xx, c), v3 = vld(x, b, 2 * yy + 1, 2 * xx + 1, c);
+        bf16x8 m;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            m[i] = (bf16)fmaxf(fmaxf(fmaxf((float)v0[i], (float)v1[i]), (float)v2[i]), (float)v3[i]);
+        vst(y, b, yy, xx, c, m);
     }
 }
 
 // The gradient goes to the first input (row-major in the window) equal to the maximum; then
 // every input of the window takes the ReLU derivative of x (the layer that produced x).
+// Thread = (pooled pixel, group of 8 channels).
 __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
-    const size_t n = (size_t)y.B * y.H * y.W * y.C;
+    const int G = y.C / 8;
+    const size_t n = (size_t)y.B * y.H * y.W * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % y.C;
-        const size_t p = e / y.C;
+        const int c = 8 * (int)(e % G);
+        const size_t p = e / G;
         const int xx = p % y.W, yb = p / y.W, yy = yb % y.H, b = yb / y.H;
-        const float m = (float)y.p[at4(y, b, yy, xx, c)];
-        const float g = (float)dy.p[at4(dy, b, yy, xx, c)];
-        bool done = false;
+        const bf16x8 m = vld(y, b, yy, xx, c), g = vld(dy, b, yy, xx, c);
+        bool done[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) done[i] = false;
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int iy = 2 * yy + (q >> 1), ix = 2 * xx + (q & 1);
-            const float xv = (float)x.p[at4(x, b, iy, ix, c)];
-            const bool arg = !done && xv == m;
-            done = done || arg;
-            const size_t o = at4(dx, b, iy, ix, c);
-            if (!(xv > 0.f)) dx.p[o] = (bf16)0.f;
-            else if (arg) dx.p[o] = (bf16)((float)dx.p[o] + g);
+            const bf16x8 xv = vld(x, b, iy, ix, c);
+            bf16x8 d = vld(dx, b, iy, ix, c);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bool arg = !done[i] && (float)xv[i] == (float)m[i];
+                done[i] = done[i] || arg;
+                if (!((float)xv[i] > 0.f)) d[i] = (bf16)0.f;
+                else if (arg) d[i] = (bf16)((float)d[i] + (float)g[i]);
+            }
+            vst(dx, b, iy, ix, c, d);
         }
     }
 }
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Stage 1: block k sums pixels [k*P/nblk, (k+1)*P/nblk) of every channel -> part[k][C].
 // Thread (channel group g of 8 channels, pixel lane pl) reads 16 bytes per pixel; the pixel
@@ -129,10 +151,14 @@ __global__ void k_head(Tensor a, const float* w, const float* bias, const float*
         const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
         const bf16* q = a.p + p * a.cs + a.coff;
         float s0 = bias[0], s1 = bias[1];
-        for (int c = 0; c < a.C; ++c) {
-            const float v = (float)q[c];
-            s0 = fmaf(v, w[c], s0);
-            s1 = fmaf(v, w[a.C + c], s1);
+        for (int c0 = 0; c0 < a.C; c0 += 8) {          // 16-byte loads, channels in order
+            const bf16x8 v8 = *(const bf16x8*)(q + c0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float v = (float)v8[i];
+                s0 = fmaf(v, w[c0 + i], s0);
+                s1 = fmaf(v, w[a.C + c0 + i], s1);
+            }
         }
         const size_t o0 = ((size_t)(b * 2 + 0) * H + y) * W + xx, o1 = ((size_t)(b * 2 + 1) * H + y) * W + xx;
         out[o0] = x_in[o0] + s0;
@@ -154,12 +180,12 @@ __global__ __launch_bounds__(kT) void k_mse1(const float* out, const float* t, s
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
-__global__ void k_mse2(const double* part, int nblk, size_t n, double* loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < nblk; ++k) s += part[k];
-        *loss = s / (double)n;
-    }
+__global__ __launch_bounds__(kT) void k_mse2(const double* part, int nblk, size_t n, double* loss) {
+    __shared__ double red[kT / 64];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kT) s += part[k];
+    s = block_sum(s, red);                       // fixed order
+    if (threadIdx.x == 0) *loss = s / (double)n;
 }
 
 // head backward: part[k][0..2C) = sum over the block's pixels of dout[o] * a[c] for o = 0, 1;
@@ -253,12 +279,12 @@ hipError_t pack_input(const float* x, int B, int H, int W, const Tensor& o, hipS
     return hipGetLastError();
 }
 hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s) {
-    k_pool<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(x, y);
+    k_pool<<<nblocks((size_t)y.B * y.H * y.W * (y.C / 8)), kT, 0, s>>>(x, y);
     return hipGetLastError();
 }
 hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
                            hipStream_t s) {
-    k_pool_bwd<<<nblocks((size_t)y.B * y.H * y.W * y.C), kT, 0, s>>>(x, y, dy, dx);
+    k_pool_bwd<<<nblocks((size_t)y.B * y.H * y.W * (y.C / 8)), kT, 0, s>>>(x, y, dy, dx);
     return hipGetLastError();
 }
 hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s) {
@@ -278,7 +304,7 @@ hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float
 hipError_t mse_loss(const float* out, const float* target, size_t n, double* part, int nblk,
                     double* loss, float* dout, hipStream_t s) {
     k_mse1<<<nblk, kT, 0, s>>>(out, target, n, part, nblk, dout);
-    k_mse2<<<1, 64, 0, s>>>(part, nblk, n, loss);
+    k_mse2<<<1, kT, 0, s>>>(part, nblk, n, loss);
     return hipGetLastError();
 }
 hipError_t head_bwd(const Tensor& a, const float* w, const float* dout, int B, int H, int W,
