@@ -263,9 +263,15 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
         const SliceDesc& d = D[w.x];
         if (skipped(d)) continue;
         const int a = w.y, nd = d.n_det, M = d.n_mask;
-        float* Pm = d.P + (size_t)a * nd;
-        float* Pd = d.P + ((size_t)d.n_theta + a) * nd;
-        const float* se = d.s_exp + (size_t)a * M * nd;
+        // global-address-space views of the descriptor's (generic) pointers: global loads
+        // and stores instead of flat ones
+        typedef __attribute__((address_space(1))) float gf;
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(1))) f4v gf4;
+        gf* Pm = (gf*)(d.P + (size_t)a * nd);
+        gf* Pd = (gf*)(d.P + ((size_t)d.n_theta + a) * nd);
+        const gf* se = (const gf*)(d.s_exp + (size_t)a * M * nd);
+        gf4* flat = (gf4*)d.flat;
         const double sm = d.scale_mu, sdl = d.scale_de;
         const float kap = d.kappa;
         double r2 = 0.0;
@@ -277,13 +283,16 @@ __global__ __launch_bounds__(kIcThreads) void k_ic(const SliceDesc* __restrict__
             const double pn = k > 0 ? sdl * (double)Pd[k - 1] : 0.0;
             const double T = exp(-pm);
             const double dl = (double)kap * 0.5 * (pp - pn);
-            const float4 fl = d.flat[k];       // A, c, 1/(2 s^2), 1/s^2
+            const f4v fl = flat[k];            // A, c, 1/(2 s^2), 1/s^2
             const double z = (double)fl.z, fw = (double)fl.w;
             double sf = 0.0, sfp = 0.0;
-            for (int j = 0; j < M; ++j) {
+            float s_nx = se[k];                // the next mask position's signal is loaded
+            for (int j = 0; j < M; ++j) {      // while the current one is evaluated
+                const float s_j = s_nx;
+                if (j + 1 < M) s_nx = se[(size_t)(j + 1) * nd + k];
                 const double uu = d.mask[j] - dl - (double)fl.y;
                 const double f = (double)fl.x * exp(-uu * uu * z);
-                const double r = fma(T, f, -(double)se[(size_t)j * nd + k]);
+                const double r = fma(T, f, -(double)s_j);
                 r2 = fma(r, r, r2);
                 sf = fma(r, f, sf);
                 sfp = fma(r, -uu * fw * f, sfp);
