@@ -481,6 +481,42 @@ def stack220_main(args, log):
     return 0
 
 
+def gemm_ref_main(args, log):
+    """Calibration, not part of the path: the library GEMM (torch.matmul, which calls
+    hipBLASLt) at the warm-start network's layer shapes as plain BF16 GEMMs (no im2col), for
+    comparison with the network's own implicit-GEMM and weight-gradient kernels (whose
+    per-layer times come from the kernel trace of `--workload unet_train`)."""
+    import torch
+    torch.cuda.set_device(0)
+    shapes = [("3x3 conv 32->32 at 256^2, batch 16 (pixels x Co x 9Ci)", 1048576, 32, 288),
+              ("3x3 conv 64->32 (concatenation input) at 256^2", 1048576, 32, 576),
+              ("3x3 conv 64->64 at 128^2", 262144, 64, 576),
+              ("3x3 conv 128->128 at 64^2", 65536, 128, 1152),
+              ("3x3 conv 256->256 at 32^2", 16384, 256, 2304),
+              ("weight gradient 128->128 at 64^2 (Co x 9Ci x pixels)", 128, 1152, 65536),
+              ("weight gradient 32->32 at 256^2", 32, 288, 1048576)]
+    rows = []
+    for name, M, N, K in shapes:
+        a = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(K, N, device="cuda", dtype=torch.bfloat16)
+        warm_up(lambda: a @ b)
+        reps = max(args.steps, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            a @ b
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        rows.append({"shape": name, "M": M, "N": N, "K": K, "us": round(1e6 * dt, 1),
+                     "tflops": round(2.0 * M * N * K / dt / 1e12, 1)})
+        log(f"# {name}: {1e6 * dt:.1f} us, {2.0 * M * N * K / dt / 1e12:.0f} TFLOP/s")
+    print(json.dumps({"metric": "library BF16 GEMM at the warm-start network's layer shapes",
+                      "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "dtype": "bf16",
+                      "data": "synthetic", "config": {"workload": "gemm_ref", "library": "torch.matmul (hipBLASLt)"},
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def sweeps_main(args, log):
     """Secondary sweeps (context, not targets): the projector alone at Table 1's sinogram shapes
     (N_t detector pixels = grid size, N_theta angles over 180 deg, both maps), and full h-mode
@@ -540,7 +576,8 @@ def sweeps_main(args, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["slice512", "batch256", "unet_train", "unet_infer",
-                                           "autograd1024", "paper220", "stack220", "sweeps"],
+                                           "autograd1024", "paper220", "stack220", "sweeps",
+                                           "gemm_ref"],
                     default="slice512",
                     help="slice512 (default): the headline slice; batch256: 256 mixed slices; "
                          "unet_train / unet_infer: the warm-start network; autograd1024: "
@@ -583,6 +620,8 @@ def main():
         return stack220_main(args, log)
     if args.workload == "sweeps":
         return sweeps_main(args, log)
+    if args.workload == "gemm_ref":
+        return gemm_ref_main(args, log)
 
     child = None
     if not args.no_cpu_baseline:
