@@ -116,6 +116,7 @@ struct eit_plan {
     // full model of eq. 4 (ext == 0: the plain two-map model of eq. 2)
     int ext = 0;
     int n_maps = 2;        // maps in the parameter vector (1 in h-mode)
+    int eval_maps = 2;     // maps the kernels evaluate: 1 in h-mode (R h once), else 2
     double gamma = 0.0;    // h-mode: delta = gamma h
     double off_scale = 1.0;
     int nq = 0;            // tabulated flat samples per pixel
@@ -254,6 +255,7 @@ int build_model(const eit_setup* setup, const eit_model* m, eit_plan* p, HostTab
     const int nt = p->n_theta, nd = p->n_det;
     p->ext = 0;
     p->n_maps = 2;
+    p->eval_maps = 2;
     p->nvu = p->nv;
     if (!m) return EIT_OK;
     if (m->hmode) {
@@ -261,6 +263,7 @@ int build_model(const eit_setup* setup, const eit_model* m, eit_plan* p, HostTab
         p->ext |= EXT_HMODE;
         p->gamma = m->gamma;
         p->n_maps = 1;
+        p->eval_maps = nd <= kSingleMapMaxDet ? 1 : 2;
     }
     if (m->fit_drift) p->ext |= EXT_DRIFT;
     if (m->fit_ring) p->ext |= EXT_RING;
@@ -694,6 +697,7 @@ SliceDesc base_desc(const eit_plan* p) {
     d.nq = p->nq; d.tab_u0 = p->tab_u0; d.tab_du = p->tab_du; d.ftab = p->ftab;
     d.off_scale = 1.0;
     d.nvu = p->nvu;
+    d.maps = 2;
     return d;
 }
 
@@ -704,7 +708,9 @@ void set_ext_buffers(const eit_plan* p, SliceDesc& d, void* base, const EvalLayo
     const size_t nn = (size_t)p->n * p->n;
     d.xu = x_param;
     d.xe = (p->ext & EXT_HMODE) ? (float*)at(base, L.xe) : nullptr;
-    d.x = d.xe ? d.xe : x_param;
+    d.maps = p->eval_maps;
+    // the pair evaluation reads the expanded [h, h]; the single-map one reads h in place
+    d.x = d.xe && d.maps == 2 ? d.xe : x_param;
     d.off = (p->ext & (EXT_DRIFT | EXT_RING)) ? x_param + p->n_maps * nn : nullptr;
     d.g = (float*)at(base, L.ge);
     d.g_mo = (p->ext & EXT_DRIFT) ? (double*)at(base, L.g_mo) : nullptr;
@@ -718,7 +724,7 @@ void set_split_buffers(SliceDesc& d, void* base, const EvalLayout& L) {
 
 // Adjoint launch, then (split plans) the pass that adds the parts into d.g.
 int enqueue_backproject(const eit_plan* p, const SliceDesc* dd, int add_reg, hipStream_t st) {
-    HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
+    HIP_TRY(launch_backproject(p->adj_v, 2, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
                                add_reg, st));
     if (p->adj_splits > 1)
         HIP_TRY(launch_bp_combine(dd, p->it_vec, p->n_it_vec, grid_for(p->n_it_vec, kGridCap),
@@ -754,7 +760,7 @@ namespace {
 
 int enqueue_eval(const eit_plan* p, const SliceDesc* dd, bool seeds, bool grad, hipStream_t st) {
     HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
-    HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
+    HIP_TRY(launch_project(p->proj_v, 2, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
                            p->proj_lds, st));
     HIP_TRY(launch_ic(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap), seeds ? 1 : 0, st));
     if (grad) return enqueue_backproject(p, dd, 1, st);
@@ -778,7 +784,7 @@ extern "C" int eit_project(const eit_plan* p, const float* x, float* sino, void*
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     HIP_TRY(launch_store_desc(d, dd, st));
     HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
-    HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
+    HIP_TRY(launch_project(p->proj_v, 2, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
                            p->proj_lds, st));
     return EIT_OK;
 }
@@ -823,9 +829,9 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
     set_split_buffers(d, ws, L);
     SliceDesc* dd = (SliceDesc*)at(ws, L.desc);
     if (p->ext) {
-        // full model: the maps (h expanded to [h, h], P_delta scaled by gamma) through the
-        // two-map kernels, the eq. 4 IC stage, the adjoint without regulariser and the
-        // contraction to the parameter layout
+        // full model: the maps through the two-map kernels (h-mode: h once through the
+        // single-map kernels, or expanded to [h, h]; P_delta scaled by gamma), the eq. 4 IC
+        // stage, the adjoint without regulariser and the contraction to the parameter layout
         set_ext_buffers(p, d, ws, L, x);
         d.gu = grad;
         if (p->ext & EXT_HMODE) {
@@ -834,18 +840,18 @@ extern "C" int eit_cost_and_grad(const eit_plan* p, const float* x, const float*
             d.reg_de = 0.0;
         }
         HIP_TRY(launch_store_desc(d, dd, st));
-        if (p->ext & EXT_HMODE)
+        if ((p->ext & EXT_HMODE) && p->eval_maps == 2)
             HIP_TRY(launch_ext_expand(dd, p->it_hvec, p->n_it_hvec, grid_for(p->n_it_hvec, kGridCap), st));
         HIP_TRY(launch_transpose(dd, p->it_tr, p->n_it_tr, grid_for(p->n_it_tr, kGridCap), st));
-        HIP_TRY(launch_project(p->proj_v, dd, p->it_pr, p->n_it_pr, grid_for(p->n_it_pr, kGridCap),
-                               p->proj_lds, st));
+        HIP_TRY(launch_project(p->proj_v, p->eval_maps, dd, p->it_pr, p->n_it_pr,
+                               grid_for(p->n_it_pr, kGridCap), p->proj_lds, st));
         HIP_TRY(launch_ic_ext(dd, p->it_ic, p->n_it_ic, grid_for(p->n_it_ic, kGridCap),
                               grad ? 1 : 0, p->n_det, st));
         HIP_TRY(launch_cost_reduce(dd, 1, st));
         if (!grad) return EIT_OK;
         // the contraction adds a split adjoint's partial planes itself (no combine pass)
-        HIP_TRY(launch_backproject(p->adj_v, dd, p->it_bp, p->n_it_bp, grid_for(p->n_it_bp, kGridCap),
-                                   0, st));
+        HIP_TRY(launch_backproject(p->adj_v, p->eval_maps, dd, p->it_bp, p->n_it_bp,
+                                   grid_for(p->n_it_bp, kGridCap), 0, st));
         HIP_TRY(launch_ext_contract(dd, p->it_cvec, p->n_it_cvec, grid_for(p->n_it_cvec, kGridCap), st));
         HIP_TRY(launch_ext_ring_grad(dd, p->it_ring, p->n_it_ring, grid_for(p->n_it_ring, kGridCap), st));
         return EIT_OK;
@@ -919,7 +925,7 @@ struct StepPlan {
     const LbDesc* L;
     int n_slices;
     // per projector / adjoint variant groups (batch may mix variants)
-    struct Launch { int variant; const Item* items; int n; size_t lds; };
+    struct Launch { int variant; const Item* items; int n; size_t lds; int maps; };
     std::vector<Launch> proj, adj;
     const Item* it_tr; int n_tr;
     const Item* it_ic; int n_ic;
@@ -945,14 +951,14 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
         HIP_TRY(launch_transpose(sp.D, sp.it_tr, sp.n_tr, grid_for(sp.n_tr, kGridCap), st));
         if (int rc = mark(2)) return rc;
         for (const auto& l : sp.proj)
-            HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
+            HIP_TRY(launch_project(l.variant, l.maps, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
         if (int rc = mark(3)) return rc;
         HIP_TRY(launch_ic_ext(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, sp.max_det, st));
         if (int rc = mark(4)) return rc;
         HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
         if (int rc = mark(5)) return rc;
         for (const auto& l : sp.adj)
-            HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 0, st));
+            HIP_TRY(launch_backproject(l.variant, l.maps, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 0, st));
         // the contraction adds a split adjoint's partial planes itself
         HIP_TRY(launch_ext_contract(sp.D, sp.it_cvec, sp.n_cvec, grid_for(sp.n_cvec, kGridCap), st));
         HIP_TRY(launch_ext_ring_grad(sp.D, sp.it_ring, sp.n_ring, grid_for(sp.n_ring, kGridCap), st));
@@ -967,14 +973,14 @@ int enqueue_step(const StepPlan& sp, hipStream_t st, hipEvent_t* ev) {
     if (int rc = mark(1)) return rc;
     if (int rc = mark(2)) return rc;
     for (const auto& l : sp.proj)
-        HIP_TRY(launch_project(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
+        HIP_TRY(launch_project(l.variant, l.maps, sp.D, l.items, l.n, grid_for(l.n, kGridCap), l.lds, st));
     if (int rc = mark(3)) return rc;
     HIP_TRY(launch_ic(sp.D, sp.it_ic, sp.n_ic, grid_for(sp.n_ic, kGridCap), 1, st));
     if (int rc = mark(4)) return rc;
     HIP_TRY(launch_lb_decide(sp.D, sp.L, sp.n_slices, st));
     if (int rc = mark(5)) return rc;
     for (const auto& l : sp.adj)
-        HIP_TRY(launch_backproject(l.variant, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 1, st));
+        HIP_TRY(launch_backproject(l.variant, l.maps, sp.D, l.items, l.n, grid_for(l.n, kGridCap), 1, st));
     if (int rc = mark(6)) return rc;
     HIP_TRY(launch_lb_update(sp.L, sp.it_vec, sp.n_vec, grid_for(sp.n_vec, kGridCap), st));
     if (int rc = mark(7)) return rc;
@@ -1304,8 +1310,8 @@ extern "C" int eit_reconstruct(const eit_plan* p, const float* s_exp, const eit_
 
     StepPlan sp;
     sp.D = dd; sp.L = ld; sp.n_slices = 1;
-    sp.proj.push_back({p->proj_v, p->it_pr, p->n_it_pr, p->proj_lds});
-    sp.adj.push_back({p->adj_v, p->it_bp, p->n_it_bp, 0});
+    sp.proj.push_back({p->proj_v, p->it_pr, p->n_it_pr, p->proj_lds, p->eval_maps});
+    sp.adj.push_back({p->adj_v, p->it_bp, p->n_it_bp, 0, p->eval_maps});
     sp.it_tr = p->it_tr; sp.n_tr = p->n_it_tr;
     sp.it_ic = p->it_ic; sp.n_ic = p->n_it_ic;
     sp.it_vec = p->it_uvec; sp.n_vec = p->n_it_uvec;
@@ -1399,7 +1405,8 @@ struct BatchLayout {
     std::pair<int, int> r_ring{0, 0}; // full model: pixel blocks of ring-term gradients
     std::pair<int, int> r_cvec{0, 0}; // full model: contraction chunks
     bool ext = false;                 // full-model batch (every plan has model options)
-    std::vector<std::tuple<int, int, int, size_t>> r_proj, r_adj;   // variant, off, count, lds
+    // variant, off, count, lds, maps evaluated
+    std::vector<std::tuple<int, int, int, size_t, int>> r_proj, r_adj;
 };
 
 int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout& B) {
@@ -1435,18 +1442,19 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     B.r_vec.second = (int)H.size() - B.r_vec.first;
     B.r_proj.clear();
     B.r_adj.clear();
-    for (int v = 0; v < proj_variant_count(); ++v) {
-        const int off = (int)H.size();
-        size_t lds = 0;
-        for (int i : B.order) {
-            const eit_plan* p = plans[i];
-            if (p->proj_v != v) continue;
-            lds = std::max(lds, p->proj_lds);
-            for (int g = 0; g < p->n_groups; ++g)
-                for (int b = 0; b < p->n_dblk; ++b) H.push_back(make_int4(i, g, b, 0));
+    for (int v = 0; v < proj_variant_count(); ++v)
+        for (int mp = 2; mp >= 1; --mp) {          // one launch per (variant, maps evaluated)
+            const int off = (int)H.size();
+            size_t lds = 0;
+            for (int i : B.order) {
+                const eit_plan* p = plans[i];
+                if (p->proj_v != v || p->eval_maps != mp) continue;
+                lds = std::max(lds, p->proj_lds);
+                for (int g = 0; g < p->n_groups; ++g)
+                    for (int b = 0; b < p->n_dblk; ++b) H.push_back(make_int4(i, g, b, 0));
+            }
+            if ((int)H.size() > off) B.r_proj.emplace_back(v, off, (int)H.size() - off, lds, mp);
         }
-        if ((int)H.size() > off) B.r_proj.emplace_back(v, off, (int)H.size() - off, lds);
-    }
     // the angle split only serves launches with few tiles: a batch that fills the chip
     // without it runs every slice unsplit
     long long tiles = 0;
@@ -1461,17 +1469,18 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     for (int i : B.order)
         for (int b = 0; b < plans[i]->n_it_cvec; ++b) H.push_back(make_int4(i, b, 0, 0));
     B.r_cvec.second = (int)H.size() - B.r_cvec.first;
-    for (int v = 0; v < adj_variant_count(); ++v) {
-        const int off = (int)H.size();
-        for (int i : B.order) {
-            const eit_plan* p = plans[i];
-            if (p->adj_v != v) continue;
-            for (int ty = 0; ty < p->n_ty; ++ty)
-                for (int tx = 0; tx < p->n_tx; ++tx)
-                    for (int g = 0; g < B.splits[i]; ++g) H.push_back(make_int4(i, tx, ty, g));
+    for (int v = 0; v < adj_variant_count(); ++v)
+        for (int mp = 2; mp >= 1; --mp) {
+            const int off = (int)H.size();
+            for (int i : B.order) {
+                const eit_plan* p = plans[i];
+                if (p->adj_v != v || p->eval_maps != mp) continue;
+                for (int ty = 0; ty < p->n_ty; ++ty)
+                    for (int tx = 0; tx < p->n_tx; ++tx)
+                        for (int g = 0; g < B.splits[i]; ++g) H.push_back(make_int4(i, tx, ty, g));
+            }
+            if ((int)H.size() > off) B.r_adj.emplace_back(v, off, (int)H.size() - off, (size_t)0, mp);
         }
-        if ((int)H.size() > off) B.r_adj.emplace_back(v, off, (int)H.size() - off, (size_t)0);
-    }
     Layout L;
     B.descs = L.take(sizeof(SliceDesc) * n);
     B.lbdescs = L.take(sizeof(LbDesc) * n);
@@ -1535,9 +1544,9 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
     StepPlan sp;
     sp.D = dd; sp.L = ld; sp.n_slices = n;
     for (auto& r : B.r_proj)
-        sp.proj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r)});
+        sp.proj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r), std::get<4>(r)});
     for (auto& r : B.r_adj)
-        sp.adj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r)});
+        sp.adj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r), std::get<4>(r)});
     sp.it_tr = it + B.r_dir.first; sp.n_tr = B.r_dir.second;
     sp.it_ic = it + B.r_ic.first; sp.n_ic = B.r_ic.second;
     sp.it_vec = it_vec; sp.n_vec = n_vec;

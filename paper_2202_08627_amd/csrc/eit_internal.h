@@ -72,24 +72,26 @@ struct SliceDesc {
     double* part_ic;               // [n_theta] data-term partials
     double* part_reg;              // [n_reg_blocks][2] ||mu||^2, ||delta||^2 partials
     int32_t n_reg_blocks;
-    int32_t pad0;
+    int32_t maps;                  // maps evaluated: 2 (mu, delta; also the default), or 1 in
+                                   // h-mode (R h once; P_delta = gamma scale R h, seeds summed)
     double* cost;                  // scalar cost
     const int32_t* skip;           // optional device flag: nonzero => kernels no-op
     const int32_t* skip_adj;       // optional: nonzero => adjoint no-ops
     // adjoint angle split: G = adj_splits blocks per voxel tile (1 = no split)
     int32_t adj_splits, n_pairs;   // n_pairs: entries of apairs (mirror-pair adjoint only)
     const int2* apairs;            // [n_pairs] (angle, mirror angle or -1)
-    double* bp_part;               // [G][2][n][n] FP64 partial sums of the adjoint (G > 1)
+    double* bp_part;               // [G][maps][n][n] FP64 partial sums of the adjoint (G > 1)
     // Full model of eq. 4 (ext != 0; the plain two-map model leaves every field below zero).
-    // The unknowns form one parameter vector xu: the maps (two, or h alone in h-mode, where
-    // the evaluation runs on the expanded pair [h, h] with P_delta scaled by gamma), then the
-    // per-angle drift m_o and the per-pixel ring term m_r when fitted.
+    // The unknowns form one parameter vector xu: the maps (two, or h alone in h-mode, which
+    // is evaluated once by the single-map kernels, maps == 1, or as the expanded pair [h, h],
+    // with P_delta scaled by gamma), then the per-angle drift m_o and the per-pixel ring term
+    // m_r when fitted.
     int32_t ext;                   // EXT_* flags
     int32_t nq;                    // tabulated flat: samples per pixel
     double tab_u0, tab_du;         // sample q of the table sits at u = tab_u0 + q tab_du
     const double* ftab;            // [n_det][nq] measured flat IC (EXT_TABLE)
     const float* xu;               // parameter vector of the evaluation point
-    float* xe;                     // [2][n][n] expanded maps (h-mode)
+    float* xe;                     // [2][n][n] expanded maps (h-mode pair evaluation)
     const float* off;              // offsets of the point: m_o [n_theta] then m_r [n_det]
     double off_scale;              // raw offset = off_scale * off
     double* g_mo;                  // [n_theta] sum over pixels of G_Delta (drift)
@@ -100,6 +102,9 @@ struct SliceDesc {
 
 // SliceDesc::ext flags.
 constexpr int EXT_HMODE = 1, EXT_DRIFT = 2, EXT_RING = 4, EXT_TABLE = 8;
+// h-mode plans evaluate R h once (single-map kernels) up to this many detector pixels, beyond
+// it through the pair [h, h] (the eq. 4 IC stage keeps two rows of doubles in LDS)
+constexpr int kSingleMapMaxDet = 2048;
 
 // Work items: (slice, a, b, c) -- meaning depends on the kernel.
 using Item = int4;
@@ -185,13 +190,15 @@ hipError_t launch_store_lbdesc(const LbDesc& v, LbDesc* dst, hipStream_t s);
 // ---------------------------------------------------------------- launchers (kernels.hip)
 hipError_t launch_transpose(const SliceDesc* d_descs, const Item* items, int n_items,
                             int grid, hipStream_t s);
-hipError_t launch_project(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
-                          int grid, size_t lds_bytes, hipStream_t s);
+// maps: 2 (the pair of maps) or 1 (map 0 only; its projections land in plane 0)
+hipError_t launch_project(int variant, int maps, const SliceDesc* d_descs, const Item* items,
+                          int n_items, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_ic(const SliceDesc* d_descs, const Item* items, int n_items, int grid,
                      int want_seeds, hipStream_t s);
 hipError_t launch_cost_reduce(const SliceDesc* d_descs, int n_slices, hipStream_t s);
-hipError_t launch_backproject(int variant, const SliceDesc* d_descs, const Item* items, int n_items,
-                              int grid, int add_reg, hipStream_t s);
+// maps: 2 (both seed planes into both gradient planes) or 1 (seed plane 0 into plane 0)
+hipError_t launch_backproject(int variant, int maps, const SliceDesc* d_descs, const Item* items,
+                              int n_items, int grid, int add_reg, hipStream_t s);
 hipError_t launch_bp_combine(const SliceDesc* d_descs, const Item* vec_items, int n_items, int grid,
                              int add_reg, hipStream_t s);
 

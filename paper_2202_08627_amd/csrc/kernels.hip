@@ -13,8 +13,9 @@
 namespace eit {
 
 // ------------------------------------------------------------------------ transpose
-// Item (slice, tile_x, tile_y, -): 32x32 tile of both maps through LDS. Also writes the
-// tile's sums of mu^2 and delta^2 (FP64) to part_reg[tile] for the regulariser.
+// Item (slice, tile_x, tile_y, -): 32x32 tile of both maps (map 0 alone when d.maps == 1)
+// through LDS. Also writes the tile's sums of mu^2 and delta^2 (FP64) to part_reg[tile] for
+// the regulariser.
 __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __restrict__ D,
                                                          const Item* __restrict__ items,
                                                          int n_items) {
@@ -26,9 +27,9 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
         const SliceDesc& d = D[w.x];
         if (skipped(d)) continue;
         const int n = d.n, tx = w.y, ty = w.z;
+        const int nm = d.maps == 1 ? 1 : 2;
         double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < nm; ++c) {
             const float* src = d.x + (size_t)c * n * n;
             for (int r = ly; r < kTrTile; r += 8) {
                 const int j = ty * kTrTile + r, i = tx * kTrTile + lx;
@@ -40,8 +41,7 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < nm; ++c) {
             float* dst = d.xT + (size_t)c * n * n;
             for (int r = ly; r < kTrTile; r += 8) {
                 const int i = tx * kTrTile + r, j = ty * kTrTile + lx;
@@ -80,7 +80,9 @@ __global__ __launch_bounds__(kTrThreads) void k_transpose(const SliceDesc* __res
 // the benchmark and test geometries.
 // Interleaved 16-row variants are held to 80 VGPRs (six wavefronts per SIMD, three 512-thread
 // blocks per CU); unconstrained they take 84 and only two blocks fit.
-template <int A, int W, int R, int PW, int DUP, int LP, int IL>
+// MP = 1 projects map 0 alone (h-mode): entries hold one map (x_c, or x_c and x_{c+1} - x_c),
+// a sample is one FMA pair fewer, and only plane 0 of P is written.
+template <int A, int W, int R, int PW, int DUP, int LP, int IL, int MP>
 __global__ __launch_bounds__(A* W) __attribute__((amdgpu_waves_per_eu(IL && R >= 16 ? 6 : 1)))
 void k_project(const SliceDesc* __restrict__ D,
                                                   const Item* __restrict__ items, int n_items) {
@@ -94,7 +96,9 @@ void k_project(const SliceDesc* __restrict__ D,
     static_assert(R % RS == 0, "strip must tile the block");
     static_assert(LP <= PW, "LDS rows hold at most the staged width");
     constexpr int SLOTS = R / RS * CS;
-    typedef typename std::conditional<DUP != 0, float4, float2>::type Entry;
+    static_assert(MP == 1 || MP == 2, "one or two maps");
+    typedef typename std::conditional<MP == 2, typename std::conditional<DUP != 0, float4, float2>::type,
+                                      typename std::conditional<DUP != 0, float2, float>::type>::type Entry;
     // LDS rows of LP entries (LP <= PW; window columns past LP are never staged or read)
     __shared__ Entry win[R * LP];
     const int tid = threadIdx.x;
@@ -153,10 +157,14 @@ void k_project(const SliceDesc* __restrict__ D,
         // or outside the map reads as zero; entry win_w - 1's second half is never used)
         Entry buf[SLOTS];
         auto load_pair = [&](int q, int vo, int vo1) {
-            if constexpr (DUP != 0)
+            if constexpr (MP == 1) {
+                if constexpr (DUP != 0) buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bm, vo1));
+                else buf[q] = buf_ld(bm, vo);
+            } else if constexpr (DUP != 0) {
                 buf[q] = make_float4(buf_ld(bm, vo), buf_ld(bd, vo), buf_ld(bm, vo1), buf_ld(bd, vo1));
-            else
+            } else {
                 buf[q] = make_float2(buf_ld(bm, vo), buf_ld(bd, vo));
+            }
         };
         // (WIDE staging) a wavefront whose first staged column lies past the window skips its
         // loads and LDS writes: entries at or past win_w are never read
@@ -195,9 +203,11 @@ void k_project(const SliceDesc* __restrict__ D,
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
                 Entry e = buf[q];
-                if constexpr (DUP != 0) {      // stored as (x_c, x_{c+1} - x_c) per map
+                if constexpr (DUP != 0 && MP == 2) {   // stored as (x_c, x_{c+1} - x_c) per map
                     e.z -= e.x;
                     e.w -= e.y;
+                } else if constexpr (DUP != 0) {
+                    e.y -= e.x;
                 }
                 if constexpr (WIDE) {
                     if (c0w < win_w && (LP == PW || sc < LP)) win[(sr + q * RS) * LP + sc] = e;
@@ -222,7 +232,13 @@ void k_project(const SliceDesc* __restrict__ D,
                 const float u = r == 0 ? uf : fmaf((float)r, slope_f, uf);
                 const float ph = __builtin_amdgcn_fractf(u);
                 const Entry* q = rowp + r * LP + (int)u;
-                if constexpr (DUP != 0) {
+                if constexpr (MP == 1 && DUP != 0) {
+                    const float2 v = *(const float2*)q;
+                    c0 = fmaf(ph, v.y, c0 + v.x);
+                } else if constexpr (MP == 1) {
+                    const float v0 = ((const float*)q)[0], v1 = ((const float*)q)[1];
+                    c0 = fmaf(ph, v1, fmaf(1.f - ph, v0, c0));
+                } else if constexpr (DUP != 0) {
                     // x_c + ph (x_{c+1} - x_c): the interpolation without a 1 - ph weight
                     const float4 v = *(const float4*)q;
                     c0 = fmaf(ph, v.z, c0 + v.x);
@@ -239,7 +255,7 @@ void k_project(const SliceDesc* __restrict__ D,
         }
         if (a >= 0 && k < d.n_det) {
             d.P[(size_t)a * d.n_det + k] = (float)(wstep * acc_m);
-            d.P[((size_t)d.n_theta + a) * d.n_det + k] = (float)(wstep * acc_d);
+            if constexpr (MP == 2) d.P[((size_t)d.n_theta + a) * d.n_det + k] = (float)(wstep * acc_d);
         }
     }
 }
@@ -397,7 +413,9 @@ __device__ __forceinline__ TileWin tile_window(const AdjAngle* q, int i0, int j0
 // Index safety: a voxel's coordinate relative to the window is u >= 1 - 1e-5 (lo is one bin
 // below the tile's lowest crossing) and floor(u) + 1 <= kwin - 1 (kwin bounds the tile's
 // span plus margin); the host tests replay this arithmetic for every tile and angle.
-template <int TX, int TY, int AC, int VPT>
+// MP = 1 backprojects seed plane 0 alone into gradient plane 0 (h-mode: the summed seeds);
+// the staged entries are then (G of bin c, G of bin c + 1).
+template <int TX, int TY, int AC, int VPT, int MP>
 __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* __restrict__ D,
                                                               const Item* __restrict__ items,
                                                               int n_items, int add_reg) {
@@ -410,7 +428,10 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
     constexpr int SLOTS = AC / AS;
     constexpr int JS = TY / VPT;
     static_assert(TX != 32 || JS % 4 == 0, "16 x 4 wavefront patches");
-    __shared__ float4 gw[AC * PK];
+    static_assert(MP == 1 || MP == 2, "one or two maps");
+    typedef typename std::conditional<MP == 2, float4, float2>::type GEntry;
+    typedef typename std::conditional<MP == 2, float2, float>::type GLoad;
+    __shared__ GEntry gw[AC * PK];
     __shared__ float4 rec[2][AC];            // cs, sn, offset, 1/w   (double-buffered by chunk)
     __shared__ float rec2[2][AC];            // 1 - 1/w
     __shared__ int los[2][AC];
@@ -453,7 +474,7 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 los[ch & 1][tid] = lo;
             }
         };
-        float2 buf[SLOTS];
+        GLoad buf[SLOTS];
         auto load_chunk = [&](int ch) {
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
@@ -462,7 +483,8 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 const int k = los[ch & 1][aa] + sb;
                 const bool ok = a < nth && sb < kwin && (unsigned)k < (unsigned)nd;
                 const int vo = ok ? (a * nd + k) * 4 : kBufOOB;
-                buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+                if constexpr (MP == 2) buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+                else buf[q] = buf_ld(bGm, vo);
             }
         };
         __syncthreads();                  // LDS of the previous work item fully consumed
@@ -479,10 +501,17 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
             for (int q = 0; q < SLOTS; ++q) {
                 // bin sb + 1 of the same angle is held by the next lane (PK divides 64)
                 const float iw = rec[ch & 1][sa + q * AS].w;
-                const float gm = iw * buf[q].x, gd = iw * buf[q].y;
-                float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
-                if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
-                gw[(sa + q * AS) * PK + sb] = make_float4(gm, gd, nm, nd1);
+                if constexpr (MP == 2) {
+                    const float gm = iw * buf[q].x, gd = iw * buf[q].y;
+                    float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
+                    if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
+                    gw[(sa + q * AS) * PK + sb] = make_float4(gm, gd, nm, nd1);
+                } else {
+                    const float gm = iw * buf[q];
+                    float nm = __shfl_down(gm, 1);
+                    if (sb == PK - 1) nm = 0.f;
+                    gw[(sa + q * AS) * PK + sb] = make_float2(gm, nm);
+                }
             }
             if (ch + 1 < ch1) angle_setup(ch + 1);
             __syncthreads();
@@ -496,9 +525,9 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 const float4 r1 = rec[cb][aa];
                 const float omw = rec2[cb][aa];
                 const float u0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
-                const float4* row = gw + aa * PK;
+                const GEntry* row = gw + aa * PK;
                 // all of the thread's bin reads for this angle are issued before any is used
-                float4 g[VPT];
+                GEntry g[VPT];
                 float f[VPT];
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
@@ -510,8 +539,12 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 for (int q = 0; q < VPT; ++q) {
                     const float w0 = __builtin_amdgcn_fmed3f(fmaf(-f[q], r1.w, 1.f), 0.f, 1.f);
                     const float w1 = __builtin_amdgcn_fmed3f(fmaf(f[q], r1.w, omw), 0.f, 1.f);
-                    am[q] = fmaf(w0, g[q].x, fmaf(w1, g[q].z, am[q]));
-                    ad[q] = fmaf(w0, g[q].y, fmaf(w1, g[q].w, ad[q]));
+                    if constexpr (MP == 2) {
+                        am[q] = fmaf(w0, g[q].x, fmaf(w1, g[q].z, am[q]));
+                        ad[q] = fmaf(w0, g[q].y, fmaf(w1, g[q].w, ad[q]));
+                    } else {
+                        am[q] = fmaf(w0, g[q].x, fmaf(w1, g[q].y, am[q]));
+                    }
                 }
             }
 #pragma unroll
@@ -523,13 +556,13 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
         const int i = i0 + il;
         if (G > 1) {
             const size_t nn = (size_t)n * n;
-            double* part = d.bp_part + (size_t)gs * 2 * nn;
+            double* part = d.bp_part + (size_t)gs * MP * nn;
 #pragma unroll
             for (int q = 0; q < VPT; ++q) {
                 const int j = j0 + jl + q * JS;
                 if (i < n && j < n) {
                     part[(size_t)j * n + i] = acc_m[q];
-                    part[nn + (size_t)j * n + i] = acc_d[q];
+                    if constexpr (MP == 2) part[nn + (size_t)j * n + i] = acc_d[q];
                 }
             }
             continue;
@@ -543,10 +576,10 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
                 double vm = acc_m[q], vd = acc_d[q];
                 if (add_reg) {
                     vm = fma(d.reg_mu, (double)d.x[o], vm);
-                    vd = fma(d.reg_de, (double)d.x[o2], vd);
+                    if constexpr (MP == 2) vd = fma(d.reg_de, (double)d.x[o2], vd);
                 }
                 d.g[o] = (float)vm;
-                d.g[o2] = (float)vd;
+                if constexpr (MP == 2) d.g[o2] = (float)vd;
             }
         }
     }
@@ -567,8 +600,9 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject(const SliceDesc* _
 // and v' through W0 and W3. Item (slice, tile_x, tile_y, part): the tile's rows j lie in the
 // top half; a thread writes v when 2j <= n-1 and v' = (i, n-1-j) when 2j < n-1, so every voxel
 // (the middle row of an odd map included) is written once. Summation order: per voxel, the
-// pairs in order, a before b, FP32 within a chunk of AC pairs, chunk sums in FP64.
-template <int TX, int TY, int AC, int VPT>
+// pairs in order, a before b, FP32 within a chunk of AC pairs, chunk sums in FP64. MP = 1:
+// seed plane 0 alone into gradient plane 0, as in k_backproject.
+template <int TX, int TY, int AC, int VPT, int MP>
 __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDesc* __restrict__ D,
                                                                    const Item* __restrict__ items,
                                                                    int n_items, int add_reg) {
@@ -582,7 +616,10 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
     constexpr int SLOTS = NR / AS;
     constexpr int JS = TY / VPT;
     static_assert(TX != 32 || JS % 4 == 0, "16 x 4 wavefront patches");
-    __shared__ float4 gw[NR * PK];
+    static_assert(MP == 1 || MP == 2, "one or two maps");
+    typedef typename std::conditional<MP == 2, float4, float2>::type GEntry;
+    typedef typename std::conditional<MP == 2, float2, float>::type GLoad;
+    __shared__ GEntry gw[NR * PK];
     __shared__ float4 rec[2][AC];            // cs, sn, offset of u, 1/w   (double-buffered)
     __shared__ float2 rec2[2][AC];           // offset of u_s, 1 - 1/w
     __shared__ int4 wins[2][AC];             // a, b, window origin for u, for u_s
@@ -626,7 +663,7 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
                 wins[ch & 1][tid] = wv;
             }
         };
-        float2 buf[SLOTS];
+        GLoad buf[SLOTS];
         auto load_chunk = [&](int ch) {
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) {
@@ -637,7 +674,8 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
                 const int k = (wk == 1 || wk == 3) ? nd - 1 - lo - sb : lo + sb;
                 const bool ok = ang >= 0 && sb < kwin && (unsigned)k < (unsigned)nd;
                 const int vo = ok ? (ang * nd + k) * 4 : kBufOOB;
-                buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+                if constexpr (MP == 2) buf[q] = make_float2(buf_ld(bGm, vo), buf_ld(bGd, vo));
+                else buf[q] = buf_ld(bGm, vo);
             }
         };
         __syncthreads();                  // LDS of the previous work item fully consumed
@@ -655,10 +693,17 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
                 // the next bin of the same window row is held by the next lane (PK divides 64)
                 const int rr = sr + q * AS;
                 const float iw = rec[ch & 1][rr >> 2].w;
-                const float gm = iw * buf[q].x, gd = iw * buf[q].y;
-                float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
-                if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
-                gw[rr * PK + sb] = make_float4(gm, gd, nm, nd1);
+                if constexpr (MP == 2) {
+                    const float gm = iw * buf[q].x, gd = iw * buf[q].y;
+                    float nm = __shfl_down(gm, 1), nd1 = __shfl_down(gd, 1);
+                    if (sb == PK - 1) { nm = 0.f; nd1 = 0.f; }   // bin PK is never read
+                    gw[rr * PK + sb] = make_float4(gm, gd, nm, nd1);
+                } else {
+                    const float gm = iw * buf[q];
+                    float nm = __shfl_down(gm, 1);
+                    if (sb == PK - 1) nm = 0.f;
+                    gw[rr * PK + sb] = make_float2(gm, nm);
+                }
             }
             if (ch + 1 < ch1) pair_setup(ch + 1);
             __syncthreads();
@@ -673,8 +718,8 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
                 const float2 r2 = rec2[cb][pp];
                 const float uu0 = fmaf(fil, r1.x, fmaf(fjl, r1.y, r1.z));
                 const float us0 = fmaf(fil, -r1.x, fmaf(fjl, r1.y, r2.x));
-                const float4* row = gw + pp * 4 * PK;
-                float4 g0[VPT], g1[VPT], g2[VPT], g3[VPT];
+                const GEntry* row = gw + pp * 4 * PK;
+                GEntry g0[VPT], g1[VPT], g2[VPT], g3[VPT];
                 float fu[VPT], fs[VPT];
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
@@ -694,14 +739,21 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
                     const float u1 = __builtin_amdgcn_fmed3f(fmaf(fu[q], r1.w, r2.y), 0.f, 1.f);
                     const float s0 = __builtin_amdgcn_fmed3f(fmaf(-fs[q], r1.w, 1.f), 0.f, 1.f);
                     const float s1 = __builtin_amdgcn_fmed3f(fmaf(fs[q], r1.w, r2.y), 0.f, 1.f);
-                    am[q] = fmaf(u0, g0[q].x, fmaf(u1, g0[q].z, am[q]));
-                    ad[q] = fmaf(u0, g0[q].y, fmaf(u1, g0[q].w, ad[q]));
-                    bm[q] = fmaf(u0, g1[q].x, fmaf(u1, g1[q].z, bm[q]));
-                    bd[q] = fmaf(u0, g1[q].y, fmaf(u1, g1[q].w, bd[q]));
-                    am[q] = fmaf(s0, g2[q].x, fmaf(s1, g2[q].z, am[q]));
-                    ad[q] = fmaf(s0, g2[q].y, fmaf(s1, g2[q].w, ad[q]));
-                    bm[q] = fmaf(s0, g3[q].x, fmaf(s1, g3[q].z, bm[q]));
-                    bd[q] = fmaf(s0, g3[q].y, fmaf(s1, g3[q].w, bd[q]));
+                    if constexpr (MP == 2) {
+                        am[q] = fmaf(u0, g0[q].x, fmaf(u1, g0[q].z, am[q]));
+                        ad[q] = fmaf(u0, g0[q].y, fmaf(u1, g0[q].w, ad[q]));
+                        bm[q] = fmaf(u0, g1[q].x, fmaf(u1, g1[q].z, bm[q]));
+                        bd[q] = fmaf(u0, g1[q].y, fmaf(u1, g1[q].w, bd[q]));
+                        am[q] = fmaf(s0, g2[q].x, fmaf(s1, g2[q].z, am[q]));
+                        ad[q] = fmaf(s0, g2[q].y, fmaf(s1, g2[q].w, ad[q]));
+                        bm[q] = fmaf(s0, g3[q].x, fmaf(s1, g3[q].z, bm[q]));
+                        bd[q] = fmaf(s0, g3[q].y, fmaf(s1, g3[q].w, bd[q]));
+                    } else {
+                        am[q] = fmaf(u0, g0[q].x, fmaf(u1, g0[q].y, am[q]));
+                        bm[q] = fmaf(u0, g1[q].x, fmaf(u1, g1[q].y, bm[q]));
+                        am[q] = fmaf(s0, g2[q].x, fmaf(s1, g2[q].y, am[q]));
+                        bm[q] = fmaf(s0, g3[q].x, fmaf(s1, g3[q].y, bm[q]));
+                    }
                 }
             }
 #pragma unroll
@@ -721,28 +773,34 @@ __global__ __launch_bounds__(TX* TY / VPT) void k_backproject_pair(const SliceDe
             const bool wrm = i < n && 2 * j < n - 1;
             const size_t o = (size_t)j * n + i, om = (size_t)jm * n + i;
             if (G > 1) {
-                double* part = d.bp_part + (size_t)gs * 2 * nn;
-                if (wr) { part[o] = acc_m[q]; part[nn + o] = acc_d[q]; }
-                if (wrm) { part[om] = mir_m[q]; part[nn + om] = mir_d[q]; }
+                double* part = d.bp_part + (size_t)gs * MP * nn;
+                if (wr) {
+                    part[o] = acc_m[q];
+                    if constexpr (MP == 2) part[nn + o] = acc_d[q];
+                }
+                if (wrm) {
+                    part[om] = mir_m[q];
+                    if constexpr (MP == 2) part[nn + om] = mir_d[q];
+                }
                 continue;
             }
             if (wr) {
                 double vm = acc_m[q], vd = acc_d[q];
                 if (add_reg) {
                     vm = fma(d.reg_mu, (double)d.x[o], vm);
-                    vd = fma(d.reg_de, (double)d.x[nn + o], vd);
+                    if constexpr (MP == 2) vd = fma(d.reg_de, (double)d.x[nn + o], vd);
                 }
                 d.g[o] = (float)vm;
-                d.g[nn + o] = (float)vd;
+                if constexpr (MP == 2) d.g[nn + o] = (float)vd;
             }
             if (wrm) {
                 double vm = mir_m[q], vd = mir_d[q];
                 if (add_reg) {
                     vm = fma(d.reg_mu, (double)d.x[om], vm);
-                    vd = fma(d.reg_de, (double)d.x[nn + om], vd);
+                    if constexpr (MP == 2) vd = fma(d.reg_de, (double)d.x[nn + om], vd);
                 }
                 d.g[om] = (float)vm;
-                d.g[nn + om] = (float)vd;
+                if constexpr (MP == 2) d.g[nn + om] = (float)vd;
             }
         }
     }
@@ -839,14 +897,18 @@ hipError_t launch_transpose(const SliceDesc* D, const Item* items, int n_items, 
     return hipGetLastError();
 }
 
-hipError_t launch_project(int variant, const SliceDesc* D, const Item* items, int n_items,
-                          int grid, size_t lds, hipStream_t s) {
+hipError_t launch_project(int variant, int maps, const SliceDesc* D, const Item* items,
+                          int n_items, int grid, size_t lds, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, A, W, R, PW, DUP, LP, IL)                                                  \
-    if (variant == id) {                                                                 \
-        (void)lds;                                                                       \
-        k_project<A, W, R, PW, DUP, LP, IL><<<grid, A * W, 0, s>>>(D, items, n_items);   \
-        return hipGetLastError();                                                        \
+    if (maps != 1 && maps != 2) return hipErrorInvalidValue;
+#define X(id, A, W, R, PW, DUP, LP, IL)                                                     \
+    if (variant == id) {                                                                    \
+        (void)lds;                                                                          \
+        if (maps == 1)                                                                      \
+            k_project<A, W, R, PW, DUP, LP, IL, 1><<<grid, A * W, 0, s>>>(D, items, n_items); \
+        else                                                                                \
+            k_project<A, W, R, PW, DUP, LP, IL, 2><<<grid, A * W, 0, s>>>(D, items, n_items); \
+        return hipGetLastError();                                                           \
     }
     EIT_PROJ_VARIANTS(X)
 #undef X
@@ -865,18 +927,24 @@ hipError_t launch_cost_reduce(const SliceDesc* D, int n_slices, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(int variant, const SliceDesc* D, const Item* items, int n_items,
-                              int grid, int add_reg, hipStream_t s) {
+template <int TX, int TY, int AC, int VPT, int MIR, int MP>
+void launch_adjoint_kernel(const SliceDesc* D, const Item* items, int n_items, int grid,
+                           int add_reg, hipStream_t s) {
+    if constexpr (MIR != 0)
+        k_backproject_pair<TX, TY, AC, VPT, MP><<<grid, TX * TY / VPT, 0, s>>>(D, items, n_items, add_reg);
+    else
+        k_backproject<TX, TY, AC, VPT, MP><<<grid, TX * TY / VPT, 0, s>>>(D, items, n_items, add_reg);
+}
+
+hipError_t launch_backproject(int variant, int maps, const SliceDesc* D, const Item* items,
+                              int n_items, int grid, int add_reg, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-#define X(id, TX, TY, AC, VPT, MIR)                                                       \
-    if (variant == id) {                                                                  \
-        if constexpr (MIR != 0)                                                           \
-            k_backproject_pair<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(           \
-                D, items, n_items, add_reg);                                              \
-        else                                                                              \
-            k_backproject<TX, TY, AC, VPT><<<grid, TX * TY / VPT, 0, s>>>(D, items,       \
-                                                                         n_items, add_reg); \
-        return hipGetLastError();                                                         \
+    if (maps != 1 && maps != 2) return hipErrorInvalidValue;
+#define X(id, TX, TY, AC, VPT, MIR)                                                        \
+    if (variant == id) {                                                                   \
+        if (maps == 1) launch_adjoint_kernel<TX, TY, AC, VPT, MIR, 1>(D, items, n_items, grid, add_reg, s); \
+        else launch_adjoint_kernel<TX, TY, AC, VPT, MIR, 2>(D, items, n_items, grid, add_reg, s);           \
+        return hipGetLastError();                                                          \
     }
     EIT_ADJ_VARIANTS(X)
 #undef X

@@ -231,8 +231,9 @@ __device__ __forceinline__ void st8(float* __restrict__ p, int64_t e, int64_t nv
 // Item (slice, chunk) over the optimiser's vector, for the full model of eq. 4 whose vector
 // (maps, then offsets) is not a pair of maps: the same direction and trial point as
 // k_lb_direction (FP64 combination, history slots requested a batch at a time), a thread
-// owning 8 consecutive elements, without the fused transpose. In h-mode the trial point's
-// map is also written twice into the expanded pair D.xe that the two-map kernels evaluate.
+// owning 8 consecutive elements, without the fused transpose. In h-mode with the pair
+// evaluation the trial point's map is also written twice into the expanded pair D.xe that
+// the two-map kernels evaluate (the single-map evaluation reads the trial point itself).
 __global__ __launch_bounds__(kVecThreads) void k_lb_direction_vec(const LbDesc* __restrict__ L,
                                                                  const SliceDesc* __restrict__ D,
                                                                  const Item* __restrict__ items,
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(kVecThreads) void k_lb_direction_vec(const LbDesc* 
             for (int u = 0; u < 8; ++u) tv[u] = (float)fma(alpha, dv[u], (double)zv[u]);
         }
         st8(l.zt, e, nv, vec, tv);
-        if ((dsc.ext & EXT_HMODE) && e < l.nn) {
+        if ((dsc.ext & EXT_HMODE) && dsc.maps != 1 && e < l.nn) {   // pair evaluation only
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (e + u < l.nn) {

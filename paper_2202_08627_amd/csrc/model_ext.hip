@@ -1,9 +1,11 @@
 // The paper's full forward model (theory section, eq. 4) on top of the two-map kernels:
 //   s_mod[a][j][k] = T[a][k] f_k(m_j - m_o[a] - m_r[k] - Delta[a][k]),
 // with three extensions of the plain model, each optional (SliceDesc::ext):
-//   * h-mode (homogeneous object): one map h with mu = h and delta = gamma h. The projector and
-//     the adjoint run unchanged on the expanded pair [h, h] with P_delta scaled by gamma, and
-//     the gradient is the sum of the two adjoint planes (chain rule: d/dh = d/dmu + gamma d/ddelta);
+//   * h-mode (homogeneous object): one map h with mu = h and delta = gamma h. The projector's
+//     and the adjoint's single-map forms project h once (P_mu and P_delta are that projection
+//     scaled by scale_mu and gamma scale_mu) and backproject the sum of the two scaled seeds
+//     (chain rule: d/dh = d/dmu + gamma d/ddelta). Slices wider than kSingleMapMaxDet run the
+//     two-map kernels on the expanded pair [h, h] and add the two adjoint planes instead;
 //   * per-angle drift m_o and per-pixel ring term m_r of the sample mask: unknowns whose
 //     derivatives are sums of G_Delta = dS/dDelta over pixels (m_o) or angles (m_r), since u
 //     depends on m_o, m_r and Delta with the same coefficient;
@@ -48,9 +50,14 @@ __device__ __forceinline__ void flat_eval(const SliceDesc& d, int k, float4 fl, 
 // in place of the projections), with the offsets of the point and the flat of the plan.
 // Also: g_mo[a] = sum_k G_Delta[a][k] (drift, fixed-order block sum) and g_dl[a][k] =
 // G_Delta[a][k] (ring; summed over angles by k_ext_ring_grad). G_Delta of the angle's row
-// waits in dynamically sized LDS (n_det doubles of the widest slice in the launch), and the
+// waits in dynamically sized LDS (2 n_det doubles of the widest slice in the launch), and the
 // block has 256 threads when no slice has more than 256 detector pixels, else 512.
+// Single-map evaluation (d.maps == 1, h-mode): plane 0 holds R h, read as P_mu = scale_mu R h
+// and P_delta = scale_de R h (scale_de = gamma scale_mu), and the seed written back to plane 0
+// is the sum of the two scaled seeds, which the one-map adjoint turns into the h gradient. The
+// mu part waits in LDS until every thread has read its neighbours' projections.
 constexpr int kExtMaxDet = 4096;
+static_assert(kSingleMapMaxDet * 2 <= kExtMaxDet, "single-map rows fit the LDS bound");
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ic_ext(const SliceDesc* __restrict__ D,
                                                const Item* __restrict__ items,
@@ -62,8 +69,10 @@ __global__ __launch_bounds__(NT) void k_ic_ext(const SliceDesc* __restrict__ D,
         const SliceDesc& d = D[w.x];
         if (skipped(d)) continue;
         const int a = w.y, nd = d.n_det, M = d.n_mask, nt = d.n_theta;
+        const bool one = d.maps == 1;
         float* Pm = d.P + (size_t)a * nd;
-        float* Pd = d.P + ((size_t)nt + a) * nd;
+        float* Pd = one ? Pm : d.P + ((size_t)nt + a) * nd;
+        double* gmu = gdl + nd;              // single-map: scaled mu seeds of the row
         const float* se = d.s_exp + (size_t)a * M * nd;
         const double sm = d.scale_mu, sdl = d.scale_de;
         const double kap = (double)d.kappa;
@@ -89,7 +98,8 @@ __global__ __launch_bounds__(NT) void k_ic_ext(const SliceDesc* __restrict__ D,
             }
             const double gD = -2.0 * T * sfp;                 // G_Delta
             if (want_seeds) {
-                Pm[k] = (float)(sm * (-2.0 * T * sf));        // G_Pmu, scaled
+                if (one) gmu[k] = sm * (-2.0 * T * sf);
+                else Pm[k] = (float)(sm * (-2.0 * T * sf));   // G_Pmu, scaled
                 gdl[k] = gD;
                 if (mr) d.g_dl[(size_t)a * nd + k] = gD;
             }
@@ -100,7 +110,8 @@ __global__ __launch_bounds__(NT) void k_ic_ext(const SliceDesc* __restrict__ D,
             for (int k = threadIdx.x; k < nd; k += NT) {
                 const double gp = k + 1 < nd ? gdl[k + 1] : 0.0;
                 const double gn = k > 0 ? gdl[k - 1] : 0.0;
-                Pd[k] = (float)(sdl * (-kap * 0.5 * (gp - gn)));
+                const double gd = sdl * (-kap * 0.5 * (gp - gn));   // G_Pdelta, scaled
+                Pd[k] = (float)(one ? gmu[k] + gd : gd);
             }
         }
         r2 = block_sum(r2, red);
@@ -134,8 +145,9 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_expand(const SliceDesc* __r
 
 // ------------------------------------------------------------------------ contraction
 // Item (slice, chunk) over the parameter vector: the gradient in the parameter layout from
-// the adjoint's two planes (computed without the regulariser), the point xu and the offset
-// sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h);
+// the adjoint's planes (computed without the regulariser), the point xu and the offset
+// sums. Maps: g_mu, g_delta (+ 2 lambda x), or in h-mode g_mu + g_delta (+ 2 lambda h), the
+// single-map evaluation's one plane already being that sum;
 // drift: off_scale * g_mo[a]. The ring entries are written by k_ext_ring_grad. The planes are
 // g, or with a split adjoint the FP64 partial planes added here in part order.
 __device__ __forceinline__ double adj_plane(const SliceDesc& d, int64_t e, int64_t nv2) {
@@ -160,7 +172,9 @@ __global__ __launch_bounds__(kVecThreads) void k_ext_contract(const SliceDesc* _
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
             double v;
             if (e < maps_end) {
-                if (hm) {
+                if (hm && d.maps == 1) {        // one plane: the adjoint of the summed seeds
+                    v = fma(d.reg_mu, (double)d.xu[e], adj_plane(d, e, nn));
+                } else if (hm) {
                     v = adj_plane(d, e, 2 * nn) + adj_plane(d, nn + e, 2 * nn);
                     v = fma(d.reg_mu, (double)d.xu[e], v);
                 } else {
@@ -280,7 +294,9 @@ hipError_t launch_ic_ext(const SliceDesc* D, const Item* items, int n_items, int
                          int want_seeds, int max_det, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (max_det < 1 || max_det > kExtMaxDet) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * (size_t)max_det;
+    // G_Delta, then the single-map mu seeds (single-map slices have n_det <= kExtMaxDet / 2):
+    // 2 max_det doubles, or kExtMaxDet when the widest slice is wider than that
+    const size_t lds = sizeof(double) * (size_t)(max_det <= kExtMaxDet / 2 ? 2 * max_det : kExtMaxDet);
     if (max_det <= 256)
         k_ic_ext<256><<<grid, 256, lds, s>>>(D, items, n_items, want_seeds);
     else

@@ -42,6 +42,11 @@ SMALL_H = dataclasses.replace(tiny_cfg(n=48, n_theta=80, n_mask=1, jitter=0.05),
                               mask_list=(0.3,), sigma=0.3, kappa=1.0, gamma_h=5.0, flat_scans=1,
                               drift_amp=0.02, n_ellipses=6)
 PAPER = configs.PAPER_220
+# h-mode with more than 2048 detector pixels: evaluated as the pair [h, h] by the two-map
+# kernels (every other h-mode case runs the single-map kernels)
+WIDE_H = dataclasses.replace(tiny_cfg(n=24, n_theta=12, n_mask=1, n_det=2056, jitter=0.05),
+                             angle_span=2.0, mask_list=(0.3,), sigma=0.3, kappa=1.0, gamma_h=5.0,
+                             flat_scans=1, drift_amp=0.02, n_ellipses=3)
 
 
 def oracle_setup(c, model):
@@ -86,6 +91,7 @@ OPTIONS = [
     ("two-map-all", SMALL_EXT, dict(hmode=False, fit_drift=True, fit_ring=True)),
     ("hmode-all", SMALL_H, dict(hmode=True, fit_drift=True, fit_ring=True)),
     ("paper-all", PAPER, dict(hmode=True, fit_drift=True, fit_ring=True)),
+    ("hmode-pair-wide", WIDE_H, dict(hmode=True, fit_drift=True)),
 ]
 
 
