@@ -926,6 +926,7 @@ struct StepPlan {
     int n_slices;
     // per projector / adjoint variant groups (batch may mix variants)
     struct Launch { int variant; const Item* items; int n; size_t lds; int maps; };
+    void* gather = nullptr;    // batches: device array the slices' states are gathered into
     std::vector<Launch> proj, adj;
     const Item* it_tr; int n_tr;
     const Item* it_ic; int n_ic;
@@ -1189,11 +1190,19 @@ int drive_on(const StepPlan& sp, const std::vector<SolverState*>& states, int ma
             }
         }
         if (rc) break;
-        for (size_t q = 0; q < states.size(); ++q) {
-            // k, evals, trials, mode, status are consecutive int32 fields
-            hipError_t e = hipMemcpyAsync(&host[5 * q], &states[q]->k, 5 * sizeof(int32_t),
-                                          hipMemcpyDeviceToHost, st);
+        if (sp.gather && states.size() > 1) {      // one copy for the whole batch
+            hipError_t e = launch_gather_status(sp.L, (int)states.size(), (int32_t*)sp.gather, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(host.data(), sp.gather, host.size() * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, st);
             if (e != hipSuccess) { rc = fail(EIT_ERR_DEVICE, "state read-back: %s", hipGetErrorString(e)); break; }
+        } else {
+            for (size_t q = 0; q < states.size(); ++q) {
+                // k, evals, trials, mode, status are consecutive int32 fields
+                hipError_t e = hipMemcpyAsync(&host[5 * q], &states[q]->k, 5 * sizeof(int32_t),
+                                              hipMemcpyDeviceToHost, st);
+                if (e != hipSuccess) { rc = fail(EIT_ERR_DEVICE, "state read-back: %s", hipGetErrorString(e)); break; }
+            }
         }
         if (rc) break;
         hipError_t e = hipStreamSynchronize(st);
@@ -1395,7 +1404,7 @@ extern "C" int eit_variant_info(int32_t kind, int32_t v, int32_t* a, int32_t* b,
 namespace {
 
 struct BatchLayout {
-    size_t descs = 0, lbdescs = 0, items = 0, end = 0;
+    size_t descs = 0, lbdescs = 0, items = 0, gather = 0, end = 0;
     std::vector<size_t> slice;        // per-slice solve layout base
     std::vector<int> order;           // slices by decreasing work
     std::vector<int> splits;          // adjoint split per slice
@@ -1485,6 +1494,7 @@ int batch_layout(int32_t n, const eit_plan* const* plans, int32_t m, BatchLayout
     B.descs = L.take(sizeof(SliceDesc) * n);
     B.lbdescs = L.take(sizeof(LbDesc) * n);
     B.items = L.take(sizeof(Item) * H.size());
+    B.gather = L.take(sizeof(SolverState) * n);    // state read-back staging
     B.slice.resize(n);
     for (int i = 0; i < n; ++i) {
         const size_t base = L.off;
@@ -1543,6 +1553,7 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
 
     StepPlan sp;
     sp.D = dd; sp.L = ld; sp.n_slices = n;
+    sp.gather = at(ws, B.gather);
     for (auto& r : B.r_proj)
         sp.proj.push_back({std::get<0>(r), it + std::get<1>(r), std::get<2>(r), std::get<3>(r), std::get<4>(r)});
     for (auto& r : B.r_adj)
@@ -1566,8 +1577,9 @@ extern "C" int eit_reconstruct_batch(int32_t n, const eit_plan* const* plans,
         return rc;
     HIP_TRY(launch_lb_scale(ld, it_vec, n_vec, grid_for(n_vec, kGridCap), 0, st));
     std::vector<SolverState> hs(n);
-    for (int i = 0; i < n; ++i)
-        HIP_TRY(hipMemcpyAsync(&hs[i], states[i], sizeof(SolverState), hipMemcpyDeviceToHost, st));
+    SolverState* gathered = (SolverState*)at(ws, B.gather);
+    HIP_TRY(launch_gather_states(ld, n, gathered, st));
+    HIP_TRY(hipMemcpyAsync(hs.data(), gathered, sizeof(SolverState) * n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     int worst = EIT_OK;
     for (int i = 0; i < n; ++i) {

@@ -165,6 +165,9 @@ hipError_t launch_lb_update(const LbDesc* L, const Item* items, int n_items, int
                             hipStream_t s);
 hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s);
 hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s);
+// batch read-back: 5 status ints per slice into out[5 n], or whole states into out[n]
+hipError_t launch_gather_status(const LbDesc* L, int n_slices, int32_t* out, hipStream_t s);
+hipError_t launch_gather_states(const LbDesc* L, int n_slices, SolverState* out, hipStream_t s);
 hipError_t launch_lb_direction_vec(const LbDesc* L, const SliceDesc* D, const Item* items,
                                    int n_items, int grid, hipStream_t s);
 

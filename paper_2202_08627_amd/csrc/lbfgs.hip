@@ -471,8 +471,35 @@ __global__ __launch_bounds__(kFinThreads) void k_lb_finalize(const LbDesc* __res
     finalize_body(l);
 }
 
+// Read-back helpers for batches: the host reads every slice's state in one copy from a
+// contiguous array instead of one copy per slice. k_gather_status: (k, evals, trials, mode,
+// status) -- consecutive int32 fields of SolverState -- of slice i into out[5 i ..]; one
+// thread per slice. k_gather_states: the whole state of slice blockIdx.x into out[blockIdx.x].
+__global__ void k_gather_status(const LbDesc* __restrict__ L, int n, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t* src = &L[i].st->k;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[5 * i + q] = src[q];
+}
+__global__ void k_gather_states(const LbDesc* __restrict__ L, SolverState* __restrict__ out) {
+    const int* src = (const int*)L[blockIdx.x].st;
+    int* dst = (int*)(out + blockIdx.x);
+    for (int q = threadIdx.x; q < (int)(sizeof(SolverState) / 4); q += blockDim.x) dst[q] = src[q];
+}
+
 hipError_t launch_lb_decide(const SliceDesc* D, const LbDesc* L, int n_slices, hipStream_t s) {
     k_lb_decide<<<n_slices, kIcThreads, 0, s>>>(D, L);
+    return hipGetLastError();
+}
+hipError_t launch_gather_status(const LbDesc* L, int n_slices, int32_t* out, hipStream_t s) {
+    if (n_slices <= 0) return hipSuccess;
+    k_gather_status<<<(n_slices + 255) / 256, 256, 0, s>>>(L, n_slices, out);
+    return hipGetLastError();
+}
+hipError_t launch_gather_states(const LbDesc* L, int n_slices, SolverState* out, hipStream_t s) {
+    if (n_slices <= 0) return hipSuccess;
+    k_gather_states<<<n_slices, 256, 0, s>>>(L, out);
     return hipGetLastError();
 }
 hipError_t launch_lb_finalize(const LbDesc* L, int n_slices, hipStream_t s) {

@@ -29,11 +29,11 @@ def _both(plan, x, s, lam_mu, lam_de):
     lib = L.lib()
     ws = plan.workspace(L.EIT_OP_COST_GRAD)
     c_ws = torch.empty((), dtype=torch.float64, device="cuda:0")
-    g_ws = torch.empty(plan.x_shape, dtype=torch.float32, device="cuda:0")
+    g_ws = torch.empty(plan.param_shape, dtype=torch.float32, device="cuda:0")
     L.check(lib.eit_cost_and_grad(plan.handle, _ptr(x), _ptr(s), lam_mu, lam_de, _ptr(c_ws),
                                   _ptr(g_ws), _ptr(ws), ws.numel(), _stream()))
     c_na = torch.empty((), dtype=torch.float64, device="cuda:0")
-    g_na = torch.full(plan.x_shape, float("nan"), dtype=torch.float32, device="cuda:0")
+    g_na = torch.full(plan.param_shape, float("nan"), dtype=torch.float32, device="cuda:0")
     L.check(lib.eit_cost_and_grad_noalloc(plan.handle, _ptr(x), _ptr(s), lam_mu, lam_de,
                                           _ptr(c_na), _ptr(g_na), _stream()))
     torch.cuda.synchronize()
@@ -66,6 +66,27 @@ def test_noalloc_matches_workspace_entry_two_calls_shrinking():
                                               small.lam_delta, _ptr(c), None, _stream()))
     torch.cuda.synchronize()
     assert float(c) == c_ws
+
+
+def test_noalloc_model_plan_matches_workspace_entry():
+    """The full model of eq. 4 at the paper's acquisition (h-mode, single-map kernels, drift
+    fitted, measured flat table): the parameter vector's gradient, bit for bit."""
+    torch.cuda.set_device(0)
+    from paper_2202_08627_amd import experiment
+    cfg = configs.PAPER_220
+    cases, _ = synth.make_stack(cfg, 8)
+    c = cases[4]
+    plan = experiment.model_plan(c, fit_drift=True, fit_ring=False)
+    rng = np.random.default_rng(3)
+    nn = cfg.n * cfg.n
+    p = np.concatenate([0.9 * c.mu_true.ravel(), 0.01 * rng.standard_normal(cfg.n_theta)])
+    assert p.size == plan.n_params
+    x, s = dev(p), dev(c.s_exp)
+    c_ws, g_ws, c_na, g_na = _both(plan, x, s, cfg.lam_mu, 0.0)
+    print(f"noalloc model plan: cost {c_ws:.6e}, |g| {np.linalg.norm(g_ws):.3e}", flush=True)
+    assert np.isfinite(c_ws) and c_ws > 0 and np.all(np.isfinite(g_ws[:nn]))
+    assert c_na == c_ws
+    assert np.array_equal(g_na, g_ws)
 
 
 def test_noalloc_rejects_problems_over_the_limit():
