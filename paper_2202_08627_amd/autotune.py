@@ -9,7 +9,12 @@ partial sums are added by the update pass instead of a separate one, and the cho
 fastest per evaluation there. `tiling_for(geo)` returns the cached (projector variant,
 adjoint variant, adjoint split), or (-1, -1, 0) = library defaults.
 
-    python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json] [--angle-span 2]
+With --hmode the optimiser step is that of the paper's acquisition at this size (h-mode,
+single-map kernels, one mask position, drift fitted, measured flat table), every split of
+the fastest adjoint variants is a step candidate, and the entry records the mode: a size
+class whose slices are h-mode (the paper-shaped 220 x 400 x 220) is tuned that way.
+
+    python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json] [--angle-span 2] [--hmode]
 """
 from __future__ import annotations
 
@@ -96,7 +101,15 @@ def pick_adjoint(step: dict, kernel: dict, tie: float = STEP_TIE):
     return min(close, key=lambda k: kernel[k])
 
 
-def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
+def _hmode_case(geo):
+    """The paper's acquisition (configs.PAPER_220's settings) at this geometry's size."""
+    from . import configs
+    cfg = dataclasses.replace(configs.PAPER_220, n=geo.n, n_theta=geo.n_theta, n_det=geo.n_det,
+                              mu_scale=configs.PAPER_220.mu_scale * configs.PAPER_220.n / geo.n)
+    return cfg, synth.make_case(cfg, seed=12345)
+
+
+def tune(geo, reps: int = 20, verbose: bool = True, hmode: bool = False) -> dict:
     """Times every applicable variant; returns the record stored in the cache."""
     import torch
     rng = np.random.default_rng(0)
@@ -134,18 +147,28 @@ def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
                 print(f"  backproject variant {v} {shape} split {g}: {ms * 1e3:.1f} us", flush=True)
             plan.close()
     pv = min(res["proj"], key=res["proj"].get)
-    # optimiser-step timing of the best adjoint candidates on a simulated random-ellipse slice
-    # of this size (a run that keeps iterating; flat data would stop within a few steps)
-    from . import warmstart
-    cfg = warmstart.slice_config(geo.n, geo.n_theta, geo.n_mask)
-    cfg = dataclasses.replace(cfg, n_det=geo.n_det)
-    case = synth.make_case(cfg, seed=12345)
+    # optimiser-step timing of the best adjoint candidates on a simulated slice of this size
+    # (a run that keeps iterating; flat data would stop within a few steps): random ellipses
+    # with the plain model, or the paper's acquisition with the h-mode model
+    model = None
+    if hmode:
+        cfg, case = _hmode_case(geo)
+        model = ops.Model.from_case(case, fit_drift=True, fit_ring=False)
+        kw = dict(lam=cfg.lam, mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale)
+        top = sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]
+        cands = sorted({(v, g) for v, _ in top for g in SPLITS if _fits(geo, pv, v, g)})
+    else:
+        from . import warmstart
+        cfg = warmstart.slice_config(geo.n, geo.n_theta, geo.n_mask)
+        cfg = dataclasses.replace(cfg, n_det=geo.n_det)
+        case = synth.make_case(cfg, seed=12345)
+        kw = dict(lam=cfg.lam, mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale)
+        cands = sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]
     sgeo = ops.Geometry.from_case(case)
     s_exp = torch.as_tensor(case.s_exp, device="cuda")
-    kw = dict(lam=cfg.lam, mu_scale=cfg.mu_scale, delta_scale=cfg.delta_scale)
     step = {}
-    for key in sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]:
-        plan = ops.Plan(sgeo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1])
+    for key in cands:
+        plan = ops.Plan(sgeo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1], model=model)
         ws = plan.workspace(L.EIT_OP_RECONSTRUCT, 10)
         plan.reconstruct(s_exp, iters=2, ws=ws, **kw)
         best = float("inf")
@@ -163,15 +186,22 @@ def tune(geo, reps: int = 20, verbose: bool = True) -> dict:
             print(f"  optimiser step with adjoint {key[0]} split {key[1]}: {best * 1e3:.1f} us"
                   " per evaluation", flush=True)
         plan.close()
-    av, ag = pick_adjoint(step, res["adj"])
-    return {"proj_variant": pv, "adj_variant": av, "adj_splits": ag,
-            "proj_us": {str(k): round(v * 1e3, 2) for k, v in res["proj"].items()},
-            "adj_us": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in res["adj"].items()},
-            "step_us_per_eval": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in step.items()}}
+    if hmode:       # the two-map kernel times say nothing about the single-map adjoint
+        av, ag = min(step, key=step.get)
+    else:
+        av, ag = pick_adjoint(step, res["adj"])
+    rec = {"proj_variant": pv, "adj_variant": av, "adj_splits": ag,
+           "proj_us": {str(k): round(v * 1e3, 2) for k, v in res["proj"].items()},
+           "adj_us": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in res["adj"].items()},
+           "step_us_per_eval": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in step.items()}}
+    if hmode:
+        rec["step_model"] = "h-mode (paper's acquisition, drift fitted, measured flat table)"
+    return rec
 
 
-def tune_and_store(geo, path: str = DEFAULT_CACHE, reps: int = 20, verbose: bool = True) -> dict:
-    rec = tune(geo, reps, verbose)
+def tune_and_store(geo, path: str = DEFAULT_CACHE, reps: int = 20, verbose: bool = True,
+                   hmode: bool = False) -> dict:
+    rec = tune(geo, reps, verbose, hmode)
     cache = load_cache(path)
     cache[size_key(geo)] = rec
     with open(path, "w") as f:
@@ -194,11 +224,13 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--angle-span", type=float, default=1.0,
                     help="angles a * span * pi / n_theta (2 for 360 degrees)")
+    ap.add_argument("--hmode", action="store_true",
+                    help="time the adjoint candidates in the h-mode optimiser step")
     a = ap.parse_args()
     for n, nt in zip(a.n, a.n_theta):
         geo = geometry_for(n, nt, angle_span=a.angle_span)
-        print(f"tuning {size_key(geo)}", flush=True)
-        rec = tune_and_store(geo, a.cache, a.reps)
+        print(f"tuning {size_key(geo)}" + (" (h-mode step)" if a.hmode else ""), flush=True)
+        rec = tune_and_store(geo, a.cache, a.reps, hmode=a.hmode)
         print(json.dumps(rec), flush=True)
 
 
