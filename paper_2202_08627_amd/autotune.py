@@ -10,9 +10,10 @@ fastest per evaluation there. `tiling_for(geo)` returns the cached (projector va
 adjoint variant, adjoint split), or (-1, -1, 0) = library defaults.
 
 With --hmode the optimiser step is that of the paper's acquisition at this size (h-mode,
-single-map kernels, one mask position, drift fitted, measured flat table), every split of
-the fastest adjoint variants is a step candidate, and the entry records the mode: a size
-class whose slices are h-mode (the paper-shaped 220 x 400 x 220) is tuned that way.
+single-map kernels, one mask position, drift fitted, measured flat table): every split of
+the fastest adjoint variants is a step candidate, then the fastest projector variants are
+timed in the step with the chosen adjoint, and the entry records the mode. A size class
+whose slices are h-mode (the paper-shaped 220 x 400 x 220) is tuned that way.
 
     python -m paper_2202_08627_amd.autotune --n 512 --n-theta 720 [--cache tiles.json] [--angle-span 2] [--hmode]
 """
@@ -31,6 +32,7 @@ from . import ops, synth
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
 SPLITS = (1, 2, 4, 8)
 SOLVER_CANDIDATES = 4
+PROJ_STEP_CANDIDATES = 6      # h-mode: projector variants timed in the step
 SOLVER_ITERS = 40
 SOLVER_REPS = 3
 STEP_TIE = 0.01
@@ -166,9 +168,8 @@ def tune(geo, reps: int = 20, verbose: bool = True, hmode: bool = False) -> dict
         cands = sorted(res["adj"], key=res["adj"].get)[:SOLVER_CANDIDATES]
     sgeo = ops.Geometry.from_case(case)
     s_exp = torch.as_tensor(case.s_exp, device="cuda")
-    step = {}
-    for key in cands:
-        plan = ops.Plan(sgeo, proj_variant=pv, adj_variant=key[0], adj_splits=key[1], model=model)
+    def time_step(pv_, av_, ag_):
+        plan = ops.Plan(sgeo, proj_variant=pv_, adj_variant=av_, adj_splits=ag_, model=model)
         ws = plan.workspace(L.EIT_OP_RECONSTRUCT, 10)
         plan.reconstruct(s_exp, iters=2, ws=ws, **kw)
         best = float("inf")
@@ -181,13 +182,24 @@ def tune(geo, reps: int = 20, verbose: bool = True, hmode: bool = False) -> dict
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1) / max(rep["evals"], 1))
-        step[key] = best
-        if verbose:
-            print(f"  optimiser step with adjoint {key[0]} split {key[1]}: {best * 1e3:.1f} us"
-                  " per evaluation", flush=True)
         plan.close()
-    if hmode:       # the two-map kernel times say nothing about the single-map adjoint
+        return best
+
+    step = {}
+    for key in cands:
+        step[key] = time_step(pv, *key)
+        if verbose:
+            print(f"  optimiser step with adjoint {key[0]} split {key[1]}: {step[key] * 1e3:.1f} us"
+                  " per evaluation", flush=True)
+    pstep = {}
+    if hmode:       # the two-map kernel times say nothing about the single-map kernels
         av, ag = min(step, key=step.get)
+        for v in sorted(res["proj"], key=res["proj"].get)[:PROJ_STEP_CANDIDATES]:
+            pstep[v] = step[(av, ag)] if v == pv else time_step(v, av, ag)
+            if verbose:
+                print(f"  optimiser step with projector {v}: {pstep[v] * 1e3:.1f} us per evaluation",
+                      flush=True)
+        pv = min(pstep, key=pstep.get)
     else:
         av, ag = pick_adjoint(step, res["adj"])
     rec = {"proj_variant": pv, "adj_variant": av, "adj_splits": ag,
@@ -196,6 +208,7 @@ def tune(geo, reps: int = 20, verbose: bool = True, hmode: bool = False) -> dict
            "step_us_per_eval": {f"{k[0]}/{k[1]}": round(v * 1e3, 2) for k, v in step.items()}}
     if hmode:
         rec["step_model"] = "h-mode (paper's acquisition, drift fitted, measured flat table)"
+        rec["proj_step_us_per_eval"] = {str(k): round(v * 1e3, 2) for k, v in pstep.items()}
     return rec
 
 
