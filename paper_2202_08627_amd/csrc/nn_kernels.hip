@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "nn_internal.h"
 
@@ -348,36 +349,35 @@ hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipSt
 }
 
 // --------------------------------------------------------------------------- weight gradients
-// Partial weight gradients over pixel slabs, as GEMMs whose reduction runs over pixels:
+// Partial weight gradients over pixel slabs, as GEMMs whose reduction runs over pixels, stored
+// as part[z][co][tap][ci] for split z:
 //   3x3 conv:    m = co, n = tap * Ci + ci:   sum_p dZ[p][co] X[p + off(tap)][ci]
+//                (k_wgrad_tr below; part[z] also holds the Co bias partials sum_p dZ[p][co]
+//                after its Co * 9 * Ci weights, the parameter layout's order, so one split-K
+//                reduction yields both)
 //   2x2 up-conv: m = d * Co + co, n = ci:     sum_p G[b, 2y + d/2, 2x + d%2][co] X[p][ci]
-//                (p = (b, y, x) over the up-conv's input)
-// stored as part[z][co][tap][ci] (tap = d for the up-conv). For the 3x3 conv each split also
-// stores the bias-gradient partials sum_p dZ[p][co] after its weight block, part[z] being
-// Co * 9 * Ci + Co floats (the parameter layout's weights-then-bias order, so one split-K
-// reduction yields both): the blocks of the first n tile add up the dZ rows they stage.
-// Pixels are strided in NHWC, so
-// each 64-pixel step stages both operands transposed into LDS ([row][pixel], rows padded to
-// 72 elements): a thread loads 16 bytes (8 consecutive channels = 8 rows of one tap) for each
-// of a few consecutive pixels and writes them as 8 short row segments, and an MFMA fragment
-// (8 consecutive pixels of one row) is one 16-byte LDS read. Rows of a thread group and
-// pixel groups interleave so that each LDS write instruction covers every bank once. The
-// next step's operands are loaded into registers while the current step is multiplied.
+//                (p = (b, y, x) over the up-conv's input; tap = d; k_wgrad_up)
+// k_wgrad_up: pixels are strided in NHWC, so each 64-pixel step stages both operands
+// transposed into LDS ([row][pixel], rows padded to 72 elements): a thread loads 16 bytes
+// (8 consecutive channels = 8 rows of one sub-pixel) for each of a few consecutive pixels and
+// writes them as 8 short row segments, and an MFMA fragment (8 consecutive pixels of one row)
+// is one 16-byte LDS read. Rows of a thread group and pixel groups interleave so that each
+// LDS write instruction covers every bank once. The next step's operands are loaded into
+// registers while the current step is multiplied.
 // Block: TM x TN output tile (TM * TN = 64 * 64, 4 wavefronts of 32 x 32; TM = 32 when m
 // has at most 32 rows); grid (m tiles, n tiles, splits), split z covering pixels
 // [z kps, min(P, (z + 1) kps)), kps a multiple of 32. Channel counts are multiples of 8, so
-// an 8-row group never straddles a tap or a sub-pixel. Registers are held to five wavefronts
-// per SIMD (measured faster than four with the compiler's free choice).
+// an 8-row group never straddles a sub-pixel. Registers are held to five wavefronts per SIMD
+// (measured faster than four with the compiler's free choice).
 constexpr int kWgStep = 64;
 constexpr int kWgRow = kWgStep + 8;
-template <int UP, int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgrad(Tensor dz, Tensor x, float* __restrict__ part,
-                                               int P, int kps) {
+template <int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_wgrad_up(Tensor dz, Tensor x, float* __restrict__ part,
+                                                  int P, int kps) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     constexpr int TN = 64 * 64 / TM;
     constexpr int WM = TM / 32, WN = 4 / WM;       // wavefront grid
-    constexpr int NTAP = UP ? 4 : 9;
     // A staging: OA row groups x 16 pixel groups of AP = 4 pixels (threads past OA * 16 idle);
     // B staging: OB row groups x GB pixel groups of BP pixels (all 256 threads)
     constexpr int OA = TM / 8, GA = 16, AP = kWgStep / GA;
@@ -393,18 +393,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int m0 = bx * TM, n0 = by * TN;
     const int pb = bz * kps, pe = min(P, pb + kps);
     const int Co = dz.C, Ci = x.C;
-    const int M = UP ? 4 * Co : Co, N = UP ? Ci : 9 * Ci;
+    const int M = 4 * Co, N = Ci;
     const int H = x.H, W = x.W;                  // the pixel grid p runs over
     const int ga = tid % GA, oa = tid / GA;
     const bool a_act = oa < OA;
     const int gb = tid % GB, ob = tid / GB;
     const int m = m0 + 8 * oa;
     const bool m_ok = a_act && m < M;
-    const int d = UP && m_ok ? m / Co : 0, co = m_ok ? m - d * Co : 0;
+    const int d = m_ok ? m / Co : 0, co = m_ok ? m - d * Co : 0;
     const int n = n0 + 8 * ob;
     const bool n_ok = n < N;
-    const int tap = !UP && n_ok ? n / Ci : 4, ci = n_ok ? n - (UP ? 0 : tap * Ci) : 0;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;  // zero shift for the up-conv (tap 4)
+    const int ci = n_ok ? n : 0;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -414,39 +413,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int a_bytes = (int)((size_t)dz.B * dz.H * dz.W * dz.cs * sizeof(bf16));
     const int b_bytes = (int)((size_t)x.B * x.H * x.W * x.cs * sizeof(bf16));
     auto load = [&](int k0) {
-        if (a_act) {   // A: dZ at the pixel (conv), G at the row group's sub-pixel d (up-conv)
+        if (a_act) {   // A: G at the row group's sub-pixel d
             int p = k0 + AP * ga;
             int yb = p / W, xx = p - yb * W;     // one division per step, then carries
             int b = yb / H, yy = yb - b * H;
 #pragma unroll
             for (int q = 0; q < AP; ++q) {
-                const int o = UP ? ((b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs
-                                 : p * dz.cs;
+                const int o = ((b * 2 * H + 2 * yy + (d >> 1)) * (2 * W) + 2 * xx + (d & 1)) * dz.cs;
                 av[q] = bld8(dz.p, a_bytes, p < pe && m_ok ? 2 * (o + dz.coff + co) : kOOB);
                 ++p;
                 if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
             }
         }
-        {   // B: X at the pixel shifted by the row group's tap (conv) or at the pixel (up-conv)
-            int p = k0 + BP * gb;
-            int yb = p / W, xx = p - yb * W;
-            int b = yb / H, yy = yb - b * H;
 #pragma unroll
-            for (int q = 0; q < BP; ++q) {
-                const int sy = yy + dy, sx = xx + dx;
-                const bool ok = p < pe && n_ok && (unsigned)sy < (unsigned)H && (unsigned)sx < (unsigned)W;
-                bv[q] = bld8(x.p, b_bytes, ok ? 2 * (((b * H + sy) * W + sx) * x.cs + x.coff + ci) : kOOB);
-                ++p;
-                if (++xx == W) { xx = 0; if (++yy == H) { yy = 0; ++b; } }
-            }
+        for (int q = 0; q < BP; ++q) {           // B: X at the pixel
+            const int p = k0 + BP * gb + q;
+            bv[q] = bld8(x.p, b_bytes, p < pe && n_ok ? 2 * (p * x.cs + x.coff + ci) : kOOB);
         }
     };
-    // bias partials (3x3 conv, first n tile): thread t adds 8 pixels of rows t / 8 + 32 r
-    constexpr int BR = TM / 32;
-    const bool bias_blk = !UP && by == 0;
-    float bsum[BR];
-#pragma unroll
-    for (int r = 0; r < BR; ++r) bsum[r] = 0.f;
     load(pb);
     for (int k0 = pb; k0 < pe; k0 += kWgStep) {
         __syncthreads();                       // previous step's fragments consumed
@@ -466,14 +450,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
         __syncthreads();
         if (k0 + kWgStep < pe) load(k0 + kWgStep);
-        if (bias_blk) {
-#pragma unroll
-            for (int r = 0; r < BR; ++r) {
-                const bf16x8 v = *(const bf16x8*)(As + ((tid >> 3) + 32 * r) * kWgRow + 8 * (tid & 7));
-#pragma unroll
-                for (int u = 0; u < 8; ++u) bsum[r] += (float)v[u];
-            }
-        }
 #pragma unroll
         for (int kk = 0; kk < kWgStep; kk += 32) {
             bf16x8 a[2], bb[2];
@@ -489,18 +465,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
         }
     }
-    float* dst = part + (size_t)bz * (Co * NTAP * Ci + (UP ? 0 : Co));
-    if (bias_blk) {
-#pragma unroll
-        for (int r = 0; r < BR; ++r) {
-            float v = bsum[r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            const int o = m0 + (tid >> 3) + 32 * r;
-            if ((tid & 7) == 0 && o < M) dst[(size_t)M * N + o] = v;
-        }
-    }
+    float* dst = part + (size_t)bz * (Co * 4 * Ci);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -510,40 +475,258 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const int o = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
                 const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (o < M && nn < N) {
-                    if (UP) {
-                        const int dd = o / Co, cc = o - dd * Co;
-                        dst[((size_t)cc * 4 + dd) * Ci + nn] = acc[i][j][r];
-                    } else {
-                        dst[(size_t)o * N + nn] = acc[i][j][r];
-                    }
+                    const int dd = o / Co, cc = o - dd * Co;
+                    dst[((size_t)cc * 4 + dd) * Ci + nn] = acc[i][j][r];
                 }
             }
 }
 
-template <int UP>
-hipError_t wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, hipStream_t s) {
+// --------------------------------------------------------------------------- weight gradients, 3x3
+// The 3x3 convolution's weight gradient without register staging: both operands go from
+// memory to LDS by direct buffer loads (buffer_load ... lds: lane i of a wavefront writes
+// its 16 bytes at the wavefront's LDS base + 16 i), kept in their memory layout (rows of
+// pixels, 8 channels per 16-byte slot), and the MFMA fragments, which need 8 consecutive
+// pixels of one channel per lane, are read with the transposing LDS load ds_read_b64_tr_b16:
+// in each 16-lane group, lane 4r + c supplies the address of 4 consecutive channels
+// (4c .. 4c + 3) of pixel row r, and lane 4c + e receives channel 4c + e of the 4 rows. Two
+// such reads (pixel rows 8g .. 8g + 3 and 8g + 4 .. 8g + 7 for lane group g) give a lane the
+// same 8 pixels of one channel that the MFMA's k layout asks for, so the products are those
+// of the register-staged kernel. No VALU work transposes data and no registers hold the next
+// step's operands, so NS stages of 64 pixels are in flight: the loads of stage s + NS - 1
+// are issued while stage s is multiplied. The stage ring is counted with explicit vmcnt
+// waits (the loads are written in inline asm, which the compiler does not track): every
+// wavefront issues the same number of loads per stage (past the slab's end they read zeros),
+// so "stage s landed" is "at most (NS - 2) stages' loads outstanding", and a barrier then
+// makes every wavefront's part visible.
+// Slot layout of an operand with C chunks (16-byte groups) per pixel row: pixel p, chunk q
+// at slot C p + (q ^ swz(p)); the XOR spreads the 8 rows that one 32-lane half of a
+// transposing read touches (rows 8g + 4h + r, r < 4, two values of g) over distinct 32-byte
+// bank windows. Bias gradients (first n tile) are products with a fragment of ones in the
+// wavefronts of the first n column: sum_p dZ[p][co] in the MFMA's FP32 accumulation.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+typedef __attribute__((address_space(3))) bf16 lds_bf16;
+
+__device__ __forceinline__ i32x4 rsrc_words(const void* base, int bytes) {
+    const unsigned long long a = (unsigned long long)base;
+    return i32x4{(int)(unsigned)a, (int)((unsigned)(a >> 32) & 0xffffu), bytes, 0x00020000};
+}
+// 16 bytes per lane from byte offset voff of the resource (>= extent: zeros) into LDS at
+// lds_base + 16 * lane; lds_base is uniform across the wavefront.
+__device__ __forceinline__ void dma16(i32x4 rs, unsigned lds_base, int voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :: "s"(lds_base), "v"(voff), "s"(rs) : "memory", "m0");
+}
+// Wait until at most N vector-memory operations of this wavefront are outstanding (the
+// expcnt and lgkmcnt fields of the s_waitcnt immediate left at their maximum).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+template <int C>
+__device__ __forceinline__ int wg_swz(int p) {
+    static_assert(C == 4 || C == 8 || C == 16, "chunks per pixel row");
+    if constexpr (C == 4) return ((p >> 3) & 1) << 1;
+    else if constexpr (C == 8) return (((p >> 1) & 1) << 1) | (((p >> 3) & 1) << 2);
+    else return ((p & 3) << 1) | (((p >> 3) & 1) << 3);
+}
+
+constexpr int kWtStep = 64;   // pixels per stage
+template <int TM, int NS>
+__global__ __launch_bounds__(256) void k_wgrad_tr(Tensor dz, Tensor x, float* __restrict__ part,
+                                                  int P, int kps) {
+    constexpr int TN = 64 * 64 / TM;
+    constexpr int WM = TM / 32, WN = 4 / WM;
+    constexpr int CA = TM / 8, CB = TN / 8;           // 16-byte chunks per pixel row
+    constexpr int SA = kWtStep * CA, SB = kWtStep * CB;   // slots per stage
+    constexpr int DA = SA / 256, DB = SB / 256;       // loads per wavefront per stage
+    constexpr int D = DA + DB;
+    static_assert(NS >= 2 && DA >= 1 && DB >= 1, "stage shape");
+    __shared__ __attribute__((aligned(16))) bf16 lds[NS * (SA + SB) * 8];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: LDS bases go to m0
+    const int wm = wv / WN, wn = wv % WN;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = tile_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bz = t / (gx * gy), bx = t % gx, by = (t / gx) % gy;
+    const int m0 = bx * TM, n0 = by * TN;
+    const int pb = bz * kps, pe = min(P, pb + kps);
+    const int Co = dz.C, Ci = x.C, M = Co, N = 9 * Ci;
+    const int H = x.H, W = x.W;
+    const i32x4 rsA = rsrc_words(dz.p, (int)((size_t)dz.B * dz.H * dz.W * dz.cs * sizeof(bf16)));
+    const i32x4 rsB = rsrc_words(x.p, (int)((size_t)x.B * x.H * x.W * x.cs * sizeof(bf16)));
+    const unsigned lds0 = (unsigned)(size_t)(lds_bf16*)lds;
+
+    // this lane's slots: pixel row and chunk of A load j and of B load j (fixed per stage)
+    int pA[DA];
+    unsigned offA[DA];      // byte offsets, modulo 2^32 (used only where the access is valid)
+    bool okA[DA];
+#pragma unroll
+    for (int j = 0; j < DA; ++j) {
+        const int sl = 64 * (wv * DA + j) + lane, p = sl / CA, q = (sl % CA) ^ wg_swz<CA>(p);
+        pA[j] = p;
+        okA[j] = m0 + 8 * q < M;
+        offA[j] = 2u * (unsigned)((pb + p) * dz.cs + dz.coff + m0 + 8 * q);
+    }
+    int pB[DB], dyB[DB], dxB[DB], yyB[DB], xxB[DB];
+    unsigned offB[DB];
+    bool okB[DB];
+#pragma unroll
+    for (int j = 0; j < DB; ++j) {
+        const int sl = 64 * (wv * DB + j) + lane, p = sl / CB, q = (sl % CB) ^ wg_swz<CB>(p);
+        const int n = n0 + 8 * q;
+        okB[j] = n < N;
+        const int tap = okB[j] ? n / Ci : 4, ci = okB[j] ? n - tap * Ci : 0;
+        dyB[j] = tap / 3 - 1;
+        dxB[j] = tap % 3 - 1;
+        pB[j] = p;
+        const int P0 = pb + p;
+        xxB[j] = P0 % W;
+        yyB[j] = (P0 / W) % H;
+        offB[j] = 2u * (unsigned)((P0 + dyB[j] * W + dxB[j]) * x.cs + x.coff + ci);
+    }
+    const unsigned stepA = 2u * kWtStep * dz.cs, stepB = 2u * kWtStep * x.cs;
+    // loads of stage index st (pixels pb + 64 st ..) into ring buffer st % NS
+    auto issue = [&](int st, int buf) {
+        const int k0 = pb + kWtStep * st;
+        const unsigned baseA = lds0 + (unsigned)(buf * (SA + SB)) * 16u;
+        const unsigned baseB = baseA + SA * 16u;
+#pragma unroll
+        for (int j = 0; j < DA; ++j) {
+            const bool ok = okA[j] && k0 + pA[j] < pe;
+            dma16(rsA, baseA + (unsigned)(wv * DA + j) * 1024u, ok ? (int)offA[j] : kOOB);
+            offA[j] += stepA;
+        }
+#pragma unroll
+        for (int j = 0; j < DB; ++j) {
+            const bool ok = okB[j] && k0 + pB[j] < pe && (unsigned)(yyB[j] + dyB[j]) < (unsigned)H &&
+                            (unsigned)(xxB[j] + dxB[j]) < (unsigned)W;
+            dma16(rsB, baseB + (unsigned)(wv * DB + j) * 1024u, ok ? (int)offB[j] : kOOB);
+            offB[j] += stepB;
+            xxB[j] += kWtStep;
+            while (xxB[j] >= W) {
+                xxB[j] -= W;
+                if (++yyB[j] == H) yyB[j] = 0;
+            }
+        }
+    };
+
+    // fragment addresses (bytes from the operand's stage base): lane group g, row r, column
+    // group c of a transposing read at pixel rows 8g + 4h + r (+ kk)
+    const int g = lane >> 4, r = (lane >> 2) & 3, c = lane & 3;
+    const int prow = 8 * g + r;
+    unsigned fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int qa = (wm * 32 + i * 16) / 8, qb = (wn * 32 + i * 16) / 8;
+        fa[i] = (unsigned)((CA * prow + ((qa ^ wg_swz<CA>(prow)) + (c >> 1))) * 16 + 8 * (c & 1));
+        fb[i] = (unsigned)(SA * 16 + (CB * prow + ((qb ^ wg_swz<CB>(prow)) + (c >> 1))) * 16 + 8 * (c & 1));
+    }
+    const bool bias_w = by == 0 && wn == 0;
+    f32x4 acc[2][2], accb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int nsteps = (pe - pb + kWtStep - 1) / kWtStep;
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st) issue(st, st);
+    // the step loop, instantiated with and without the bias products (a wavefront-uniform
+    // choice; one loop with a branch inside costs accumulator copies every step)
+    auto run = [&](auto bias_tag) {
+        constexpr bool BIAS = decltype(bias_tag)::value;
+        bf16x8 ones;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ones[u] = (__bf16)1.0f;
+        int cur = 0, nxt = NS - 1;
+        for (int s = 0; s < nsteps; ++s) {
+            wait_vm<(NS - 2) * D>();               // this wavefront's loads of stage s landed
+            __syncthreads();                       // everyone's landed; stage s - 1 consumed
+            issue(s + NS - 1, nxt);
+            const char __attribute__((address_space(3)))* st0 =
+                (const char __attribute__((address_space(3)))*)(lds_bf16*)lds + cur * (SA + SB) * 16;
+            auto tr = [&](unsigned off) {
+                return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(st0 + off));
+            };
+#pragma unroll
+            for (int kk = 0; kk < kWtStep; kk += 32) {
+                bf16x8 a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const s16x4 a0 = tr(fa[i] + CA * 16 * kk), a1 = tr(fa[i] + CA * 16 * (kk + 4));
+                    const s16x4 b0 = tr(fb[i] + CB * 16 * kk), b1 = tr(fb[i] + CB * 16 * (kk + 4));
+                    a[i] = __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
+                    b[i] = __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                if constexpr (BIAS) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ones, accb[i], 0, 0, 0);
+                }
+            }
+            cur = cur + 1 == NS ? 0 : cur + 1;
+            nxt = nxt + 1 == NS ? 0 : nxt + 1;
+        }
+    };
+    if (bias_w) run(std::true_type{});
+    else run(std::false_type{});
+    wait_vm<0>();                              // no load may still write this block's LDS
+    float* dst = part + (size_t)bz * (Co * 9 * Ci + Co);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+            const int o = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r4;
+            if (bias_w && (lane & 15) == 0 && o < M) dst[(size_t)M * N + o] = accb[i][r4];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (o < M && nn < N) dst[(size_t)o * N + nn] = acc[i][j][r4];
+            }
+        }
+}
+
+constexpr int kWtStages = 2;
+hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
+                      hipStream_t s) {
+    if (ksize != 3) return hipErrorInvalidValue;
     const int P = x.B * x.H * x.W;
     const int kps = wgrad_slab(P, splits);
     const int sp = wgrad_splits_used(P, splits);
-    const int M = UP ? 4 * dz.C : dz.C, N = UP ? x.C : 9 * x.C;
+    const int M = dz.C, N = 9 * x.C;
     if (M <= 32) {
         dim3 g(1, (N + 127) / 128, sp);
-        k_wgrad<UP, 32><<<g, 256, 0, s>>>(dz, x, part, P, kps);
+        k_wgrad_tr<32, kWtStages><<<g, 256, 0, s>>>(dz, x, part, P, kps);
     } else {
         dim3 g((M + 63) / 64, (N + 63) / 64, sp);
-        k_wgrad<UP, 64><<<g, 256, 0, s>>>(dz, x, part, P, kps);
+        k_wgrad_tr<64, kWtStages><<<g, 256, 0, s>>>(dz, x, part, P, kps);
     }
     return hipGetLastError();
 }
 
-hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
-                      hipStream_t s) {
-    if (ksize != 3) return hipErrorInvalidValue;
-    return wgrad<0>(x, dz, part, splits, s);
-}
-
 hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s) {
-    return wgrad<1>(x, g, part, splits, s);
+    const int P = x.B * x.H * x.W;
+    const int kps = wgrad_slab(P, splits);
+    const int sp = wgrad_splits_used(P, splits);
+    const int M = 4 * g.C, N = x.C;
+    if (M <= 32) {
+        dim3 gr(1, (N + 127) / 128, sp);
+        k_wgrad_up<32><<<gr, 256, 0, s>>>(g, x, part, P, kps);
+    } else {
+        dim3 gr((M + 63) / 64, (N + 63) / 64, sp);
+        k_wgrad_up<64><<<gr, 256, 0, s>>>(g, x, part, P, kps);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace nn
