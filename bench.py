@@ -71,8 +71,8 @@ WEIGHTS = os.path.join(ROOT, "paper_2202_08627_amd", "weights", "unet_b32_256.np
 # each scaled by the counts of a plain 256 MiB copy; valid only for the kernel source with
 # this SHA-256 (first 16 hex digits). Filled from the committed traffic summary.
 TRAFFIC = {
-    "project": {"src": "cb20e4f9f29ee8c2", "variant": 23, "bytes": 24.98e6},
-    "backproject": {"src": "cb20e4f9f29ee8c2", "variant": 12, "bytes": 22.93e6},
+    "project": {"src": "8bae7ef64b4443db", "variant": 23, "bytes": 24.98e6},
+    "backproject": {"src": "8bae7ef64b4443db", "variant": 12, "bytes": 22.92e6},
 }
 
 
