@@ -514,10 +514,11 @@ __device__ __forceinline__ i32x4 rsrc_words(const void* base, int bytes) {
     return i32x4{(int)(unsigned)a, (int)((unsigned)(a >> 32) & 0xffffu), bytes, 0x00020000};
 }
 // 16 bytes per lane from byte offset voff of the resource (>= extent: zeros) into LDS at
-// lds_base + 16 * lane; lds_base is uniform across the wavefront.
+// lds_base + 16 * lane; lds_base is uniform across the wavefront. The LDS base is an operand
+// bound to M0 (the "{m0}" constraint), so the compiler sets M0 itself and knows it is read.
 __device__ __forceinline__ void dma16(i32x4 rs, unsigned lds_base, int voff) {
-    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
-                 :: "s"(lds_base), "v"(voff), "s"(rs) : "memory", "m0");
+    asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds"
+                 :: "v"(voff), "s"(rs), "{m0}"(lds_base) : "memory");
 }
 // Wait until at most N vector-memory operations of this wavefront are outstanding (the
 // expcnt and lgkmcnt fields of the s_waitcnt immediate left at their maximum).
