@@ -39,6 +39,31 @@ __device__ __forceinline__ bf16x8 bld8(const bf16* base, int bytes, int off) {
     return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
+// Direct buffer-to-LDS loads (the halo-tile convolution and the 3x3 weight gradients).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+typedef __attribute__((address_space(3))) bf16 lds_bf16;
+
+__device__ __forceinline__ i32x4 rsrc_words(const void* base, int bytes) {
+    const unsigned long long a = (unsigned long long)base;
+    return i32x4{(int)(unsigned)a, (int)((unsigned)(a >> 32) & 0xffffu), bytes, 0x00020000};
+}
+// 16 bytes per lane from byte offset voff of the resource (>= extent: zeros) into LDS at
+// lds_base + 16 * lane; lds_base is uniform across the wavefront. The LDS base is an operand
+// bound to M0 (the "{m0}" constraint), so the compiler sets M0 itself and knows it is read.
+__device__ __forceinline__ void dma16(i32x4 rs, unsigned lds_base, int voff) {
+    asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds"
+                 :: "v"(voff), "s"(rs), "{m0}"(lds_base) : "memory");
+}
+// Wait until at most N vector-memory operations of this wavefront are outstanding (the
+// expcnt and lgkmcnt fields of the s_waitcnt immediate left at their maximum).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 // --------------------------------------------------------------------------- loaders
 // A loader is used in two stages: row(m, M) decodes row m once per output tile (pixel
 // coordinates and validity), load(ctx, k0, ok) returns the 8 consecutive k (k0 .. k0+7,
@@ -298,6 +323,166 @@ hipError_t gemm(LA la, LB lb, EP ep, int M, int N, int K, int splits, hipStream_
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------- 3x3 convolution, halo tiles
+// The implicit GEMM above fetches every input pixel once per tap (nine times per layer) and
+// every weight row once per 32-k step of every 128-pixel tile; at the 32- and 64-channel
+// layers that operand stream keeps the L2 channels 80-85 % busy and bounds the kernel. This
+// kernel computes a TR x TW pixel tile (TR * TW = 64 TM, TM 16-pixel fragments per wavefront,
+// 4 wavefronts) over BN output channels and runs the reduction as C / 32 channel chunks, each
+// staged once: the chunk's (TR + 2) x (TW + 2) input pixels (the tile and its one-pixel border,
+// zeros outside the image) and its BN x 9 x 32 weights, both by direct buffer-to-LDS loads;
+// the nine taps then read shifted A fragments from the staged tile. Per 32-channel chunk a
+// block reads (TR + 2)(TW + 2) input pixels instead of 9 TR TW, and its weights once.
+// LDS layouts (16-byte groups of 8 channels):
+//   tile:    pixel h = hr (TW + 2) + hc, group g at slot 4 h + (g ^ ((h >> 2) & 3)): the 16 lanes
+//            of one fragment read 16 consecutive h at one g and cover all 64 banks once;
+//   weights: row n (37 slots: tap t, group g at slot 4 t + g, one pad slot), so 16 consecutive
+//            rows at one slot fall on distinct banks (37 x 16 bytes = 148 words = 20 mod 64).
+// A direct load writes lane i's 16 bytes at the wavefront's base + 16 i, so each lane loads
+// the (pixel, group) or (row, tap, group) its slot holds; slots past the data read zeros.
+// flip = 1 is the data-gradient form (input pixel p - off(tap)). Sums run chunk by chunk,
+// taps in order inside a chunk, 32 k per MFMA.
+template <int TR, int TW, int BN>
+__global__ __launch_bounds__(256) void k_conv3(Tensor x, const bf16* __restrict__ w, int ldw, int N,
+                                               int flip, EpiAct ep) {
+    constexpr int BM = TR * TW, TM = BM / 64, TN = BN / 16;
+    static_assert(BM % 64 == 0 && TM >= 1 && BN % 16 == 0, "tile shape");
+    constexpr int HW = TW + 2, HP = (TR + 2) * HW;                 // staged pixels
+    constexpr int HS = (4 * HP + 63) / 64 * 64;                    // tile slots, whole wavefront loads
+    constexpr int WR = 37, WS = (BN * WR + 63) / 64 * 64;           // weight slots
+    constexpr int DH = HS / 64, DW = WS / 64;                       // wavefront loads per chunk
+    constexpr int LDR = BN + 8;
+    constexpr int OUT = BM * LDR / 8;
+    __shared__ bf16x8 smem[HS + WS > OUT ? HS + WS : OUT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int H = x.H, W = x.W, C = x.C;
+    const int tx = W / TW, ty = H / TR;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = tile_order(blockIdx.x + gx * blockIdx.y, gx * gy);
+    const int pt = t / gy, by = t % gy;                             // n tiles of a pixel tile adjacent
+    const int b = pt / (tx * ty), y0 = (pt / tx) % ty * TR, x0 = pt % tx * TW;
+    const int n0 = by * BN;
+    const i32x4 rsX = rsrc_words(x.p, (int)((size_t)x.B * H * W * x.cs * sizeof(bf16)));
+    const i32x4 rsW = rsrc_words(w, (int)((size_t)N * ldw * sizeof(bf16)));
+    const unsigned lds0 = (unsigned)(size_t)(lds_bf16*)(bf16*)smem;
+    const unsigned ldsW = lds0 + HS * 16u;
+    // tile loads: slot s = 64 (DH-slot wavefront load index) + lane -> staged pixel, group
+    // byte offsets of channel 0 of each load's group (-1: the slot reads zeros)
+    int offX[(DH + 3) / 4];
+#pragma unroll
+    for (int j = 0; j < (DH + 3) / 4; ++j) {
+        const int q = wv + 4 * j, sl = 64 * q + lane, h = sl >> 2;
+        const int g = (sl & 3) ^ ((h >> 2) & 3);
+        const int hr = h / HW, hc = h - hr * HW;
+        const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
+        const bool ok = q < DH && h < HP && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+        offX[j] = ok ? 2 * (((b * H + yy) * W + xx) * x.cs + x.coff + 8 * g) : -1;
+    }
+    int offW[(DW + 3) / 4];
+#pragma unroll
+    for (int j = 0; j < (DW + 3) / 4; ++j) {
+        const int q = wv + 4 * j, sl = 64 * q + lane, n = sl / WR, e = sl - n * WR;
+        const int tap = e >> 2, g = e & 3;
+        const bool ok = q < DW && n < BN && e < 36 && n0 + n < N;
+        offW[j] = ok ? 2 * ((n0 + n) * ldw + tap * C + 8 * g) : -1;
+    }
+    // A fragment slots of this lane for tap offset (0, 0): tile pixel of fragment i, group
+    const int g = lane >> 4;
+    int hA[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int p = wv * TM * 16 + i * 16 + (lane & 15), r = p / TW, c = p - r * TW;
+        hA[i] = (r + 1) * HW + c + 1;
+    }
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int sgn = flip ? -1 : 1;
+    for (int c0 = 0; c0 < C; c0 += 32) {
+        if (c0) __syncthreads();               // every wavefront done with the previous chunk
+#pragma unroll
+        for (int j = 0; j < (DH + 3) / 4; ++j)
+            if (wv + 4 * j < DH) dma16(rsX, lds0 + (unsigned)(wv + 4 * j) * 1024u, offX[j] >= 0 ? offX[j] + 2 * c0 : kOOB);
+#pragma unroll
+        for (int j = 0; j < (DW + 3) / 4; ++j)
+            if (wv + 4 * j < DW) dma16(rsW, ldsW + (unsigned)(wv + 4 * j) * 1024u, offW[j] >= 0 ? offW[j] + 2 * c0 : kOOB);
+        wait_vm<0>();
+        __syncthreads();                       // the chunk is staged
+        const bf16x8* Ws = smem + HS;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dh = sgn * ((tap / 3 - 1) * HW + (tap % 3 - 1));
+            bf16x8 a[TM], bb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int h = hA[i] + dh;
+                a[i] = smem[4 * h + (g ^ ((h >> 2) & 3))];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bb[j] = Ws[(j * 16 + (lane & 15)) * WR + 4 * tap + g];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    bf16* const tile = (bf16*)smem;
+    __syncthreads();                           // every wavefront done with the staged chunk
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wv * TM * 16 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = j * 16 + (lane & 15);
+                tile[row * LDR + col] = (__bf16)ep.pre(n0 + col, acc[i][j][r]);
+            }
+    __syncthreads();
+    constexpr int GPR = BN / 8;
+    for (int e = tid; e < BM * GPR; e += 256) {
+        const int row = e / GPR, gg = e - row * GPR;
+        const int r = row / TW, c = row - r * TW;
+        const int m = (b * H + y0 + r) * W + x0 + c, n = n0 + 8 * gg;
+        if (n < ep.N) ep.store8(m, n, *(const bf16x8*)(tile + row * LDR + 8 * gg));
+    }
+}
+
+// Halo-tile launch for a 3x3 convolution whose input has C % 32 == 0 channels and whose image
+// sides are multiples of the tile (returns false otherwise: the implicit GEMM runs instead).
+// 256-pixel tiles, or 128-pixel tiles where 256 would leave fewer than 1024 blocks.
+template <int TR, int TW, int BN>
+hipError_t conv3_launch(const Tensor& x, const bf16* w, int ldw, int N, int flip, const EpiAct& ep,
+                        hipStream_t s) {
+    dim3 g(x.B * (x.H / TR) * (x.W / TW), (N + BN - 1) / BN);
+    k_conv3<TR, TW, BN><<<g, 256, 0, s>>>(x, w, ldw, N, flip, ep);
+    return hipGetLastError();
+}
+template <int BN>
+bool conv3_halo(const Tensor& x, const bf16* w, int N, int flip, const EpiAct& ep, hipStream_t s,
+                hipError_t* err) {
+    if (x.C % 32 || x.W % 32) return false;
+    const int ldw = 9 * x.C, nt = (N + BN - 1) / BN;
+    const long px = (long)x.B * x.H * x.W;
+    const bool big = px / 256 * nt >= 1024;
+    if (x.W % 64 == 0) {
+        if (big && x.H % 4 == 0) { *err = conv3_launch<4, 64, BN>(x, w, ldw, N, flip, ep, s); return true; }
+        if (x.H % 2 == 0) { *err = conv3_launch<2, 64, BN>(x, w, ldw, N, flip, ep, s); return true; }
+        return false;
+    }
+    if (big && x.H % 8 == 0) { *err = conv3_launch<8, 32, BN>(x, w, ldw, N, flip, ep, s); return true; }
+    if (x.H % 4 == 0) { *err = conv3_launch<4, 32, BN>(x, w, ldw, N, flip, ep, s); return true; }
+    return false;
+}
+bool conv3_halo_any(const Tensor& x, const bf16* w, int N, int flip, const EpiAct& ep, hipStream_t s,
+                    hipError_t* err) {
+    return N <= 32 ? conv3_halo<32>(x, w, N, flip, ep, s, err) : conv3_halo<64>(x, w, N, flip, ep, s, err);
+}
+
 int ilog2(int v) {
     int s = 0;
     while ((1 << s) < v) ++s;
@@ -312,9 +497,11 @@ inline int matrix_bytes(int rows, int cols) { return (int)((size_t)rows * cols *
 hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu, const Tensor& y,
                     int ksize, hipStream_t s) {
     const int taps = ksize * ksize;
+    EpiAct ep{y.p, bias, y.cs, y.coff, relu, y.C};
+    hipError_t err;
+    if (ksize == 3 && conv3_halo_any(x, w, y.C, 0, ep, s, &err)) return err;
     LoadConvA la{x.p, x.B, x.H, x.W, x.C, x.cs, x.coff, ilog2(x.C), taps * x.C, 0, ksize, tensor_bytes(x)};
     LoadRows lb{w, y.C, taps * x.C, taps * x.C, matrix_bytes(y.C, taps * x.C)};
-    EpiAct ep{y.p, bias, y.cs, y.coff, relu, y.C};
     return gemm(la, lb, ep, x.B * x.H * x.W, y.C, taps * x.C, 1, s);
 }
 
@@ -322,10 +509,12 @@ hipError_t conv_fwd(const Tensor& x, const bf16* w, const float* bias, int relu,
 hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ksize, hipStream_t s,
                       const Tensor* relu_of) {
     const int taps = ksize * ksize;
-    LoadConvA la{dz.p, dz.B, dz.H, dz.W, dz.C, dz.cs, dz.coff, ilog2(dz.C), taps * dz.C, 1, ksize, tensor_bytes(dz)};
-    LoadRows lb{wt, dx.C, taps * dz.C, taps * dz.C, matrix_bytes(dx.C, taps * dz.C)};
     EpiAct ep{dx.p, nullptr, dx.cs, dx.coff, 0, dx.C, relu_of ? relu_of->p : nullptr,
               relu_of ? relu_of->cs : 0, relu_of ? relu_of->coff : 0};
+    hipError_t err;
+    if (ksize == 3 && conv3_halo_any(dz, wt, dx.C, 1, ep, s, &err)) return err;
+    LoadConvA la{dz.p, dz.B, dz.H, dz.W, dz.C, dz.cs, dz.coff, ilog2(dz.C), taps * dz.C, 1, ksize, tensor_bytes(dz)};
+    LoadRows lb{wt, dx.C, taps * dz.C, taps * dz.C, matrix_bytes(dx.C, taps * dz.C)};
     return gemm(la, lb, ep, dz.B * dz.H * dz.W, dx.C, taps * dz.C, 1, s);
 }
 
@@ -503,30 +692,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // transposing read touches (rows 8g + 4h + r, r < 4, two values of g) over distinct 32-byte
 // bank windows. Bias gradients (first n tile) are products with a fragment of ones in the
 // wavefronts of the first n column: sum_p dZ[p][co] in the MFMA's FP32 accumulation.
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef short s16x4 __attribute__((ext_vector_type(4)));
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
-typedef __attribute__((address_space(3))) bf16 lds_bf16;
-
-__device__ __forceinline__ i32x4 rsrc_words(const void* base, int bytes) {
-    const unsigned long long a = (unsigned long long)base;
-    return i32x4{(int)(unsigned)a, (int)((unsigned)(a >> 32) & 0xffffu), bytes, 0x00020000};
-}
-// 16 bytes per lane from byte offset voff of the resource (>= extent: zeros) into LDS at
-// lds_base + 16 * lane; lds_base is uniform across the wavefront. The LDS base is an operand
-// bound to M0 (the "{m0}" constraint), so the compiler sets M0 itself and knows it is read.
-__device__ __forceinline__ void dma16(i32x4 rs, unsigned lds_base, int voff) {
-    asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds"
-                 :: "v"(voff), "s"(rs), "{m0}"(lds_base) : "memory");
-}
-// Wait until at most N vector-memory operations of this wavefront are outstanding (the
-// expcnt and lgkmcnt fields of the s_waitcnt immediate left at their maximum).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
 template <int C>
 __device__ __forceinline__ int wg_swz(int p) {
     static_assert(C == 4 || C == 8 || C == 16, "chunks per pixel row");
