@@ -19,6 +19,11 @@ Printed as one JSON line. Extra keys:
   roofline.project_plus_adjoint
                 algorithmic HBM bytes of projector and adjoint (maps and sinograms in and out)
                 over their summed launch time, against 8 TB/s;
+  roofline.valu_issue
+                the dominant kernel's VALU wavefront instructions per launch (rocprofv3
+                SQ_INSTS_VALU, recorded with the source hash like `traffic`) over the chip's
+                issue rate (one per SIMD per 4 cycles), against its launch time: how close the
+                kernel is to the bound that binds it;
   cpu_baseline  the FP64 oracle on this host, single thread, two cost+gradient evaluations
                 of the same slice, scaled to slice-iterations/s; `host`: one oracle process per
                 host core (at most 16) at the same time, the host's aggregate rate;
@@ -74,6 +79,18 @@ TRAFFIC = {
     "project": {"src": "8bae7ef64b4443db", "variant": 23, "bytes": 24.98e6},
     "backproject": {"src": "8bae7ef64b4443db", "variant": 12, "bytes": 22.92e6},
 }
+
+
+# VALU wavefront instructions per launch at this workload (rocprofv3 --pmc SQ_INSTS_VALU,
+# medians over working launches, same source and tiles as TRAFFIC). A SIMD has 16 lanes, so a
+# wavefront of 64 issues one VALU instruction per 4 cycles: the chip issues at most
+# 1024 SIMDs x 2.4 GHz / 4 = 6.14e11 wavefront instructions per second, and the kernel's VALU
+# issue fraction is its instruction count over that rate and its launch time.
+VALU_INSTS = {
+    "project": {"src": "8bae7ef64b4443db", "variant": 23, "insts": 3.2235e7},
+    "backproject": {"src": "8bae7ef64b4443db", "variant": 12, "insts": 2.7450e7},
+}
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
 def _src_hash() -> str:
@@ -727,6 +744,11 @@ def main():
         "tiling": {"proj_variant": info["proj_variant"], "adj_variant": info["adj_variant"],
                    "adj_splits": info["adj_splits"]},
     }
+    vi = VALU_INSTS.get(dom)
+    if vi and vi["src"] == _src_hash() and vi["variant"] == (info["proj_variant"] if dom == "project" else info["adj_variant"]):
+        issue_us = vi["insts"] / VALU_ISSUE_PER_S * 1e6
+        roof["valu_issue"] = {"insts_per_launch": vi["insts"], "per_unit": round(vi["insts"] * 64 / units, 2),
+                              "issue_bound_us": round(issue_us, 2), "frac": round(issue_us / (ms * 1e3), 4)}
 
     ttt = None
     if not args.no_warm_start:
