@@ -52,8 +52,16 @@ hipError_t mse_loss(const float* out, const float* target, size_t n, double* par
 hipError_t head_bwd(const Tensor& a, const float* w, const float* dout, int B, int H, int W,
                     float* dw, float* db, float* part, int nblk, const Tensor& da, hipStream_t s);
 hipError_t to_bf16(const float* src, bf16* dst, size_t n, hipStream_t s);
-// dst[i][t][o] = src[o][t][i] for src of shape [O][T][I] (weight transposes for dgrad)
-hipError_t transpose_oti(const float* src, bf16* dst, int O, int T, int I, hipStream_t s);
+// Weight transposes for the data gradients, all layers in one launch: layer j's weights
+// src[src_j + (o T + t) I + i] (shape [O][T][I]) go to dst[dst_j + (i T + t) O + o] as BF16;
+// begin[j] is the running element count (begin[0] = 0, begin[n] = the total).
+constexpr int kOtiMax = 24;
+struct OtiTable {
+    int n;
+    size_t begin[kOtiMax + 1], src[kOtiMax], dst[kOtiMax];
+    int O[kOtiMax], T[kOtiMax], I[kOtiMax];
+};
+hipError_t transpose_oti(const OtiTable& tab, const float* src, bf16* dst, hipStream_t s);
 hipError_t adam(float* p, float* m, float* v, const float* g, size_t n, float lr, float b1,
                 float b2, float eps, float c1, float c2, hipStream_t s);
 

@@ -134,12 +134,27 @@ __global__ __launch_bounds__(kT) void k_chsum2(const float* part, int nblk, int 
     }
 }
 
-__global__ void k_splitk(const float* part, int splits, int n, float* out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float s = 0.f;
+// out[i] = sum_z part[z][i]. A block takes 32 consecutive i and its 8 wavefront halves split
+// the slabs: half h sums z = h, h + 8, ... in order, then the 8 half sums are added in order
+// of h (a fixed order: the result does not depend on scheduling). Every block reads 32
+// consecutive floats (128 bytes) of each slab it visits.
+constexpr int kSkCols = 32, kSkGroups = kT / kSkCols;
+__global__ __launch_bounds__(kT) void k_splitk(const float* part, int splits, int n, float* out) {
+    __shared__ float red[kSkGroups][kSkCols];
+    const int col = threadIdx.x % kSkCols, grp = threadIdx.x / kSkCols;
+    const int i = blockIdx.x * kSkCols + col;
+    float s = 0.f;
+    if (i < n) {
 #pragma unroll 8
-        for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
-        out[i] = s;
+        for (int z = grp; z < splits; z += kSkGroups) s += part[(size_t)z * n + i];
+    }
+    red[grp][col] = s;
+    __syncthreads();
+    if (grp == 0 && i < n) {
+        float t = red[0][col];
+#pragma unroll
+        for (int h = 1; h < kSkGroups; ++h) t += red[h][col];
+        out[i] = t;
     }
 }
 
@@ -251,13 +266,20 @@ __global__ void k_tobf16(const float* s, bf16* d, size_t n) {
         d[i] = (bf16)s[i];
 }
 
-__global__ void k_transpose_oti(const float* s, bf16* d, int O, int T, int I) {
-    const size_t n = (size_t)O * T * I;
+// Every layer's transposed BF16 weight copy in one launch: element e of the concatenated
+// weight tensors belongs to the layer j with begin[j] <= e < begin[j + 1]; within it
+// d[i][t][o] = s[o][t][i] for the layer's [O][T][I] weights.
+__global__ void k_transpose_oti(OtiTable tab, const float* s, bf16* d) {
+    const size_t n = tab.begin[tab.n];
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = e % I;
-        const size_t r = e / I;
+        int j = 0;
+        while (e >= tab.begin[j + 1]) ++j;
+        const size_t le = e - tab.begin[j];
+        const int O = tab.O[j], T = tab.T[j], I = tab.I[j];
+        const int i = le % I;
+        const size_t r = le / I;
         const int t = r % T, o = r / T;
-        d[((size_t)i * T + t) * O + o] = (bf16)s[e];
+        d[tab.dst[j] + ((size_t)i * T + t) * O + o] = (bf16)s[tab.src[j] + le];
     }
 }
 
@@ -293,7 +315,7 @@ hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipS
     return hipGetLastError();
 }
 hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s) {
-    k_splitk<<<nblocks((size_t)n), kT, 0, s>>>(part, splits, n, out);
+    k_splitk<<<(n + kSkCols - 1) / kSkCols, kT, 0, s>>>(part, splits, n, out);
     return hipGetLastError();
 }
 hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in, float* out,
@@ -320,8 +342,9 @@ hipError_t to_bf16(const float* src, bf16* dst, size_t n, hipStream_t s) {
     k_tobf16<<<nblocks(n), kT, 0, s>>>(src, dst, n);
     return hipGetLastError();
 }
-hipError_t transpose_oti(const float* src, bf16* dst, int O, int T, int I, hipStream_t s) {
-    k_transpose_oti<<<nblocks((size_t)O * T * I), kT, 0, s>>>(src, dst, O, T, I);
+hipError_t transpose_oti(const OtiTable& tab, const float* src, bf16* dst, hipStream_t s) {
+    if (tab.n < 1 || tab.n > kOtiMax) return hipErrorInvalidValue;
+    k_transpose_oti<<<nblocks(tab.begin[tab.n]), kT, 0, s>>>(tab, src, dst);
     return hipGetLastError();
 }
 hipError_t adam(float* p, float* m, float* v, const float* g, size_t n, float lr, float b1,

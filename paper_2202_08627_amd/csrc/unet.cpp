@@ -256,10 +256,18 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
 
 int prepare_weights(const eit_unet* u, const float* prm, bf16* wf, bf16* wt, hipStream_t s) {
     NN_TRY(to_bf16(prm, wf, u->n_params, s));
+    OtiTable tab{};
     for (const Layer& l : u->L) {
-        if (l.kind == 0) NN_TRY(transpose_oti(prm + l.w, wt + l.wt, l.cout, 9, l.cin, s));
-        if (l.kind == 1) NN_TRY(transpose_oti(prm + l.w, wt + l.wt, l.cout, 4, l.cin, s));
+        if (l.kind != 0 && l.kind != 1) continue;
+        const int j = tab.n++;
+        tab.O[j] = l.cout;
+        tab.T[j] = l.kind == 0 ? 9 : 4;
+        tab.I[j] = l.cin;
+        tab.src[j] = l.w;
+        tab.dst[j] = l.wt;
+        tab.begin[j + 1] = tab.begin[j] + (size_t)tab.O[j] * tab.T[j] * tab.I[j];
     }
+    NN_TRY(transpose_oti(tab, prm, wt, s));
     return EIT_OK;
 }
 
