@@ -74,5 +74,27 @@ inline int wgrad_splits_used(int pixels, int splits) {
     return (pixels + kps - 1) / kps;
 }
 
+// 3x3 weight gradients by 128-pixel halo tiles (k_wgrad3: 2 x 64 tiles, or 4 x 32 where the
+// width is not a multiple of 64; 32 or 64 output channels per block) for input and output
+// channel counts that are multiples of 32; the slabs are sized for about 512 blocks (at most
+// one per tile: more blocks mean more partial sums to write and reduce, fewer leave CUs idle). wgrad3_parts is the number of partial slabs conv_wgrad then writes.
+inline bool wgrad3_halo(int h, int w, int ci, int co) {
+    return ci % 32 == 0 && co % 32 == 0 && w % 32 == 0 && (w % 64 == 0 ? h % 2 == 0 : h % 4 == 0);
+}
+inline int wgrad3_co(int co) { return co % 64 == 0 ? 64 : 32; }
+inline int wgrad3_parts(int nb, int h, int w, int ci, int co) {
+    const int T = nb * h * w / 128, bps = (co / wgrad3_co(co)) * (ci / 32);
+    int sp = (512 + bps - 1) / bps;
+    sp = sp < T ? sp : T;
+    sp = sp > 1 ? sp : 1;
+    const int tps = (T + sp - 1) / sp;
+    return (T + tps - 1) / tps;
+}
+// Partial slabs written by conv_wgrad for an input of nb x h x w pixels, ci channels, and co
+// output channels, given the split count of the general kernel.
+inline int conv_wgrad_parts(int nb, int h, int w, int ci, int co, int splits) {
+    return wgrad3_halo(h, w, ci, co) ? wgrad3_parts(nb, h, w, ci, co) : wgrad_splits_used(nb * h * w, splits);
+}
+
 }  // namespace nn
 }  // namespace eit

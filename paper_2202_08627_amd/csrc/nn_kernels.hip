@@ -862,10 +862,155 @@ __global__ __launch_bounds__(256) void k_wgrad_tr(Tensor dz, Tensor x, float* __
         }
 }
 
+// --------------------------------------------------------------------------- weight gradients, 3x3 halo tiles
+// dW[co][tap][ci] = sum_p dZ[p][co] X[p + off(tap)][ci] and db[co] = sum_p dZ[p][co] over
+// TR x TW pixel tiles: per tile a block stages the tile's dZ (CO output channels) and the tile's
+// X with its one-pixel border (32 input channels, zeros outside the image) once, by direct
+// buffer-to-LDS loads, and all nine taps read from the staged X; k_wgrad_tr instead loads X
+// once per tap column of every n tile. Three wavefronts, one per stencil row dy: wavefront w
+// takes the taps (w, dx = -1, 0, 1) for CO output x 32 input channels and reads the dZ
+// fragments once per 32-pixel k step for its three taps. Layouts: groups of 8 channels per
+// pixel (CO / 8 for dZ, 4 for X), group g of pixel h at slot G h + (g ^ ((h >> 2) & 3)); MFMA
+// fragments (8 consecutive pixels of one channel per lane) come from pairs of transposing
+// reads (ds_read_b64_tr_b16), as in k_wgrad_tr. A block's split z covers tiles
+// [z tps, (z + 1) tps) in order, with the next tile's loads in flight during the current one
+// (two stage buffers); it writes its partial sums as part[z][co][tap][ci] followed by the Co
+// bias partials (first input-channel chunk).
+template <int TR, int TW, int CO>
+__global__ __launch_bounds__(192) void k_wgrad3(Tensor dz, Tensor x, float* __restrict__ part, int tps, int ntiles) {
+    constexpr int BM = TR * TW, HW = TW + 2, HP = (TR + 2) * HW, GA = CO / 8, TMo = CO / 16;
+    constexpr int SA = BM * GA, SH = (4 * HP + 63) / 64 * 64, STG = SA + SH;
+    constexpr int DA = SA / 64, DH = SH / 64, NW = 3;
+    static_assert(BM % 32 == 0 && (GA == 4 || GA == 8), "tile");
+    __shared__ __attribute__((aligned(16))) bf16 lds[2 * STG * 8];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int H = x.H, W = x.W, Co = dz.C, Ci = x.C;
+    const int tx = W / TW, ty = H / TR;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = tile_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bz = t / (gx * gy), cot = t % gx, cic = (t / gx) % gy;   // channel tiles of a slab adjacent
+    const int t0 = bz * tps, t1 = min(ntiles, t0 + tps);
+    const i32x4 rsA = rsrc_words(dz.p, (int)((size_t)dz.B * H * W * dz.cs * sizeof(bf16)));
+    const i32x4 rsX = rsrc_words(x.p, (int)((size_t)x.B * H * W * x.cs * sizeof(bf16)));
+    const unsigned lds0 = (unsigned)(size_t)(lds_bf16*)lds;
+    auto swz = [](int h) { return (h >> 2) & 3; };
+    // loads of tile tt into stage buffer buf: wavefront w issues wavefront loads w, w + 3, ...
+    auto issue = [&](int tt, int buf) {
+        const int b = tt / (tx * ty), y0 = (tt / tx) % ty * TR, x0 = tt % tx * TW;
+        const unsigned base = lds0 + (unsigned)(buf * STG) * 16u;
+        for (int q = wv; q < DA + DH; q += NW) {
+            int off = kOOB;
+            if (q < DA) {
+                const int sl = 64 * q + lane, P = sl / GA, g = (sl % GA) ^ swz(P);
+                const int r = P / TW, c = P - r * TW;
+                off = 2 * (((b * H + y0 + r) * W + x0 + c) * dz.cs + dz.coff + CO * cot + 8 * g);
+                dma16(rsA, base + (unsigned)q * 1024u, off);
+            } else {
+                const int sl = 64 * (q - DA) + lane, h = sl >> 2, g = (sl & 3) ^ swz(h);
+                const int hr = h / HW, hc = h - hr * HW, yy = y0 - 1 + hr, xx = x0 - 1 + hc;
+                if (h < HP && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                    off = 2 * (((b * H + yy) * W + xx) * x.cs + x.coff + 32 * cic + 8 * g);
+                dma16(rsX, base + (unsigned)q * 1024u, off);
+            }
+        }
+    };
+    // transposing-read addresses: lane group g, row r, column piece c reads pixel row
+    // 8 g + 4 hh + r of a 32-pixel k step, channels 16 i + 4 c .. + 3
+    const int g = lane >> 4, r = (lane >> 2) & 3, c = lane & 3;
+    auto slot_addr = [&](int G, int h, int i) {   // byte address of channels 16 i + 4 c .. of pixel h
+        const int q = 2 * i + (c >> 1);
+        return (G * h + (q ^ swz(h))) * 16 + 8 * (c & 1);
+    };
+    f32x4 acc[3][TMo][2], accb[TMo];
+#pragma unroll
+    for (int i = 0; i < TMo; ++i) {
+        accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bool bias_w = cic == 0 && wv == 0;
+    bf16x8 ones;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ones[u] = (__bf16)1.0f;
+    const int dyw = wv - 1;
+    if (t0 < t1) issue(t0, 0);
+    for (int tt = t0, it = 0; tt < t1; ++tt, ++it) {
+        wait_vm<0>();                          // this wavefront's loads of tile tt landed
+        __syncthreads();                       // every part landed; the other buffer consumed
+        if (tt + 1 < t1) issue(tt + 1, (it + 1) & 1);
+        const char __attribute__((address_space(3)))* st0 =
+            (const char __attribute__((address_space(3)))*)(lds_bf16*)lds + (it & 1) * STG * 16;
+        auto tr = [&](int off) { return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(st0 + off)); };
+        auto frag = [&](int o0, int o1) {
+            const s16x4 v0 = tr(o0), v1 = tr(o1);
+            return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(v0, v1, 0, 1, 2, 3, 4, 5, 6, 7));
+        };
+#pragma unroll 1
+        for (int k0 = 0; k0 < BM; k0 += 32) {
+            const int P0 = k0 + 8 * g + r, P1 = P0 + 4;
+            bf16x8 a[TMo];
+#pragma unroll
+            for (int i = 0; i < TMo; ++i) a[i] = frag(slot_addr(GA, P0, i), slot_addr(GA, P1, i));
+            // halo pixel of tile pixel P shifted by (dyw, dx)
+            const int h0 = (P0 / TW + 1 + dyw) * HW + P0 % TW + 1, h1 = (P1 / TW + 1 + dyw) * HW + P1 % TW + 1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                bf16x8 bb[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bb[j] = frag(SA * 16 + slot_addr(4, h0 + d - 1, j), SA * 16 + slot_addr(4, h1 + d - 1, j));
+#pragma unroll
+                for (int i = 0; i < TMo; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[d][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[d][i][j], 0, 0, 0);
+            }
+            if (bias_w) {
+#pragma unroll
+                for (int i = 0; i < TMo; ++i) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ones, accb[i], 0, 0, 0);
+            }
+        }
+    }
+    wait_vm<0>();
+    const size_t mn = (size_t)Co * 9 * Ci;
+    float* dst = part + (size_t)bz * (mn + Co);
+#pragma unroll
+    for (int i = 0; i < TMo; ++i)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+            const int co = CO * cot + 16 * i + 4 * (lane >> 4) + r4;
+            if (bias_w && (lane & 15) == 0) dst[mn + co] = accb[i][r4];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int tap = 3 * wv + d, ci = 32 * cic + 16 * j + (lane & 15);
+                    dst[((size_t)co * 9 + tap) * Ci + ci] = acc[d][i][j][r4];
+                }
+        }
+}
+
 constexpr int kWtStages = 2;
 hipError_t conv_wgrad(const Tensor& x, const Tensor& dz, float* part, int splits, int ksize,
                       hipStream_t s) {
     if (ksize != 3) return hipErrorInvalidValue;
+    if (wgrad3_halo(x.H, x.W, x.C, dz.C)) {
+        const int co = wgrad3_co(dz.C);
+        const int tr = x.W % 64 == 0 ? 2 : 4, tw = x.W % 64 == 0 ? 64 : 32;
+        const int T = x.B * (x.H / tr) * (x.W / tw);
+        const int sp = wgrad3_parts(x.B, x.H, x.W, x.C, dz.C), tps = (T + sp - 1) / sp;
+        dim3 g(dz.C / co, x.C / 32, sp);
+        if (co == 32) {
+            if (tw == 64) k_wgrad3<2, 64, 32><<<g, 192, 0, s>>>(dz, x, part, tps, T);
+            else k_wgrad3<4, 32, 32><<<g, 192, 0, s>>>(dz, x, part, tps, T);
+        } else {
+            if (tw == 64) k_wgrad3<2, 64, 64><<<g, 192, 0, s>>>(dz, x, part, tps, T);
+            else k_wgrad3<4, 32, 64><<<g, 192, 0, s>>>(dz, x, part, tps, T);
+        }
+        return hipGetLastError();
+    }
     const int P = x.B * x.H * x.W;
     const int kps = wgrad_slab(P, splits);
     const int sp = wgrad_splits_used(P, splits);

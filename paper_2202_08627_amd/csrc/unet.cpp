@@ -114,7 +114,9 @@ WsLayout layout(const eit_unet* u, int nb, int h, int w, bool train) {
             if (i >= D2A && i <= UP1) { hh = h / 2; ww = w / 2; }
             const size_t pix = (size_t)nb * hh * ww;
             const size_t mn = l.kind == 0 ? (size_t)l.cout * 9 * l.cin + l.cout : (size_t)4 * l.cout * l.cin;
-            if (l.kind != 2) pe = std::max(pe, mn * wgrad_splits(pix));
+            const size_t parts = l.kind == 0 ? (size_t)conv_wgrad_parts(nb, hh, ww, l.cin, l.cout, wgrad_splits(pix))
+                                             : (size_t)wgrad_splits_used((int)pix, wgrad_splits(pix));
+            if (l.kind != 2) pe = std::max(pe, mn * parts);
         }
     }
     L.part_elems = pe;
@@ -204,8 +206,8 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
         // weight and bias partials; one reduction writes both (the bias directly follows the
         // weights in the parameter layout)
         NN_TRY(conv_wgrad(X, dY, part, sp, 3, s));
-        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), L[li].cout * 9 * L[li].cin + L[li].cout,
-                             grad + L[li].w, s));
+        NN_TRY(splitk_reduce(part, conv_wgrad_parts(X.B, X.H, X.W, X.C, dY.C, sp),
+                             L[li].cout * 9 * L[li].cin + L[li].cout, grad + L[li].w, s));
         if (dX) NN_TRY(conv_dgrad(dY, c.wt + L[li].wt, *dX, 3, s, mask_dx ? &X : nullptr));
         return EIT_OK;
     };
