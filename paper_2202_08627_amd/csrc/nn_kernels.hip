@@ -105,6 +105,21 @@ struct LoadRows {
     }
 };
 
+// Transposed-convolution weights [Co][4][Ci] read with the rows in sub-pixel-major order:
+// GEMM row n = d Co + co is parameter row 4 co + d, so 8 consecutive GEMM columns are 8
+// consecutive channels of one output pixel (the epilogue stores them with one 16-byte store).
+struct LoadRowsUp {
+    const bf16* t; int co_n, K, ld, bytes;
+    typedef LoadRows::Ctx Ctx;
+    __device__ Ctx row(int r, int) const {
+        const int d = r / co_n, co = r - d * co_n;
+        return Ctx{r < 4 * co_n ? 2 * (4 * co + d) * ld : 0, r < 4 * co_n};
+    }
+    __device__ bf16x8 load(const Ctx& r, int k0, bool ok) const {
+        return bld8(t, bytes, ok && r.ok && k0 < K ? r.off + 2 * k0 : kOOB);
+    }
+};
+
 // Transposed-convolution (2x2, stride 2) output gradient seen from an input pixel:
 // row m = input pixel (b, y, x), k = d * C + c, value = g[b, 2y + d/2, 2x + d%2, c].
 struct LoadUpGradA {
@@ -165,6 +180,18 @@ struct EpiUp {
         const int x = m % W, yb = m / W, y = yb % H, b = yb / H;
         v += bias[c];
         t[((size_t)(b * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * cs + coff + c] = (__bf16)v;
+    }
+};
+// The same with the GEMM columns in sub-pixel-major order (n = d C + c, LoadRowsUp): staged
+// through LDS and stored 8 channels (16 bytes) at a time.
+struct EpiUpV {
+    static constexpr bool kVector = true;
+    bf16* t; const float* bias; int B, H, W, C, cs, coff, N;
+    __device__ float pre(int n, float v) const { return n < N ? v + bias[n % C] : v; }
+    __device__ void store8(int m, int n, bf16x8 v) const {
+        const int d = n / C, c = n - d * C;
+        const int x = m % W, yb = m / W, y = yb % H, b = yb / H;
+        *(bf16x8*)(t + ((size_t)(b * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * cs + coff + c) = v;
     }
 };
 // FP32 split-K partials [split][M][N].
@@ -522,6 +549,11 @@ hipError_t conv_dgrad(const Tensor& dz, const bf16* wt, const Tensor& dx, int ks
 hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const Tensor& y,
                       hipStream_t s) {
     LoadRows la{x.p + x.coff, x.B * x.H * x.W, x.C, x.cs, tensor_bytes(x) - 2 * x.coff};
+    if (y.C % 8 == 0 && y.cs % 8 == 0 && y.coff % 8 == 0) {
+        LoadRowsUp lb{w, y.C, x.C, x.C, matrix_bytes(4 * y.C, x.C)};
+        EpiUpV ep{y.p, bias, x.B, x.H, x.W, y.C, y.cs, y.coff, 4 * y.C};
+        return gemm(la, lb, ep, x.B * x.H * x.W, 4 * y.C, x.C, 1, s);
+    }
     LoadRows lb{w, 4 * y.C, x.C, x.C, matrix_bytes(4 * y.C, x.C)};
     EpiUp ep{y.p, bias, x.B, x.H, x.W, y.C, y.cs, y.coff, 4 * y.C};
     return gemm(la, lb, ep, x.B * x.H * x.W, 4 * y.C, x.C, 1, s);
