@@ -69,23 +69,30 @@ __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
         const size_t p = e / G;
         const int xx = p % y.W, yb = p / y.W, yy = yb % y.H, b = yb / y.H;
         const bf16x8 m = vld(y, b, yy, xx, c), g = vld(dy, b, yy, xx, c);
+        // every load of the window before the first store (the stores could alias them for
+        // all the compiler knows, which would serialise four memory round trips)
+        bf16x8 xv[4], d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int iy = 2 * yy + (q >> 1), ix = 2 * xx + (q & 1);
+            xv[q] = vld(x, b, iy, ix, c);
+            d[q] = vld(dx, b, iy, ix, c);
+        }
         bool done[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) done[i] = false;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int iy = 2 * yy + (q >> 1), ix = 2 * xx + (q & 1);
-            const bf16x8 xv = vld(x, b, iy, ix, c);
-            bf16x8 d = vld(dx, b, iy, ix, c);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const bool arg = !done[i] && (float)xv[i] == (float)m[i];
+                const bool arg = !done[i] && (float)xv[q][i] == (float)m[i];
                 done[i] = done[i] || arg;
-                if (!((float)xv[i] > 0.f)) d[i] = (bf16)0.f;
-                else if (arg) d[i] = (bf16)((float)d[i] + (float)g[i]);
+                if (!((float)xv[q][i] > 0.f)) d[q][i] = (bf16)0.f;
+                else if (arg) d[q][i] = (bf16)((float)d[q][i] + (float)g[i]);
             }
-            vst(dx, b, iy, ix, c, d);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vst(dx, b, 2 * yy + (q >> 1), 2 * xx + (q & 1), c, d[q]);
     }
 }
 
@@ -187,10 +194,21 @@ __global__ __launch_bounds__(kT) void k_mse1(const float* out, const float* t, s
     __shared__ double red[kT / 64];
     const size_t i0 = n * blockIdx.x / nblk, i1 = n * (blockIdx.x + 1) / nblk;
     double s = 0.0;
-    for (size_t i = i0 + threadIdx.x; i < i1; i += kT) {
-        const float r = out[i] - t[i];
-        s += (double)r * r;
-        if (dout) dout[i] = 2.f * r / (float)n;
+    constexpr int U = 4;      // U elements' loads before their stores; the sum runs over i in order
+    for (size_t iu = i0 + threadIdx.x; iu < i1; iu += (size_t)U * kT) {
+        float r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = iu + (size_t)u * kT;
+            r[u] = i < i1 ? out[i] - t[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = iu + (size_t)u * kT;
+            if (i >= i1) break;
+            s += (double)r[u] * r[u];
+            if (dout) dout[i] = 2.f * r[u] / (float)n;
+        }
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -223,22 +241,39 @@ __global__ __launch_bounds__(kT) void k_head_bwd1(Tensor a, const float* w, cons
         s1[i] = 0.f;
     }
     float b0 = 0.f, b1 = 0.f;
-    for (size_t p = p0 + pl; p < p1; p += NL) {
-        const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
-        const float g0 = dout[((size_t)(b * 2 + 0) * H + y) * W + xx];
-        const float g1 = dout[((size_t)(b * 2 + 1) * H + y) * W + xx];
-        const bf16x8 v = *(const bf16x8*)(a.p + p * a.cs + a.coff + 8 * g);
-        bf16x8 d;
+    // U pixels' loads are issued before their stores (which could alias them for all the
+    // compiler knows); the sums still run over p in order
+    constexpr int U = 4;
+    for (size_t pu = p0 + pl; pu < p1; pu += (size_t)U * NL) {
+        float g0[U], g1[U];
+        bf16x8 v[U];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float av = (float)v[i];
-            s0[i] = fmaf(g0, av, s0[i]);
-            s1[i] = fmaf(g1, av, s1[i]);
-            d[i] = av > 0.f ? (bf16)fmaf(g0, w0[i], g1 * w1[i]) : (bf16)0.f;
+        for (int u = 0; u < U; ++u) {
+            const size_t p = pu + (size_t)u * NL;
+            g0[u] = g1[u] = 0.f;
+            if (p < p1) {
+                const int xx = p % W, yb = p / W, y = yb % H, b = yb / H;
+                g0[u] = dout[((size_t)(b * 2 + 0) * H + y) * W + xx];
+                g1[u] = dout[((size_t)(b * 2 + 1) * H + y) * W + xx];
+                v[u] = *(const bf16x8*)(a.p + p * a.cs + a.coff + 8 * g);
+            }
         }
-        *(bf16x8*)(da.p + p * da.cs + da.coff + 8 * g) = d;
-        b0 += g0;
-        b1 += g1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t p = pu + (size_t)u * NL;
+            if (p >= p1) break;
+            bf16x8 d;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float av = (float)v[u][i];
+                s0[i] = fmaf(g0[u], av, s0[i]);
+                s1[i] = fmaf(g1[u], av, s1[i]);
+                d[i] = av > 0.f ? (bf16)fmaf(g0[u], w0[i], g1[u] * w1[i]) : (bf16)0.f;
+            }
+            *(bf16x8*)(da.p + p * da.cs + da.coff + 8 * g) = d;
+            b0 += g0[u];
+            b1 += g1[u];
+        }
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
