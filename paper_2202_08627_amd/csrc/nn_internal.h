@@ -34,6 +34,9 @@ hipError_t upconv_fwd(const Tensor& x, const bf16* w, const float* bias, const T
                       hipStream_t s);
 hipError_t upconv_dgrad(const Tensor& g, const bf16* wt, const Tensor& dx, hipStream_t s,
                         const Tensor* relu_of = nullptr);
+// Transposed-convolution weight gradients: part[z] holds the 4 Co Ci weight partials
+// ([co][d][ci]) followed by 4 Co row sums sum_p G[(d, co)][p] (index d Co + co), whose sum over
+// d is the bias gradient's partial
 hipError_t upconv_wgrad(const Tensor& x, const Tensor& g, float* part, int splits, hipStream_t s);
 
 // element-wise and reduction kernels (nn_misc.hip)
@@ -43,8 +46,10 @@ hipError_t maxpool_fwd(const Tensor& x, const Tensor& y, hipStream_t s);
 // post-ReLU pooling input); the windows cover x (even sides)
 hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, const Tensor& dx,
                            hipStream_t s);
-hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s);
-hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s);
+// out[i] = sum_z part[z ld + i] for i < n (ld = 0: ld = n)
+hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s, size_t ld = 0);
+// out[c] = sum_z sum_d part[z ld + d C + c], d < D
+hipError_t fold_sums(const float* part, int splits, size_t ld, int C, int D, float* out, hipStream_t s);
 hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in,
                     float* out, int B, int H, int W, hipStream_t s);
 hipError_t mse_loss(const float* out, const float* target, size_t n, double* part, int nblk,

@@ -628,11 +628,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int n = n0 + 8 * ob;
     const bool n_ok = n < N;
     const int ci = n_ok ? n : 0;
-    f32x4 acc[2][2];
+    f32x4 acc[2][2], accb[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // bias sums (first n tile, first wavefront column): products with a fragment of ones give
+    // sum_p G[(d, co)][p] per row, the up-conv bias gradient before its sum over d
+    const bool bias_w = by == 0 && wn == 0;
+    bf16x8 ones;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ones[u] = (__bf16)1.0f;
     bf16x8 av[AP], bv[BP];
     const int a_bytes = (int)((size_t)dz.B * dz.H * dz.W * dz.cs * sizeof(bf16));
     const int b_bytes = (int)((size_t)x.B * x.H * x.W * x.cs * sizeof(bf16));
@@ -687,9 +695,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+            if (bias_w) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ones, accb[i], 0, 0, 0);
+            }
         }
     }
-    float* dst = part + (size_t)bz * (Co * 4 * Ci);
+    float* dst = part + (size_t)bz * (Co * 4 * Ci + 4 * Co);     // weights, then the 4 Co row sums
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -697,6 +709,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int o = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                if (bias_w && (lane & 15) == 0 && o < M) dst[(size_t)Co * 4 * Ci + o] = accb[i][r];
                 const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (o < M && nn < N) {
                     const int dd = o / Co, cc = o - dd * Co;

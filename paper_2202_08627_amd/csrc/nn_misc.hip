@@ -96,32 +96,8 @@ __global__ void k_pool_bwd(Tensor x, Tensor y, Tensor dy, Tensor dx) {
     }
 }
 
-// Stage 1: block k sums pixels [k*P/nblk, (k+1)*P/nblk) of every channel -> part[k][C].
-// Thread (channel group g of 8 channels, pixel lane pl) reads 16 bytes per pixel; the pixel
-// lanes' sums meet in LDS in a fixed order.
-__global__ __launch_bounds__(kT) void k_chsum1(Tensor t, float* part, int nblk) {
-    __shared__ float red[kT * 8];
-    const size_t P = (size_t)t.B * t.H * t.W;
-    const size_t p0 = P * blockIdx.x / nblk, p1 = P * (blockIdx.x + 1) / nblk;
-    const int C = t.C, G = C / 8;                 // G divides kT (C <= 8 kT, power of two)
-    const int g = threadIdx.x % G, pl = threadIdx.x / G, NL = kT / G;
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (size_t p = p0 + pl; p < p1; p += NL) {
-        const bf16x8 v = *(const bf16x8*)(t.p + p * t.cs + t.coff + 8 * g);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) red[threadIdx.x * 8 + i] = acc[i];
-    __syncthreads();
-    for (int c = threadIdx.x; c < C; c += kT) {
-        float v = 0.f;
-        for (int l = 0; l < NL; ++l) v += red[(l * G + c / 8) * 8 + c % 8];
-        part[(size_t)blockIdx.x * C + c] = v;
-    }
-}
-// Stage 2: out[c] = sum_k part[k][c], 32 columns per pass, eight row lanes each; the lanes'
-// sums meet in LDS in a fixed order.
+// out[c] = sum_k part[k][c] over per-block partials (the head backward's weight and bias sums),
+// 32 columns per pass, eight row lanes each; the lanes' sums meet in LDS in a fixed order.
 __global__ __launch_bounds__(kT) void k_chsum2(const float* part, int nblk, int C, float* out) {
     __shared__ float red[kT];
     const int cl = threadIdx.x & 31, rl = threadIdx.x >> 5;   // column lane, row lane (8)
@@ -146,14 +122,14 @@ __global__ __launch_bounds__(kT) void k_chsum2(const float* part, int nblk, int 
 // of h (a fixed order: the result does not depend on scheduling). Every block reads 32
 // consecutive floats (128 bytes) of each slab it visits.
 constexpr int kSkCols = 32, kSkGroups = kT / kSkCols;
-__global__ __launch_bounds__(kT) void k_splitk(const float* part, int splits, int n, float* out) {
+__global__ __launch_bounds__(kT) void k_splitk(const float* part, int splits, int n, size_t ld, float* out) {
     __shared__ float red[kSkGroups][kSkCols];
     const int col = threadIdx.x % kSkCols, grp = threadIdx.x / kSkCols;
     const int i = blockIdx.x * kSkCols + col;
     float s = 0.f;
     if (i < n) {
 #pragma unroll 8
-        for (int z = grp; z < splits; z += kSkGroups) s += part[(size_t)z * n + i];
+        for (int z = grp; z < splits; z += kSkGroups) s += part[(size_t)z * ld + i];
     }
     red[grp][col] = s;
     __syncthreads();
@@ -344,13 +320,23 @@ hipError_t maxpool_bwd_add(const Tensor& x, const Tensor& y, const Tensor& dy, c
     k_pool_bwd<<<nblocks((size_t)y.B * y.H * y.W * (y.C / 8)), kT, 0, s>>>(x, y, dy, dx);
     return hipGetLastError();
 }
-hipError_t channel_sums(const Tensor& t, float* part, int nblk, float* out, hipStream_t s) {
-    k_chsum1<<<nblk, kT, 0, s>>>(t, part, nblk);
-    k_chsum2<<<(t.C + 31) / 32, kT, 0, s>>>(part, nblk, t.C, out);
+hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s, size_t ld) {
+    k_splitk<<<(n + kSkCols - 1) / kSkCols, kT, 0, s>>>(part, splits, n, ld ? ld : (size_t)n, out);
     return hipGetLastError();
 }
-hipError_t splitk_reduce(const float* part, int splits, int n, float* out, hipStream_t s) {
-    k_splitk<<<(n + kSkCols - 1) / kSkCols, kT, 0, s>>>(part, splits, n, out);
+// out[c] = sum_z sum_d part[z ld + d C + c] (d < D), z outer, in order (serial per output: for
+// few slabs, e.g. the transposed convolution's bias from its slab-reduced per-sub-pixel sums).
+__global__ __launch_bounds__(kT) void k_fold_sums(const float* part, int splits, size_t ld, int C, int D,
+                                                  float* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float t = 0.f;
+    for (int z = 0; z < splits; ++z)
+        for (int d = 0; d < D; ++d) t += part[(size_t)z * ld + (size_t)d * C + c];
+    out[c] = t;
+}
+hipError_t fold_sums(const float* part, int splits, size_t ld, int C, int D, float* out, hipStream_t s) {
+    k_fold_sums<<<(C + kT - 1) / kT, kT, 0, s>>>(part, splits, ld, C, D, out);
     return hipGetLastError();
 }
 hipError_t head_fwd(const Tensor& a, const float* w, const float* b, const float* x_in, float* out,

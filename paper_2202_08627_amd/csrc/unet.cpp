@@ -113,7 +113,7 @@ WsLayout layout(const eit_unet* u, int nb, int h, int w, bool train) {
             if (i >= D3A && i <= UP2) { hh = h / 4; ww = w / 4; }
             if (i >= D2A && i <= UP1) { hh = h / 2; ww = w / 2; }
             const size_t pix = (size_t)nb * hh * ww;
-            const size_t mn = l.kind == 0 ? (size_t)l.cout * 9 * l.cin + l.cout : (size_t)4 * l.cout * l.cin;
+            const size_t mn = l.kind == 0 ? (size_t)l.cout * 9 * l.cin + l.cout : (size_t)4 * l.cout * (l.cin + 1);
             const size_t parts = l.kind == 0 ? (size_t)conv_wgrad_parts(nb, hh, ww, l.cin, l.cout, wgrad_splits(pix))
                                              : (size_t)wgrad_splits_used((int)pix, wgrad_splits(pix));
             if (l.kind != 2) pe = std::max(pe, mn * parts);
@@ -217,9 +217,12 @@ int backward(const Ctx& c, const Acts& A, const Acts& G, const float* dout, floa
         const size_t pix = (size_t)X.B * X.H * X.W;
         const int sp = wgrad_splits(pix);
         NN_TRY(upconv_wgrad(X, gY, part, sp, s));
-        NN_TRY(splitk_reduce(part, wgrad_splits_used((int)pix, sp), 4 * L[li].cout * L[li].cin,
-                             grad + L[li].w, s));
-        NN_TRY(channel_sums(gY, sums, kSumBlocks, grad + L[li].b, s));
+        const int parts = wgrad_splits_used((int)pix, sp);
+        const size_t nw = (size_t)4 * L[li].cout * L[li].cin, ld = nw + 4 * L[li].cout;
+        NN_TRY(splitk_reduce(part, parts, (int)nw, grad + L[li].w, s, ld));
+        // bias: the 4 Co row sums reduced over the slabs (into the scratch sums), then over d
+        NN_TRY(splitk_reduce(part + nw, parts, 4 * L[li].cout, sums, s, ld));
+        NN_TRY(fold_sums(sums, 1, 0, L[li].cout, 4, grad + L[li].b, s));
         NN_TRY(upconv_dgrad(gY, c.wt + L[li].wt, dX, s, &X));
         return EIT_OK;
     };
